@@ -1,0 +1,163 @@
+"""Benchmark: spring-steps/s of the lattice spring model hot path on one GPU.
+
+Workload: 2048 x 2048 brick-and-mortar image -> triangular lattice
+(4,194,304 particles, 12,574,721 springs), FP32 forces with compensated FP32
+displacements, displacement-controlled tension in increments of 0.05 %
+strain, 2000 damped velocity Verlet steps per increment.  One bench "step"
+is one loading increment: strain increment + step-0 force evaluation, 2000
+fused step kernels (spring forces with critical-stretch breaking, force
+accumulation, integration), end-of-increment reductions and the break log.
+
+spring-steps/s = springs in the list (broken ones included, they are still
+iterated) x timesteps / wall time.  The roofline object rates the dominant
+kernel (the fused step) by its algorithmic bytes per launch over its
+average duration measured with HIP events on the library's stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("spring-steps/s (% HBM roofline); specimens/hour batched+surrogate "
+          "@≤5% error")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_step_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2201_04565_amd", "csrc", "lsm_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_src_sha256") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, img, steps: int):
+    """The FP64 oracle, single thread, on one increment of the same lattice."""
+    import oracle
+    prm = oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], dt=wl["dt"], gamma=wl["gamma"])
+    net = oracle.Net.lattice(img, prm)
+    t0 = time.perf_counter()
+    net.apply_increment(wl["d_eps"])
+    net.relax(steps)
+    dt = time.perf_counter() - t0
+    return dict(value=net.m * steps / dt, unit="spring-steps/s", cores=1, kind="oracle",
+                sample=f"full 2048x2048 lattice, 1 increment x {steps} steps "
+                       f"(+ step-0 evaluation), FP64, single thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=198, help="timed loading increments")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed loading increments")
+    ap.add_argument("--steps-per-inc", type=int, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2201_04565_amd import inputs, lsm
+
+    wl = inputs.WORKLOADS["c2"]
+    spi = args.steps_per_inc or wl["steps"]
+    img = inputs.c2_image()
+    lat = lsm.Lattice.from_workload(wl, img, precision="fp32k", device="cuda:0")
+    print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
+          flush=True)
+
+    for _ in range(args.warmup):
+        lat.apply_increment(wl["d_eps"])
+        lat.relax(spi)
+    lat.read_state()
+    lat.set_timing(True)
+    lat.read_timing()  # clear
+    torch.cuda.synchronize()
+    lat.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        lat.apply_increment(wl["d_eps"])
+        lat.relax(spi)
+        if (i + 1) % 50 == 0:
+            print(f"[bench] {i + 1}/{args.steps} increments", file=sys.stderr, flush=True)
+    lat.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = lat.read_state()
+    kern_ms, kern_launches = lat.read_timing()
+    lat.set_timing(False)
+
+    springs = lat.m
+    timesteps = args.steps * spi
+    value = springs * timesteps / wall
+    avg_kernel_s = kern_ms * 1e-3 / max(kern_launches, 1)
+    step_bytes = lat.step_bytes()
+    achieved = step_bytes / avg_kernel_s / 1e9
+    traffic = measured_traffic()
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spring-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "c2 brick-and-mortar 2048x2048 triangular lattice, fp32 forces with "
+                        "compensated fp32 displacements, 0.05% strain increments x 2000 steps",
+            "particles": lat.n,
+            "springs": springs,
+            "steps_per_increment": spi,
+            "strain_at_end": rec["eps"],
+            "broken_springs_at_end": rec["n_broken"],
+            "step_kernel_us": avg_kernel_s * 1e6,
+            "hbm_fraction_of_wall": step_bytes * timesteps / wall / 1e9 / HBM_PEAK_GBS,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": step_bytes,
+            "kernel": "k_step<2,1,kMid>",
+        },
+    }
+    if not args.no_cpu:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * lsm.h -- C ABI of the MI355X lattice spring model (LSM) library, liblsm.so.
+ *
+ * The calls follow the paper's statement of the problem (arXiv 2201.04565):
+ * an image with a number of particle types becomes a particle-spring network
+ * (Introduction, Img2Particle); a displacement-controlled mechanical test is
+ * run on it (Introduction; Section 3.1) by velocity Verlet time integration
+ * (Section 2.2, Eq. 3-5) of the truncated harmonic spring forces (Section
+ * 2.1, Eq. 1-2) with irreversible critical-stretch breaking (Section 2.3,
+ * Section 4); energies and the virial stress (Eq. 7) are reported.
+ *
+ * Conventions
+ *  - Every call returns an int status: LSM_OK (0) or a negative LSM_E* code.
+ *    No exception crosses the ABI.  lsm_last_error() gives the text of the
+ *    last failure on a handle.
+ *  - A handle is single-threaded and bound to one HIP stream.  Calls that
+ *    launch GPU work are asynchronous on that stream unless stated otherwise.
+ *  - Host arrays passed in are caller-owned and only read during the call.
+ *    Host arrays passed out are caller-allocated with the stated size.
+ *  - Device memory is caller-owned: the caller allocates
+ *    lsm_workspace_bytes() bytes (256-byte aligned) and hands the pointer to
+ *    lsm_bind(); it must stay valid until lsm_destroy().  The library itself
+ *    never allocates device memory.  Host-side objects (HIP graphs, events)
+ *    are owned by the handle.
+ *  - Particles are numbered in raster order of the non-void sites (x
+ *    fastest); springs are numbered by owner particle and then by forward
+ *    direction in canonical order (2D: east, upper-left, upper-right; 3D:
+ *    (1,0,0) (0,1,0) (0,0,1) (1,1,0) (-1,1,0) (1,0,1) (-1,0,1) (0,1,1)
+ *    (0,-1,1)).
+ */
+#ifndef LSM_H
+#define LSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define LSM_OK 0
+#define LSM_EINVAL (-1)    /* bad argument (null pointer, size, range) */
+#define LSM_ENOMEM (-2)    /* workspace too small / host allocation failed */
+#define LSM_EHIP (-3)      /* a HIP runtime call failed; see lsm_last_error */
+#define LSM_EUNSTABLE (-4) /* non-finite stress or energy detected */
+#define LSM_ESTATE (-5)    /* call made in the wrong order */
+
+/* ---- enumerations ---- */
+#define LSM_LATTICE_TRI2D 0 /* 2D triangular packing, 6 nearest neighbours */
+#define LSM_LATTICE_SC3D 1  /* 3D simple cubic, 6 face + 12 edge neighbours */
+#define LSM_FP64 0          /* FP64 displacements, velocities and forces */
+#define LSM_FP32_KAHAN 1    /* FP32 forces, compensated FP32 displacements */
+#define LSM_PRED_AFFINE 0     /* free particles follow the strain increment */
+#define LSM_PRED_GRIPS_ONLY 1 /* only the grips move at an increment */
+#define LSM_MAX_PHASES 8
+#define LSM_KERNEL_AUTO 0   /* row sweep for 2D lattices, site gather for 3D */
+#define LSM_KERNEL_GATHER 1 /* one thread per site, all incident springs */
+#define LSM_KERNEL_SWEEP 2  /* 2D: wavefronts sweep rows, forward springs once */
+
+/* Model and integration parameters.
+ *  k[P*P], break_stretch[P*P]: row-major, symmetric spring constant and
+ *    critical stretch s_c (rc = r0 (1 + s_c)) of a spring joining phases
+ *    (a, b) -- Section 2.3 assigns spring parameters by particle type, the
+ *    paper's Table "Constants of linear fracture spring" gives one such
+ *    table.  A non-finite off-diagonal entry selects the series rule
+ *    k_ab = 2 k_a k_b / (k_a + k_b), s_ab = min(s_a k_a, s_b k_b) / k_ab.
+ *  k_face, k_diag: 3D multipliers of face and edge-diagonal springs.
+ *  mass[P]: particle mass per phase (Section 2.3: mass by type).
+ *  dt: time step; damping: viscous coefficient gamma of the force -gamma v
+ *    (0 gives undamped velocity Verlet).
+ *  void_value: pixel value of empty sites, or -1 for none.              */
+typedef struct {
+    int32_t lattice;
+    int32_t nphase;
+    double a;
+    double k[LSM_MAX_PHASES * LSM_MAX_PHASES];
+    double break_stretch[LSM_MAX_PHASES * LSM_MAX_PHASES];
+    double k_face;
+    double k_diag;
+    double mass[LSM_MAX_PHASES];
+    double dt;
+    double damping;
+    int32_t precision;
+    int32_t predictor;
+    int32_t void_value;
+    int32_t reserved;
+} lsm_config;
+
+/* State record at the end of a relaxation.
+ *  eps: applied engineering strain (sum of increments).
+ *  sigma: virial stress (Eq. 7), row-major 3x3 (2D uses the upper 2x2),
+ *    tension positive, over the reference volume N * (site area or volume).
+ *  ke, pe: kinetic energy and Eq. 1 potential energy.  n_broken: broken
+ *  springs so far.  increment, step: loading increment and step inside it.
+ *  status: LSM_OK or LSM_EUNSTABLE.                                       */
+typedef struct {
+    double eps;
+    double sigma[9];
+    double ke;
+    double pe;
+    int64_t n_broken;
+    int32_t increment;
+    int32_t step;
+    int32_t status;
+    int32_t reserved;
+} lsm_record;
+
+/* One spring break: loading increment, step inside it (0 = the force
+ * evaluation right after the increment), canonical spring id, and the
+ * relative overshoot (r - rc) / rc at detection.                          */
+typedef struct {
+    int32_t increment;
+    int32_t step;
+    int64_t spring_id;
+    double margin;
+} lsm_event;
+
+typedef struct lsm_handle lsm_handle;
+
+/* Creates a handle from a copy of *cfg.  Errors: LSM_EINVAL for an invalid
+ * configuration (lattice kind, 1 <= nphase <= 8, a > 0, dt > 0,
+ * damping >= 0, masses > 0, finite non-negative diagonal k and s).        */
+int lsm_create(const lsm_config *cfg, lsm_handle **out);
+
+/* Frees the handle and its host-side objects; never touches the caller's
+ * workspace.  Synchronises the bound stream first.  Null is ignored.      */
+void lsm_destroy(lsm_handle *h);
+
+/* Image -> particles and typed springs (Introduction, Img2Particle).
+ * phase: host array of nx*ny*nz pixel values, x fastest (nz = 1 for 2D);
+ * each value is a phase index < nphase or the void value.  The first and
+ * last image columns (x = 0 and x = nx-1) are the grips of the uniaxial
+ * test (Section 3.1 boundary particles).  Host-only: may be called before
+ * lsm_bind, and not after it.                                              */
+int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t ny, int64_t nz);
+
+/* Particle and spring counts of the built lattice (LSM_ESTATE before it).  */
+int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs);
+
+/* Device workspace size in bytes for the built lattice.                   */
+int lsm_workspace_bytes(const lsm_handle *h, size_t *bytes);
+
+/* Binds caller-owned device memory (dptr, 256-byte aligned, at least
+ * lsm_workspace_bytes) and a HIP stream (hipStream_t, not the null stream
+ * so that relaxation loops can be captured into HIP graphs), then uploads
+ * the lattice and sets x = X0, v = 0 on that stream.  LSM_ENOMEM when the
+ * workspace is too small.                                                 */
+int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream);
+
+/* One displacement-controlled loading increment (Section 3.1): the strain
+ * becomes eps + d_eps, the grips move to X0_x + eps * i * a (all other
+ * components clamped, v = 0), free particles get the affine predictor
+ * d_eps * i * a along x (LSM_PRED_AFFINE), then the forces are evaluated
+ * with the break test (step 0) and the first half kick and drift of the
+ * integrator are applied.  LSM_ESTATE if called twice without lsm_relax.  */
+int lsm_apply_strain_increment(lsm_handle *h, double d_eps);
+
+/* nsteps >= 1 velocity Verlet steps (Eq. 3-5, half-step velocity form)
+ * with the spring forces of Eq. 2, the break test each step, and viscous
+ * damping; ends on a full step and computes the record (Eq. 7 stress,
+ * energies).  Launched as HIP graphs of the step kernel.                  */
+int lsm_relax(lsm_handle *h, int64_t nsteps);
+
+/* Synchronises the stream and copies the record of the last relaxation.
+ * Returns LSM_EUNSTABLE (with *out filled) if the state was not finite.   */
+int lsm_read_state(lsm_handle *h, lsm_record *out);
+
+/* Synchronises and copies broken-spring events first .. first+cap-1, in
+ * (increment, step, spring_id) order; *n receives the number copied.      */
+int lsm_read_broken(lsm_handle *h, int64_t first, int64_t cap, lsm_event *out, int64_t *n);
+
+/* Total number of broken springs (synchronises).                          */
+int lsm_n_broken(lsm_handle *h, int64_t *n);
+
+/* Canonical spring list: endpoints p < q, spring constant k, rest length
+ * r0, critical length rc, broken flag (synchronises).  Arrays of
+ * n_springs entries; any pointer may be null to skip that field.          */
+int lsm_get_springs(lsm_handle *h, int64_t *p, int64_t *q, double *k, double *r0, double *rc,
+                    uint8_t *broken);
+
+/* Reference positions X0 (host, n_particles x dim, canonical order).     */
+int lsm_get_reference(lsm_handle *h, double *X0);
+
+/* Current positions X0 + u and velocities as FP64 (host, n_particles x
+ * dim).  Synchronises.  Velocities are full-step values after lsm_relax. */
+int lsm_get_positions(lsm_handle *h, double *x);
+int lsm_get_velocities(lsm_handle *h, double *v);
+
+/* Overwrites positions or velocities (host, n_particles x dim).  Only
+ * between relaxations (LSM_ESTATE otherwise); synchronises.               */
+int lsm_set_positions(lsm_handle *h, const double *x);
+int lsm_set_velocities(lsm_handle *h, const double *v);
+
+/* One force evaluation (Eq. 2 with the break test) at the current
+ * positions, returned as FP64 (host, n_particles x dim).  commit_breaks != 0
+ * marks springs found beyond rc as broken and logs them at the current
+ * (increment, step); 0 leaves the state untouched (such springs still give
+ * no force).  Synchronises.                                               */
+int lsm_eval_forces(lsm_handle *h, double *f, int commit_breaks);
+
+/* Bitwise checkpoint of the dynamic state (displacements, velocities,
+ * broken flags, clock, events).  lsm_save_state with buf == NULL returns
+ * the size in *n; otherwise *n must hold the buffer size.  lsm_load_state
+ * requires a handle built from the same image and configuration.          */
+int lsm_save_state(lsm_handle *h, void *buf, size_t *n);
+int lsm_load_state(lsm_handle *h, const void *buf, size_t n);
+
+/* Measurement hooks.  lsm_set_timing(h, 1) brackets every graph of step
+ * kernels with HIP events on the bound stream; lsm_read_timing returns the
+ * summed event time in ms and the number of step kernels it covered
+ * (synchronises).  lsm_step_bytes gives the algorithmic bytes one step
+ * kernel must move (state read + written, site flags and break masks).    */
+int lsm_set_timing(lsm_handle *h, int enable);
+int lsm_read_timing(lsm_handle *h, double *ms, int64_t *steps);
+int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);
+
+/* Launch shape of the step kernel (used by the autotuner).  variant is one
+ * of LSM_KERNEL_*; rows_per_wave (2..4096, 0 = keep) sets the row chunk of
+ * the 2D sweep.  Results are bitwise independent of rows_per_wave.  Only
+ * between relaxations (LSM_ESTATE otherwise); drops cached graphs.        */
+int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave);
+
+const char *lsm_last_error(const lsm_handle *h);
+const char *lsm_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSM_H */

@@ -1,0 +1,949 @@
+// lsm_host.cpp -- host runtime of liblsm.so: the C ABI of include/lsm.h.
+//
+// Builds the lattice from the phase image on the host (one particle per
+// non-void pixel/voxel, springs to the nearest (2D) or face + edge (3D)
+// neighbours, typed by the phases of both ends -- Introduction, Img2Particle;
+// Section 2.3 type-based parameters), carves the caller's device workspace,
+// drives increments and relaxations on the bound stream (relaxation loops
+// are captured once into HIP graphs and replayed), and reads records,
+// events and state back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "lsm_internal.h"
+
+using lsm::Ctl;
+using lsm::DevRecord;
+using lsm::StepParams;
+using lsm::TypeRec;
+
+namespace {
+constexpr int kGraphChunk = 1000;  // step kernels per captured graph
+constexpr int kMinSweepRows = 2;
+constexpr int kMaxSweepRows = 4096;
+constexpr uint32_t kStateMagic = 0x4C534D31u;
+constexpr double kHalfSqrt3 = 0.86602540378443864676;
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Forward neighbour offsets in canonical spring order (see lsm.h).
+const int kFwd2Even[3][2] = {{1, 0}, {-1, 1}, {0, 1}};
+const int kFwd2Odd[3][2] = {{1, 0}, {0, 1}, {1, 1}};
+const int kFwd3[9][3] = {{1, 0, 0}, {0, 1, 0},  {0, 0, 1}, {1, 1, 0},  {-1, 1, 0},
+                         {1, 0, 1}, {-1, 0, 1}, {0, 1, 1}, {0, -1, 1}};
+}  // namespace
+
+struct lsm_handle {
+    lsm_config cfg{};
+    int dim = 2, prec = 0;
+    bool built = false, bound = false;
+    int64_t nx = 0, ny = 0, nz = 0, nsites = 0, n = 0, m = 0;
+    std::vector<uint8_t> flags;
+    std::vector<uint32_t> sbase;
+    std::vector<int32_t> site_of;  // particle id -> site
+    TypeRec types[lsm::kMaxTypes]{};
+    double omega = 0.0;
+    int tiles_x = 0, tiles_y = 0, ntiles = 0, nblocks = 0;
+    int variant = LSM_KERNEL_AUTO;  // step kernel family
+    int sw_rows = 16;               // rows per wavefront of the 2D row sweep
+    size_t ub = 0, vb = 0, mb = 0;  // bytes per site of u, v, mask
+    // device
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    Ctl *d_ctl = nullptr;
+    DevRecord *d_rec = nullptr;
+    TypeRec *d_types = nullptr;
+    uint8_t *d_flags = nullptr;
+    void *d_mask = nullptr;
+    uint32_t *d_sbase = nullptr;
+    void *d_U[2] = {nullptr, nullptr};
+    void *d_V = nullptr, *d_A = nullptr;
+    double *d_f64 = nullptr, *d_partials = nullptr;
+    lsm_event *d_events = nullptr;
+    int cur = 0;
+    bool half = false;  // velocities are half-step (between an increment and the end of a relax)
+    int32_t inc = 0, step = 0;
+    double eps = 0.0;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t timed_steps = 0;
+    std::vector<lsm_event> ev_sorted;
+    uint32_t ev_cached = 0xFFFFFFFFu;
+    std::string err;
+};
+
+namespace {
+
+int fail(lsm_handle *h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((h), LSM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// Spring constant and critical stretch of a pair of phases: explicit entry,
+// or two half springs in series breaking when the weaker half reaches its
+// own limit.
+void pair_params(const lsm_config &c, int pa, int pb, double *k, double *s) {
+    const int P = c.nphase;
+    const int lo = std::min(pa, pb), hi = std::max(pa, pb);
+    double kk = c.k[lo * P + hi], ss = c.break_stretch[lo * P + hi];
+    const double ka = c.k[lo * P + lo], kb = c.k[hi * P + hi];
+    const double sa = c.break_stretch[lo * P + lo], sb = c.break_stretch[hi * P + hi];
+    if (!std::isfinite(kk)) kk = (ka + kb) > 0.0 ? 2.0 * ka * kb / (ka + kb) : 0.0;
+    if (!std::isfinite(ss)) ss = kk > 0.0 ? std::min(sa * ka, sb * kb) / kk : 0.0;
+    *k = kk;
+    *s = ss;
+}
+
+void build_types(lsm_handle *h) {
+    const lsm_config &c = h->cfg;
+    std::memset(h->types, 0, sizeof(h->types));
+    for (int g = 0; g < 2; ++g)
+        for (int pa = 0; pa < c.nphase; ++pa)
+            for (int pb = 0; pb < c.nphase; ++pb) {
+                double k, s;
+                pair_params(c, pa, pb, &k, &s);
+                double r0 = c.a;
+                if (h->dim == 3) {
+                    k *= g == 0 ? c.k_face : c.k_diag;
+                    if (g == 1) r0 = std::sqrt(2.0) * c.a;
+                }
+                const double rc = r0 * (1.0 + s);
+                TypeRec &t = h->types[g * LSM_MAX_PHASES * LSM_MAX_PHASES + pa * LSM_MAX_PHASES + pb];
+                t.k32 = float(k);
+                t.kr0_32 = float(k * r0);
+                t.rc2_32 = float(rc * rc);
+                t.r0_32 = float(r0);
+                t.k64 = k;
+                t.r0_64 = r0;
+                t.rc64 = rc;
+            }
+}
+
+// Does site (i, j, k) have a non-void forward neighbour in direction d?
+bool fwd_neighbor(const lsm_handle *h, int64_t i, int64_t j, int64_t k, int d, int64_t *gq) {
+    int64_t qi, qj, qk;
+    if (h->dim == 2) {
+        const int *o = (j & 1) ? kFwd2Odd[d] : kFwd2Even[d];
+        qi = i + o[0]; qj = j + o[1]; qk = k;
+    } else {
+        qi = i + kFwd3[d][0]; qj = j + kFwd3[d][1]; qk = k + kFwd3[d][2];
+    }
+    if (qi < 0 || qi >= h->nx || qj < 0 || qj >= h->ny || qk < 0 || qk >= h->nz) return false;
+    const int64_t g = qi + h->nx * (qj + h->ny * qk);
+    if (h->flags[g] == lsm::kVoid) return false;
+    *gq = g;
+    return true;
+}
+
+void site_X0(const lsm_handle *h, int64_t g, double *X) {
+    const int64_t i = g % h->nx, j = (g / h->nx) % h->ny, k = g / (h->nx * h->ny);
+    if (h->dim == 2) {
+        X[0] = (double(i) + 0.5 * double(j & 1)) * h->cfg.a;
+        X[1] = double(j) * (kHalfSqrt3 * h->cfg.a);
+    } else {
+        X[0] = double(i) * h->cfg.a;
+        X[1] = double(j) * h->cfg.a;
+        X[2] = double(k) * h->cfg.a;
+    }
+}
+
+StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
+    StepParams p{};
+    p.nx = int32_t(h->nx);
+    p.ny = int32_t(h->ny);
+    p.nz = int32_t(h->nz);
+    p.tiles_x = h->tiles_x;
+    p.tiles_y = h->tiles_y;
+    p.ntiles = h->ntiles;
+    p.nblocks = h->nblocks;
+    p.nphase = h->cfg.nphase;
+    p.nsites = h->nsites;
+    p.a = h->cfg.a;
+    p.dt = h->cfg.dt;
+    p.gamma = h->cfg.damping;
+    for (int i = 0; i < LSM_MAX_PHASES; ++i) p.mass[i] = i < h->cfg.nphase ? h->cfg.mass[i] : 1.0;
+    p.flags = h->d_flags;
+    p.mask = h->d_mask;
+    p.sbase = h->d_sbase;
+    p.u_in = h->d_U[in_buf];
+    p.u_out = h->d_U[out_buf];
+    p.v = h->d_V;
+    p.acc = h->d_A;
+    p.types = h->d_types;
+    p.ctl = h->d_ctl;
+    p.events = h->d_events;
+    p.ev_cap = h->m;
+    p.partials = h->d_partials;
+    p.f64 = h->d_f64;
+    p.commit = 1;
+    p.sw_rows = h->sw_rows;
+    p.sw_strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
+    p.sw_nwork = p.sw_strips * int((h->ny + h->sw_rows - 1) / h->sw_rows);
+    p.sw_nblocks = ((p.sw_nwork + 4 * 8 - 1) / (4 * 8)) * 8;
+    p.red_blocks = p.nblocks;
+    return p;
+}
+
+bool use_sweep(const lsm_handle *h) { return h->dim == 2 && h->variant != LSM_KERNEL_GATHER; }
+
+// Start / interior / end step with the kernel family chosen for this lattice.
+hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_local) {
+    if (use_sweep(h) && mode != lsm::kEval) {
+        p.red_blocks = p.sw_nblocks;
+        return lsm::launch_sweep2d(p, h->prec, mode, h->stream, step_local);
+    }
+    p.red_blocks = p.nblocks;
+    return lsm::launch_step(p, h->dim, h->prec, mode, h->stream, step_local);
+}
+
+// Largest number of workgroups any end-of-relax kernel may use.
+int max_red_blocks(const lsm_handle *h) {
+    const int strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
+    const int nwork = strips * int((h->ny + kMinSweepRows - 1) / kMinSweepRows);
+    const int sweep_blocks = ((nwork + 31) / 32) * 8;
+    return std::max(h->nblocks, sweep_blocks);
+}
+
+int sync(lsm_handle *h) {
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LSM_OK;
+}
+
+hipEvent_t pool_event(lsm_handle *h) {
+    if (!h->ev_pool.empty()) {
+        hipEvent_t e = h->ev_pool.back();
+        h->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs `chunk` interior steps starting at local step index `local`.
+int run_mid_chunk(lsm_handle *h, int chunk, int local) {
+    hipGraphExec_t exec = nullptr;
+    const auto key = std::make_tuple(chunk, h->cur, local);
+    auto it = h->graphs.find(key);
+    if (it != h->graphs.end()) {
+        exec = it->second;
+    } else if (h->stream != nullptr) {
+        HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        int c = h->cur;
+        hipError_t le = hipSuccess;
+        for (int s = 0; s < chunk && le == hipSuccess; ++s) {
+            StepParams p = make_params(h, c, c ^ 1);
+            le = launch_phase(h, p, lsm::kMid, local + s);
+            c ^= 1;
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(h, LSM_EHIP, std::string("step launch during capture: ") + hipGetErrorString(le));
+        }
+        if (ce != hipSuccess) return fail(h, LSM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(h, LSM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        h->graphs[key] = exec;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->timing) {
+        e0 = pool_event(h);
+        e1 = pool_event(h);
+        if (!e0 || !e1) return fail(h, LSM_EHIP, "hipEventCreate failed");
+        HIPCHK(h, hipEventRecord(e0, h->stream));
+    }
+    if (exec) {
+        HIPCHK(h, hipGraphLaunch(exec, h->stream));
+    } else {  // null stream: no capture, launch directly
+        int c = h->cur;
+        for (int s = 0; s < chunk; ++s) {
+            StepParams p = make_params(h, c, c ^ 1);
+            HIPCHK(h, launch_phase(h, p, lsm::kMid, local + s));
+            c ^= 1;
+        }
+    }
+    if (h->timing) {
+        HIPCHK(h, hipEventRecord(e1, h->stream));
+        h->tev.emplace_back(e0, e1);
+        h->timed_steps += chunk;
+    }
+    h->cur ^= (chunk & 1);
+    return LSM_OK;
+}
+
+int check_bound(lsm_handle *h) {
+    if (!h) return LSM_EINVAL;
+    if (!h->bound) return fail(h, LSM_ESTATE, "lattice not bound to a workspace");
+    return LSM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lsm_strerror(int status) {
+    switch (status) {
+        case LSM_OK: return "ok";
+        case LSM_EINVAL: return "invalid argument";
+        case LSM_ENOMEM: return "workspace too small or out of host memory";
+        case LSM_EHIP: return "HIP runtime error";
+        case LSM_EUNSTABLE: return "non-finite state (integration unstable)";
+        case LSM_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+const char *lsm_last_error(const lsm_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+int lsm_create(const lsm_config *cfg, lsm_handle **out) {
+    if (!cfg || !out) return LSM_EINVAL;
+    *out = nullptr;
+    const lsm_config &c = *cfg;
+    if (c.lattice != LSM_LATTICE_TRI2D && c.lattice != LSM_LATTICE_SC3D) return LSM_EINVAL;
+    if (c.nphase < 1 || c.nphase > LSM_MAX_PHASES) return LSM_EINVAL;
+    if (!(c.a > 0.0) || !std::isfinite(c.a) || !(c.dt > 0.0) || !std::isfinite(c.dt)) return LSM_EINVAL;
+    if (!finite_nonneg(c.damping)) return LSM_EINVAL;
+    if (c.precision != LSM_FP64 && c.precision != LSM_FP32_KAHAN) return LSM_EINVAL;
+    if (c.predictor != LSM_PRED_AFFINE && c.predictor != LSM_PRED_GRIPS_ONLY) return LSM_EINVAL;
+    if (c.void_value < -1 || c.void_value > 255) return LSM_EINVAL;
+    for (int p = 0; p < c.nphase; ++p) {
+        if (!(c.mass[p] > 0.0) || !std::isfinite(c.mass[p])) return LSM_EINVAL;
+        if (!finite_nonneg(c.k[p * c.nphase + p]) || !finite_nonneg(c.break_stretch[p * c.nphase + p]))
+            return LSM_EINVAL;
+        for (int q = 0; q < c.nphase; ++q) {
+            const double kq = c.k[p * c.nphase + q], sq = c.break_stretch[p * c.nphase + q];
+            if (std::isfinite(kq) && kq < 0.0) return LSM_EINVAL;
+            if (std::isfinite(sq) && sq < 0.0) return LSM_EINVAL;
+        }
+    }
+    if (c.lattice == LSM_LATTICE_SC3D && (!finite_nonneg(c.k_face) || !finite_nonneg(c.k_diag)))
+        return LSM_EINVAL;
+    lsm_handle *h = new (std::nothrow) lsm_handle();
+    if (!h) return LSM_ENOMEM;
+    h->cfg = c;
+    h->dim = c.lattice == LSM_LATTICE_TRI2D ? 2 : 3;
+    h->prec = c.precision == LSM_FP32_KAHAN ? 1 : 0;
+    build_types(h);
+    *out = h;
+    return LSM_OK;
+}
+
+void lsm_destroy(lsm_handle *h) {
+    if (!h) return;
+    if (h->bound) (void)hipStreamSynchronize(h->stream);
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto &pr : h->tev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t ny, int64_t nz) {
+    if (!h || !phase) return LSM_EINVAL;
+    if (h->bound) return fail(h, LSM_ESTATE, "lattice already bound");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(h, LSM_EINVAL, "image dimensions must be >= 1");
+    if (h->dim == 2 && nz != 1) return fail(h, LSM_EINVAL, "2D lattice needs nz == 1");
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30) || nx * ny * nz >= (int64_t(1) << 31) - 1)
+        return fail(h, LSM_EINVAL, "image too large (site index must fit in 31 bits)");
+    const int64_t ns = nx * ny * nz;
+    h->nx = nx; h->ny = ny; h->nz = nz; h->nsites = ns;
+    h->flags.assign(size_t(ns), 0);
+    h->site_of.clear();
+    const int vv = h->cfg.void_value;
+    for (int64_t g = 0; g < ns; ++g) {
+        const int v = phase[g];
+        if (vv >= 0 && v == vv) {
+            h->flags[g] = lsm::kVoid;
+            continue;
+        }
+        if (v >= h->cfg.nphase) return fail(h, LSM_EINVAL, "pixel value is neither a phase nor void");
+        const int64_t i = g % nx;
+        const int grip = (i == 0) ? 1 : (i == nx - 1 ? 2 : 0);
+        h->flags[g] = uint8_t(v | (grip << 4));
+        h->site_of.push_back(int32_t(g));
+    }
+    h->n = int64_t(h->site_of.size());
+    h->sbase.assign(size_t(ns), 0);
+    const int nf = h->dim == 2 ? 3 : 9;
+    int64_t m = 0;
+    for (int64_t g = 0; g < ns; ++g) {
+        if (h->flags[g] == lsm::kVoid) continue;
+        h->sbase[g] = uint32_t(m);
+        const int64_t i = g % nx, j = (g / nx) % ny, k = g / (nx * ny);
+        int64_t gq;
+        for (int d = 0; d < nf; ++d)
+            if (fwd_neighbor(h, i, j, k, d, &gq)) ++m;
+        if (m >= (int64_t(1) << 32) - 1) return fail(h, LSM_EINVAL, "too many springs");
+    }
+    h->m = m;
+    h->tiles_x = int((nx + lsm::kTileX - 1) / lsm::kTileX);
+    h->tiles_y = int((ny + lsm::kTileY - 1) / lsm::kTileY);
+    h->ntiles = h->tiles_x * h->tiles_y * int(nz);
+    h->nblocks = ((h->ntiles + 7) / 8) * 8;
+    // reference volume of Eq. 7: sites times the area (2D) or volume (3D)
+    // per site; an empty lattice reports zero stress
+    h->omega = h->n > 0 ? double(h->n) * (h->dim == 2 ? kHalfSqrt3 * h->cfg.a * h->cfg.a
+                                                      : h->cfg.a * h->cfg.a * h->cfg.a)
+                        : 1.0;
+    const size_t rb = h->prec ? 4 : 8;
+    h->ub = h->dim == 2 ? 16 : (h->prec ? 24 : 24);
+    h->vb = size_t(h->dim) * rb;
+    h->mb = h->dim == 2 ? 1 : 4;
+    (void)rb;
+    h->built = true;
+    return LSM_OK;
+}
+
+int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
+    if (!h || !n_particles || !n_springs) return LSM_EINVAL;
+    if (!h->built) return LSM_ESTATE;
+    *n_particles = h->n;
+    *n_springs = h->m;
+    return LSM_OK;
+}
+
+static size_t layout(const lsm_handle *h, size_t *off /* 13 offsets */) {
+    size_t o = 0;
+    const size_t ns = size_t(h->nsites);
+    size_t sizes[13] = {
+        sizeof(Ctl),                                  // 0 ctl
+        sizeof(DevRecord),                            // 1 record
+        sizeof(TypeRec) * lsm::kMaxTypes,             // 2 types
+        ns,                                           // 3 flags
+        ns * h->mb,                                   // 4 mask
+        ns * 4,                                       // 5 sbase
+        ns * h->ub,                                   // 6 U0
+        ns * h->ub,                                   // 7 U1
+        ns * h->vb,                                   // 8 V
+        ns * h->vb,                                   // 9 A
+        ns * size_t(h->dim) * 8,                      // 10 f64
+        size_t(max_red_blocks(h)) * lsm::kNumPartials * 8,  // 11 partials
+        size_t(std::max<int64_t>(h->m, 1)) * sizeof(lsm_event),  // 12 events
+    };
+    for (int i = 0; i < 13; ++i) {
+        off[i] = o;
+        o += align256(sizes[i]);
+    }
+    return o;
+}
+
+int lsm_workspace_bytes(const lsm_handle *h, size_t *bytes) {
+    if (!h || !bytes) return LSM_EINVAL;
+    if (!h->built) return LSM_ESTATE;
+    size_t off[13];
+    *bytes = layout(h, off);
+    return LSM_OK;
+}
+
+int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
+    if (!h || !dptr) return LSM_EINVAL;
+    if (!h->built) return fail(h, LSM_ESTATE, "build the lattice first");
+    if (h->bound) return fail(h, LSM_ESTATE, "already bound");
+    if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return fail(h, LSM_EINVAL, "workspace must be 256-byte aligned");
+    size_t off[13];
+    const size_t need = layout(h, off);
+    if (bytes < need) return fail(h, LSM_ENOMEM, "workspace too small");
+    char *w = static_cast<char *>(dptr);
+    h->ws = w;
+    h->ws_bytes = bytes;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->d_ctl = reinterpret_cast<Ctl *>(w + off[0]);
+    h->d_rec = reinterpret_cast<DevRecord *>(w + off[1]);
+    h->d_types = reinterpret_cast<TypeRec *>(w + off[2]);
+    h->d_flags = reinterpret_cast<uint8_t *>(w + off[3]);
+    h->d_mask = w + off[4];
+    h->d_sbase = reinterpret_cast<uint32_t *>(w + off[5]);
+    h->d_U[0] = w + off[6];
+    h->d_U[1] = w + off[7];
+    h->d_V = w + off[8];
+    h->d_A = w + off[9];
+    h->d_f64 = reinterpret_cast<double *>(w + off[10]);
+    h->d_partials = reinterpret_cast<double *>(w + off[11]);
+    h->d_events = reinterpret_cast<lsm_event *>(w + off[12]);
+    HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->cur = 0;
+    h->half = false;
+    h->inc = 0;
+    h->step = 0;
+    h->eps = 0.0;
+    h->bound = true;
+    return LSM_OK;
+}
+
+int lsm_apply_strain_increment(lsm_handle *h, double d_eps) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!std::isfinite(d_eps)) return fail(h, LSM_EINVAL, "strain increment must be finite");
+    if (h->half) return fail(h, LSM_ESTATE, "relax before the next increment");
+    const double eps_new = h->eps + d_eps;
+    StepParams p = make_params(h, h->cur, h->cur ^ 1);
+    HIPCHK(h, lsm::launch_increment(p, h->dim, h->prec, h->stream, eps_new, d_eps, h->inc + 1,
+                                    h->cfg.predictor == LSM_PRED_AFFINE));
+    HIPCHK(h, launch_phase(h, p, lsm::kStart, 0));
+    h->cur ^= 1;
+    h->half = true;
+    h->inc += 1;
+    h->eps = eps_new;
+    h->step = 0;
+    return LSM_OK;
+}
+
+int lsm_relax(lsm_handle *h, int64_t nsteps) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (nsteps < 1 || nsteps > (int64_t(1) << 30)) return fail(h, LSM_EINVAL, "nsteps must be >= 1");
+    if (!h->half) {
+        StepParams p = make_params(h, h->cur, h->cur);
+        HIPCHK(h, lsm::launch_kick_drift(p, h->dim, h->prec, h->stream));
+        h->half = true;
+    }
+    int64_t rem = nsteps - 1;
+    int local = 1;
+    while (rem > 0) {
+        const int chunk = int(std::min<int64_t>(rem, kGraphChunk));
+        rc = run_mid_chunk(h, chunk, local);
+        if (rc) return rc;
+        rem -= chunk;
+        local += chunk;
+    }
+    StepParams p = make_params(h, h->cur, h->cur);
+    HIPCHK(h, launch_phase(h, p, lsm::kEnd, int(nsteps)));
+    HIPCHK(h, lsm::launch_finalize(p, h->dim, h->stream, h->d_rec, h->omega, int(nsteps)));
+    h->half = false;
+    h->step += int32_t(nsteps);
+    return LSM_OK;
+}
+
+int lsm_read_state(lsm_handle *h, lsm_record *out) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!out) return LSM_EINVAL;
+    HIPCHK(h, hipMemcpyAsync(out, h->d_rec, sizeof(lsm_record), hipMemcpyDeviceToHost, h->stream));
+    rc = sync(h);
+    if (rc) return rc;
+    return out->status == LSM_EUNSTABLE ? LSM_EUNSTABLE : LSM_OK;
+}
+
+static int fetch_events(lsm_handle *h) {
+    Ctl ctl;
+    HIPCHK(h, hipMemcpyAsync(&ctl, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    int rc = sync(h);
+    if (rc) return rc;
+    const uint32_t ne = uint32_t(std::min<int64_t>(ctl.n_events, h->m));
+    if (ne == h->ev_cached) return LSM_OK;
+    h->ev_sorted.resize(ne);
+    if (ne) {
+        HIPCHK(h, hipMemcpyAsync(h->ev_sorted.data(), h->d_events, size_t(ne) * sizeof(lsm_event),
+                                 hipMemcpyDeviceToHost, h->stream));
+        rc = sync(h);
+        if (rc) return rc;
+    }
+    std::sort(h->ev_sorted.begin(), h->ev_sorted.end(), [](const lsm_event &x, const lsm_event &y) {
+        if (x.increment != y.increment) return x.increment < y.increment;
+        if (x.step != y.step) return x.step < y.step;
+        return x.spring_id < y.spring_id;
+    });
+    h->ev_cached = ne;
+    return LSM_OK;
+}
+
+int lsm_read_broken(lsm_handle *h, int64_t first, int64_t cap, lsm_event *out, int64_t *n) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!n || first < 0 || cap < 0 || (cap > 0 && !out)) return LSM_EINVAL;
+    rc = fetch_events(h);
+    if (rc) return rc;
+    const int64_t total = int64_t(h->ev_sorted.size());
+    const int64_t cnt = std::max<int64_t>(0, std::min<int64_t>(cap, total - first));
+    if (cnt > 0) std::memcpy(out, h->ev_sorted.data() + first, size_t(cnt) * sizeof(lsm_event));
+    *n = cnt;
+    return LSM_OK;
+}
+
+int lsm_n_broken(lsm_handle *h, int64_t *n) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!n) return LSM_EINVAL;
+    rc = fetch_events(h);
+    if (rc) return rc;
+    *n = int64_t(h->ev_sorted.size());
+    return LSM_OK;
+}
+
+static int fetch_masks(lsm_handle *h, std::vector<uint32_t> &mask) {
+    std::vector<uint8_t> raw(size_t(h->nsites) * h->mb);
+    HIPCHK(h, hipMemcpyAsync(raw.data(), h->d_mask, raw.size(), hipMemcpyDeviceToHost, h->stream));
+    int rc = sync(h);
+    if (rc) return rc;
+    mask.resize(size_t(h->nsites));
+    for (int64_t g = 0; g < h->nsites; ++g) {
+        if (h->mb == 1)
+            mask[g] = raw[g];
+        else
+            std::memcpy(&mask[g], &raw[g * 4], 4);
+    }
+    return LSM_OK;
+}
+
+int lsm_get_springs(lsm_handle *h, int64_t *p, int64_t *q, double *k, double *r0, double *rc,
+                    uint8_t *broken) {
+    if (!h) return LSM_EINVAL;
+    if (!h->built) return fail(h, LSM_ESTATE, "build the lattice first");
+    std::vector<uint32_t> mask;
+    if (h->bound && broken) {
+        int e = fetch_masks(h, mask);
+        if (e) return e;
+    }
+    std::vector<int64_t> canon(size_t(h->nsites), -1);
+    for (int64_t c = 0; c < h->n; ++c) canon[h->site_of[c]] = c;
+    const int nf = h->dim == 2 ? 3 : 9;
+    int64_t s = 0;
+    for (int64_t g = 0; g < h->nsites; ++g) {
+        if (h->flags[g] == lsm::kVoid) continue;
+        const int64_t i = g % h->nx, j = (g / h->nx) % h->ny, kk = g / (h->nx * h->ny);
+        for (int d = 0; d < nf; ++d) {
+            int64_t gq;
+            if (!fwd_neighbor(h, i, j, kk, d, &gq)) continue;
+            const int geom = (h->dim == 3 && d >= 3) ? 1 : 0;
+            const TypeRec &t = h->types[geom * LSM_MAX_PHASES * LSM_MAX_PHASES +
+                                        lsm::flag_phase(h->flags[g]) * LSM_MAX_PHASES +
+                                        lsm::flag_phase(h->flags[gq])];
+            if (p) p[s] = canon[g];
+            if (q) q[s] = canon[gq];
+            if (k) k[s] = t.k64;
+            if (r0) r0[s] = t.r0_64;
+            if (rc) rc[s] = t.rc64;
+            if (broken) broken[s] = h->bound ? uint8_t((mask[g] >> d) & 1u) : 0;
+            ++s;
+        }
+    }
+    return LSM_OK;
+}
+
+int lsm_get_reference(lsm_handle *h, double *X0) {
+    if (!h || !X0) return LSM_EINVAL;
+    if (!h->built) return LSM_ESTATE;
+    for (int64_t c = 0; c < h->n; ++c) site_X0(h, h->site_of[c], X0 + c * h->dim);
+    return LSM_OK;
+}
+
+// Reads the current displacement buffer as FP64 u (nsites x dim, site order).
+static int read_u(lsm_handle *h, std::vector<double> &u) {
+    const size_t ns = size_t(h->nsites);
+    std::vector<char> raw(ns * h->ub);
+    HIPCHK(h, hipMemcpyAsync(raw.data(), h->d_U[h->cur], raw.size(), hipMemcpyDeviceToHost, h->stream));
+    int rc = sync(h);
+    if (rc) return rc;
+    u.assign(ns * h->dim, 0.0);
+    for (size_t g = 0; g < ns; ++g)
+        for (int c = 0; c < h->dim; ++c) {
+            double val;
+            if (h->dim == 2 && h->prec) {
+                const float *f = reinterpret_cast<const float *>(raw.data()) + g * 4;
+                val = double(f[c]) + double(f[2 + c]);
+            } else if (h->dim == 2) {
+                val = reinterpret_cast<const double *>(raw.data())[g * 2 + c];
+            } else if (h->prec) {
+                const float *f = reinterpret_cast<const float *>(raw.data());
+                val = double(f[c * ns + g]) + double(f[(3 + c) * ns + g]);
+            } else {
+                val = reinterpret_cast<const double *>(raw.data())[c * ns + g];
+            }
+            u[g * h->dim + c] = val;
+        }
+    return LSM_OK;
+}
+
+static int write_u(lsm_handle *h, const std::vector<double> &u) {
+    const size_t ns = size_t(h->nsites);
+    std::vector<char> raw(ns * h->ub, 0);
+    for (size_t g = 0; g < ns; ++g)
+        for (int c = 0; c < h->dim; ++c) {
+            const double val = u[g * h->dim + c];
+            const float hi = float(val);
+            const float lo = float(val - double(hi));
+            if (h->dim == 2 && h->prec) {
+                float *f = reinterpret_cast<float *>(raw.data()) + g * 4;
+                f[c] = hi;
+                f[2 + c] = lo;
+            } else if (h->dim == 2) {
+                reinterpret_cast<double *>(raw.data())[g * 2 + c] = val;
+            } else if (h->prec) {
+                float *f = reinterpret_cast<float *>(raw.data());
+                f[c * ns + g] = hi;
+                f[(3 + c) * ns + g] = lo;
+            } else {
+                reinterpret_cast<double *>(raw.data())[c * ns + g] = val;
+            }
+        }
+    HIPCHK(h, hipMemcpyAsync(h->d_U[h->cur], raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream));
+    return sync(h);
+}
+
+// velocity-like arrays (v, acc): nsites x dim in site order
+static int read_vec(lsm_handle *h, void *src, std::vector<double> &out) {
+    const size_t ns = size_t(h->nsites);
+    std::vector<char> raw(ns * h->vb);
+    HIPCHK(h, hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, h->stream));
+    int rc = sync(h);
+    if (rc) return rc;
+    out.assign(ns * h->dim, 0.0);
+    for (size_t g = 0; g < ns; ++g)
+        for (int c = 0; c < h->dim; ++c) {
+            const size_t idx = h->dim == 2 ? g * 2 + c : c * ns + g;
+            out[g * h->dim + c] = h->prec ? double(reinterpret_cast<const float *>(raw.data())[idx])
+                                          : reinterpret_cast<const double *>(raw.data())[idx];
+        }
+    return LSM_OK;
+}
+
+static int write_vec(lsm_handle *h, void *dst, const std::vector<double> &in) {
+    const size_t ns = size_t(h->nsites);
+    std::vector<char> raw(ns * h->vb, 0);
+    for (size_t g = 0; g < ns; ++g)
+        for (int c = 0; c < h->dim; ++c) {
+            const size_t idx = h->dim == 2 ? g * 2 + c : c * ns + g;
+            if (h->prec)
+                reinterpret_cast<float *>(raw.data())[idx] = float(in[g * h->dim + c]);
+            else
+                reinterpret_cast<double *>(raw.data())[idx] = in[g * h->dim + c];
+        }
+    HIPCHK(h, hipMemcpyAsync(dst, raw.data(), raw.size(), hipMemcpyHostToDevice, h->stream));
+    return sync(h);
+}
+
+int lsm_get_positions(lsm_handle *h, double *x) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!x) return LSM_EINVAL;
+    std::vector<double> u;
+    rc = read_u(h, u);
+    if (rc) return rc;
+    for (int64_t c = 0; c < h->n; ++c) {
+        double X[3];
+        const int64_t g = h->site_of[c];
+        site_X0(h, g, X);
+        for (int e = 0; e < h->dim; ++e) x[c * h->dim + e] = X[e] + u[g * h->dim + e];
+    }
+    return LSM_OK;
+}
+
+int lsm_get_velocities(lsm_handle *h, double *v) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!v) return LSM_EINVAL;
+    std::vector<double> vv;
+    rc = read_vec(h, h->d_V, vv);
+    if (rc) return rc;
+    for (int64_t c = 0; c < h->n; ++c)
+        for (int e = 0; e < h->dim; ++e) v[c * h->dim + e] = vv[h->site_of[c] * h->dim + e];
+    return LSM_OK;
+}
+
+int lsm_set_positions(lsm_handle *h, const double *x) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!x) return LSM_EINVAL;
+    if (h->half) return fail(h, LSM_ESTATE, "positions can only be set between relaxations");
+    std::vector<double> u(size_t(h->nsites) * h->dim, 0.0);
+    for (int64_t c = 0; c < h->n; ++c) {
+        double X[3];
+        const int64_t g = h->site_of[c];
+        site_X0(h, g, X);
+        for (int e = 0; e < h->dim; ++e) u[g * h->dim + e] = x[c * h->dim + e] - X[e];
+    }
+    return write_u(h, u);
+}
+
+int lsm_set_velocities(lsm_handle *h, const double *v) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!v) return LSM_EINVAL;
+    if (h->half) return fail(h, LSM_ESTATE, "velocities can only be set between relaxations");
+    std::vector<double> vv(size_t(h->nsites) * h->dim, 0.0);
+    for (int64_t c = 0; c < h->n; ++c) {
+        const int64_t g = h->site_of[c];
+        if (lsm::flag_grip(h->flags[g])) continue;  // grips stay clamped
+        for (int e = 0; e < h->dim; ++e) vv[g * h->dim + e] = v[c * h->dim + e];
+    }
+    return write_vec(h, h->d_V, vv);
+}
+
+int lsm_eval_forces(lsm_handle *h, double *f, int commit_breaks) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!f) return LSM_EINVAL;
+    StepParams p = make_params(h, h->cur, h->cur);
+    p.commit = commit_breaks ? 1 : 0;
+    HIPCHK(h, lsm::launch_step(p, h->dim, h->prec, lsm::kEval, h->stream, 0));
+    std::vector<double> raw(size_t(h->nsites) * h->dim);
+    HIPCHK(h, hipMemcpyAsync(raw.data(), h->d_f64, raw.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    rc = sync(h);
+    if (rc) return rc;
+    for (int64_t c = 0; c < h->n; ++c)
+        for (int e = 0; e < h->dim; ++e) f[c * h->dim + e] = raw[size_t(h->site_of[c]) * h->dim + e];
+    return LSM_OK;
+}
+
+// ---- checkpoint: header, u (current buffer), v, acc, mask, ctl, record, events
+struct StateHeader {
+    uint32_t magic, version;
+    int64_t nsites, m;
+    int32_t dim, prec, half, inc, step, pad;
+    double eps;
+};
+
+static size_t state_size(const lsm_handle *h, uint32_t nev) {
+    const size_t ns = size_t(h->nsites);
+    return sizeof(StateHeader) + ns * h->ub + 2 * ns * h->vb + ns * h->mb + sizeof(Ctl) +
+           sizeof(DevRecord) + size_t(nev) * sizeof(lsm_event);
+}
+
+int lsm_save_state(lsm_handle *h, void *buf, size_t *n) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!n) return LSM_EINVAL;
+    Ctl ctl;
+    HIPCHK(h, hipMemcpyAsync(&ctl, h->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, h->stream));
+    rc = sync(h);
+    if (rc) return rc;
+    const uint32_t nev = uint32_t(std::min<int64_t>(ctl.n_events, h->m));
+    const size_t need = state_size(h, nev);
+    if (!buf) {
+        *n = need;
+        return LSM_OK;
+    }
+    if (*n < need) return fail(h, LSM_ENOMEM, "checkpoint buffer too small");
+    const size_t ns = size_t(h->nsites);
+    char *o = static_cast<char *>(buf);
+    StateHeader hd{kStateMagic, 1, h->nsites, h->m, h->dim, h->prec, h->half ? 1 : 0, h->inc, h->step, 0, h->eps};
+    std::memcpy(o, &hd, sizeof(hd));
+    o += sizeof(hd);
+    HIPCHK(h, hipMemcpyAsync(o, h->d_U[h->cur], ns * h->ub, hipMemcpyDeviceToHost, h->stream)); o += ns * h->ub;
+    HIPCHK(h, hipMemcpyAsync(o, h->d_V, ns * h->vb, hipMemcpyDeviceToHost, h->stream)); o += ns * h->vb;
+    HIPCHK(h, hipMemcpyAsync(o, h->d_A, ns * h->vb, hipMemcpyDeviceToHost, h->stream)); o += ns * h->vb;
+    HIPCHK(h, hipMemcpyAsync(o, h->d_mask, ns * h->mb, hipMemcpyDeviceToHost, h->stream)); o += ns * h->mb;
+    std::memcpy(o, &ctl, sizeof(Ctl)); o += sizeof(Ctl);
+    HIPCHK(h, hipMemcpyAsync(o, h->d_rec, sizeof(DevRecord), hipMemcpyDeviceToHost, h->stream)); o += sizeof(DevRecord);
+    if (nev) HIPCHK(h, hipMemcpyAsync(o, h->d_events, size_t(nev) * sizeof(lsm_event), hipMemcpyDeviceToHost, h->stream));
+    *n = need;
+    return sync(h);
+}
+
+int lsm_load_state(lsm_handle *h, const void *buf, size_t n) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!buf || n < sizeof(StateHeader)) return LSM_EINVAL;
+    StateHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (hd.magic != kStateMagic || hd.version != 1 || hd.nsites != h->nsites || hd.m != h->m ||
+        hd.dim != h->dim || hd.prec != h->prec)
+        return fail(h, LSM_EINVAL, "checkpoint does not match this lattice");
+    const char *o = static_cast<const char *>(buf) + sizeof(hd);
+    const size_t ns = size_t(h->nsites);
+    const size_t fixed = sizeof(hd) + ns * h->ub + 2 * ns * h->vb + ns * h->mb + sizeof(Ctl) + sizeof(DevRecord);
+    if (n < fixed) return fail(h, LSM_EINVAL, "checkpoint truncated");
+    Ctl ctl;
+    std::memcpy(&ctl, o + ns * h->ub + 2 * ns * h->vb + ns * h->mb, sizeof(Ctl));
+    const uint32_t nev = uint32_t(std::min<int64_t>(ctl.n_events, h->m));
+    if (n < state_size(h, nev)) return fail(h, LSM_EINVAL, "checkpoint truncated");
+    h->cur = 0;
+    HIPCHK(h, hipMemcpyAsync(h->d_U[0], o, ns * h->ub, hipMemcpyHostToDevice, h->stream)); o += ns * h->ub;
+    HIPCHK(h, hipMemcpyAsync(h->d_V, o, ns * h->vb, hipMemcpyHostToDevice, h->stream)); o += ns * h->vb;
+    HIPCHK(h, hipMemcpyAsync(h->d_A, o, ns * h->vb, hipMemcpyHostToDevice, h->stream)); o += ns * h->vb;
+    HIPCHK(h, hipMemcpyAsync(h->d_mask, o, ns * h->mb, hipMemcpyHostToDevice, h->stream)); o += ns * h->mb;
+    HIPCHK(h, hipMemcpyAsync(h->d_ctl, o, sizeof(Ctl), hipMemcpyHostToDevice, h->stream)); o += sizeof(Ctl);
+    HIPCHK(h, hipMemcpyAsync(h->d_rec, o, sizeof(DevRecord), hipMemcpyHostToDevice, h->stream)); o += sizeof(DevRecord);
+    if (nev) HIPCHK(h, hipMemcpyAsync(h->d_events, o, size_t(nev) * sizeof(lsm_event), hipMemcpyHostToDevice, h->stream));
+    rc = sync(h);
+    if (rc) return rc;
+    h->half = hd.half != 0;
+    h->inc = hd.inc;
+    h->step = hd.step;
+    h->eps = hd.eps;
+    h->ev_cached = 0xFFFFFFFFu;
+    return LSM_OK;
+}
+
+int lsm_set_timing(lsm_handle *h, int enable) {
+    if (!h) return LSM_EINVAL;
+    h->timing = enable != 0;
+    return LSM_OK;
+}
+
+int lsm_read_timing(lsm_handle *h, double *ms, int64_t *steps) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!ms || !steps) return LSM_EINVAL;
+    rc = sync(h);
+    if (rc) return rc;
+    double tot = 0.0;
+    for (auto &pr : h->tev) {
+        float t = 0.0f;
+        HIPCHK(h, hipEventElapsedTime(&t, pr.first, pr.second));
+        tot += t;
+        h->ev_pool.push_back(pr.first);
+        h->ev_pool.push_back(pr.second);
+    }
+    h->tev.clear();
+    *ms = tot;
+    *steps = h->timed_steps;
+    h->timed_steps = 0;
+    return LSM_OK;
+}
+
+int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
+    if (!h) return LSM_EINVAL;
+    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP)
+        return fail(h, LSM_EINVAL, "unknown kernel variant");
+    if (variant == LSM_KERNEL_SWEEP && h->dim != 2) return fail(h, LSM_EINVAL, "row sweep is 2D only");
+    if (rows_per_wave != 0 && (rows_per_wave < kMinSweepRows || rows_per_wave > kMaxSweepRows))
+        return fail(h, LSM_EINVAL, "rows_per_wave out of range");
+    if (h->half) return fail(h, LSM_ESTATE, "change the launch only between relaxations");
+    if (h->variant != variant || (rows_per_wave && rows_per_wave != h->sw_rows)) {
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+    }
+    h->variant = variant;
+    if (rows_per_wave) h->sw_rows = rows_per_wave;
+    return LSM_OK;
+}
+
+int lsm_step_bytes(const lsm_handle *h, int64_t *bytes) {
+    if (!h || !bytes) return LSM_EINVAL;
+    if (!h->built) return LSM_ESTATE;
+    // per particle: displacement and velocity read and written, flag byte, break mask
+    *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb);
+    return LSM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// lsm_internal.h -- shared definitions of the host runtime and the HIP
+// kernels of liblsm.so (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lsm.h"
+
+namespace lsm {
+
+constexpr int kTileX = 64;  // one wavefront covers 64 consecutive sites of a row
+constexpr int kTileY = 4;   // four rows per workgroup
+constexpr int kBlock = kTileX * kTileY;
+constexpr int kMaxTypes = 2 * LSM_MAX_PHASES * LSM_MAX_PHASES;  // (geometry, phase, phase)
+constexpr uint8_t kVoid = 0xFF;
+constexpr int kNumPartials = 24;  // virial[9], kinetic[9], pe, ke, nonfinite, 3 spare
+constexpr int kSweepCols = 62;    // owned columns per wavefront in the 2D row sweep
+
+// Site flag byte: bits 0-3 phase, bits 4-5 grip (1 left column, 2 right column).
+__host__ __device__ inline int flag_phase(uint8_t f) { return f & 0x0F; }
+__host__ __device__ inline int flag_grip(uint8_t f) { return (f >> 4) & 3; }
+
+// Spring type record: constant, rest length and critical length for a
+// (geometry class, phase a, phase b) triple, in both precisions.
+struct TypeRec {
+    float k32, kr0_32, rc2_32, r0_32;  // k, k r0, rc^2, r0 rounded to FP32
+    double k64, r0_64, rc64, pad;
+};
+
+// Loop control kept in device memory so captured graphs can be replayed
+// across increments.
+struct Ctl {
+    double eps;
+    int32_t inc;
+    int32_t step_base;  // steps already done inside the current increment
+    uint32_t n_events;
+    int32_t pad;
+};
+
+// Device record (same layout as lsm_record).
+typedef lsm_record DevRecord;
+
+enum Mode { kStart = 0, kMid = 1, kEnd = 2, kEval = 3 };
+
+struct StepParams {
+    int32_t nx, ny, nz;
+    int32_t tiles_x, tiles_y, ntiles, nblocks;
+    int32_t nphase;
+    int64_t nsites;
+    double a;
+    double dt, gamma;
+    double mass[LSM_MAX_PHASES];
+    const uint8_t *flags;
+    void *mask;            // uint8 (2D) or uint32 (3D) broken bits per site and direction
+    const uint32_t *sbase; // canonical id of the first forward spring of a site
+    void *u_in;            // displacement state read this step
+    void *u_out;           // displacement state written this step
+    void *v;               // velocity (updated in place)
+    void *acc;             // acceleration at the last full step
+    const TypeRec *types;
+    Ctl *ctl;
+    lsm_event *events;
+    int64_t ev_cap;
+    double *partials;      // kNumPartials per workgroup (end-of-relax reductions)
+    double *f64;           // force output of the evaluation mode
+    int32_t commit;        // evaluation mode: apply the break rule to the state
+    int32_t red_blocks;    // workgroups that wrote partials in the last end-of-relax step
+    // row-sweep decomposition of the 2D lattice: each wavefront owns 62
+    // columns of a strip and sw_rows rows, sweeping upward
+    int32_t sw_strips, sw_rows, sw_nwork, sw_nblocks;
+};
+
+// Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.
+hipError_t launch_increment(const StepParams &p, int dim, int prec, hipStream_t stream,
+                            double eps_new, double d_eps, int inc, int affine);
+hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStream_t stream,
+                       int step_local);
+// 2D row-sweep variant of the start/mid/end steps (same semantics as launch_step).
+hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t stream,
+                          int step_local);
+hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
+hipError_t launch_finalize(const StepParams &p, int dim, hipStream_t stream, DevRecord *rec,
+                           double omega, int nsteps);
+
+}  // namespace lsm

@@ -1,0 +1,957 @@
+// lsm_kernels.hip -- HIP kernels (gfx950) of the lattice spring model step.
+//
+// One workgroup owns a 64 x 4 tile of lattice sites (one wavefront per row
+// segment, so every state load of a wavefront is 64 consecutive sites).
+// Each thread owns one site (particle) and gathers the forces of all its
+// incident springs in a fixed direction order, so the force sum is
+// deterministic and independent of the launch shape, and no atomics are
+// needed: a spring shared by particles p and q is evaluated by both, from
+// bitwise-negated inputs, so both reach the same break decision and exactly
+// opposite forces (Eq. 2).  Each particle keeps its own copy of the broken
+// bit of each incident spring; the owner (lower id, forward direction) logs
+// the break event.
+//
+// The step kernel fuses, per site: spring force with the critical-stretch
+// test (Eq. 1-2; Section 2.3 force routine), force accumulation, and the
+// velocity Verlet update in the half-step form (Eq. 3-5, Section 2.2) with
+// viscous damping.  Displacements u = x - X0 are stored (X0 is implied by
+// the site index), double-buffered between steps; velocities are updated in
+// place.  In the FP32 mode forces are FP32 and displacements are kept as a
+// compensated (hi, lo) FP32 pair; springs whose squared length is within a
+// narrow band of rc^2 are re-tested in FP64 from the compensated state.
+#include <math.h>
+
+#include "lsm_internal.h"
+
+namespace lsm {
+namespace {
+
+// Relative band on r^2 below rc^2 inside which the FP32 break decision is
+// handed to FP64.  FP32 errors of r^2 here are below 1e-6 relative.
+constexpr float kBand2 = 3.0e-5f;
+constexpr double kHalfSqrt3 = 0.86602540378443864676;
+
+// ------------------------------------------------------------ state layout
+template <int DIM, int PREC>
+struct State;
+
+// 2D, FP32 compensated: u = (x_hi, y_hi, x_lo, y_lo) as float4, v float2.
+template <>
+struct State<2, 1> {
+    using R = float;
+    __device__ static void load_u(const void *U, int g, int64_t, float hi[2], float lo[2]) {
+        const float4 t = reinterpret_cast<const float4 *>(U)[g];
+        hi[0] = t.x; hi[1] = t.y; lo[0] = t.z; lo[1] = t.w;
+    }
+    __device__ static void store_u(void *U, int g, int64_t, const float hi[2], const float lo[2]) {
+        reinterpret_cast<float4 *>(U)[g] = make_float4(hi[0], hi[1], lo[0], lo[1]);
+    }
+    __device__ static void load_v(const void *V, int g, int64_t, float v[2]) {
+        const float2 t = reinterpret_cast<const float2 *>(V)[g];
+        v[0] = t.x; v[1] = t.y;
+    }
+    __device__ static void store_v(void *V, int g, int64_t, const float v[2]) {
+        reinterpret_cast<float2 *>(V)[g] = make_float2(v[0], v[1]);
+    }
+};
+
+// 2D, FP64: u and v as double2; the low part is identically zero.
+template <>
+struct State<2, 0> {
+    using R = double;
+    __device__ static void load_u(const void *U, int g, int64_t, double hi[2], double lo[2]) {
+        const double2 t = reinterpret_cast<const double2 *>(U)[g];
+        hi[0] = t.x; hi[1] = t.y; lo[0] = 0.0; lo[1] = 0.0;
+    }
+    __device__ static void store_u(void *U, int g, int64_t, const double hi[2], const double *) {
+        reinterpret_cast<double2 *>(U)[g] = make_double2(hi[0], hi[1]);
+    }
+    __device__ static void load_v(const void *V, int g, int64_t, double v[2]) {
+        const double2 t = reinterpret_cast<const double2 *>(V)[g];
+        v[0] = t.x; v[1] = t.y;
+    }
+    __device__ static void store_v(void *V, int g, int64_t, const double v[2]) {
+        reinterpret_cast<double2 *>(V)[g] = make_double2(v[0], v[1]);
+    }
+};
+
+// 3D, FP32 compensated: six planes (x_hi, y_hi, z_hi, x_lo, y_lo, z_lo), v three planes.
+template <>
+struct State<3, 1> {
+    using R = float;
+    __device__ static void load_u(const void *U, int g, int64_t ns, float hi[3], float lo[3]) {
+        const float *P = reinterpret_cast<const float *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { hi[c] = P[c * ns + g]; lo[c] = P[(3 + c) * ns + g]; }
+    }
+    __device__ static void store_u(void *U, int g, int64_t ns, const float hi[3], const float lo[3]) {
+        float *P = reinterpret_cast<float *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { P[c * ns + g] = hi[c]; P[(3 + c) * ns + g] = lo[c]; }
+    }
+    __device__ static void load_v(const void *V, int g, int64_t ns, float v[3]) {
+        const float *P = reinterpret_cast<const float *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = P[c * ns + g];
+    }
+    __device__ static void store_v(void *V, int g, int64_t ns, const float v[3]) {
+        float *P = reinterpret_cast<float *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[c * ns + g] = v[c];
+    }
+};
+
+// 3D, FP64: three planes for u and for v.
+template <>
+struct State<3, 0> {
+    using R = double;
+    __device__ static void load_u(const void *U, int g, int64_t ns, double hi[3], double lo[3]) {
+        const double *P = reinterpret_cast<const double *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { hi[c] = P[c * ns + g]; lo[c] = 0.0; }
+    }
+    __device__ static void store_u(void *U, int g, int64_t ns, const double hi[3], const double *) {
+        double *P = reinterpret_cast<double *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[c * ns + g] = hi[c];
+    }
+    __device__ static void load_v(const void *V, int g, int64_t ns, double v[3]) {
+        const double *P = reinterpret_cast<const double *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = P[c * ns + g];
+    }
+    __device__ static void store_v(void *V, int g, int64_t ns, const double v[3]) {
+        double *P = reinterpret_cast<double *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) P[c * ns + g] = v[c];
+    }
+};
+
+// ------------------------------------------------------- lattice geometry
+// Directions: forward ones first, in canonical spring order, then their
+// opposites in the same order (opposite of d is d + NF).
+template <int DIM>
+struct Geo;
+
+// Triangular packing, odd rows shifted by +a/2.  Directions: E, UL, UR, W,
+// DR, DL.  Column offset = base + parity * adj, row offset = drow.
+template <>
+struct Geo<2> {
+    static constexpr int ND = 6, NF = 3;
+    using Mask = uint8_t;
+    __device__ static int di(int d, int par) {
+        constexpr int base[6] = {1, -1, 0, -1, 0, -1};
+        constexpr int adj[6] = {0, 1, 1, 0, 1, 1};
+        return base[d] + par * adj[d];
+    }
+    __device__ static int dj(int d) {
+        constexpr int v[6] = {0, 1, 1, 0, -1, -1};
+        return v[d];
+    }
+    __device__ static int dk(int) { return 0; }
+    // lattice vector in units of (a, (sqrt3/2) a)
+    __device__ static double ex(int d) {
+        constexpr double v[6] = {1.0, -0.5, 0.5, -1.0, 0.5, -0.5};
+        return v[d];
+    }
+    __device__ static double ey(int d) {
+        constexpr double v[6] = {0.0, 1.0, 1.0, 0.0, -1.0, -1.0};
+        return v[d];
+    }
+    __device__ static int geom(int) { return 0; }
+};
+
+// Simple cubic, 3 face + 6 edge forward directions.
+template <>
+struct Geo<3> {
+    static constexpr int ND = 18, NF = 9;
+    using Mask = uint32_t;
+    __device__ static int off(int d, int c) {
+        constexpr int f[9][3] = {{1, 0, 0},  {0, 1, 0},  {0, 0, 1},  {1, 1, 0}, {-1, 1, 0},
+                                 {1, 0, 1},  {-1, 0, 1}, {0, 1, 1},  {0, -1, 1}};
+        return d < 9 ? f[d][c] : -f[d - 9][c];
+    }
+    __device__ static int di(int d, int) { return off(d, 0); }
+    __device__ static int dj(int d) { return off(d, 1); }
+    __device__ static int dk(int d) { return off(d, 2); }
+    __device__ static int geom(int d) { return (d % 9) < 3 ? 0 : 1; }
+};
+
+template <int PREC>
+struct TT;
+template <>
+struct TT<1> {
+    using type = float4;  // k, k r0, rc^2, r0
+    __device__ static type make(const TypeRec &t) { return make_float4(t.k32, t.kr0_32, t.rc2_32, t.r0_32); }
+};
+struct D4 {
+    double x, y, z, w;
+};
+template <>
+struct TT<0> {
+    using type = D4;  // k, r0, rc
+    __device__ static type make(const TypeRec &t) { return D4{t.k64, t.r0_64, t.rc64, 0.0}; }
+};
+
+__device__ inline void comp_add(float &hi, float &lo, float delta) {
+    // compensated accumulation: hi + lo absorbs delta, the rounding error of
+    // the high sum is carried exactly in lo (two-sum)
+    const float y = delta + lo;
+    const float t = hi + y;
+    const float bp = t - hi;
+    lo = (hi - (t - bp)) + (y - bp);
+    hi = t;
+}
+__device__ inline void comp_add(double &hi, double &, double delta) { hi = hi + delta; }
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Fixed-order workgroup sum of kNumPartials values; result valid in thread 0.
+__device__ inline void block_sum(double *vals, double (*lds)[kBlock / 64]) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < kNumPartials; ++v) {
+        const double s = wave_sum(vals[v]);
+        if (lane == 0) lds[v][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int v = 0; v < kNumPartials; ++v) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += lds[v][w];
+            vals[v] = s;
+        }
+    }
+}
+
+__device__ inline void tile_coords(const StepParams &P, int &i, int &j, int &k, bool &ok) {
+    // XCD-aware remap: consecutive blocks go round-robin over the 8 XCDs, so
+    // give each XCD one contiguous run of tiles (neighbouring rows share L2).
+    const int b = blockIdx.x;
+    const int per = P.nblocks >> 3;
+    const int tile = (b & 7) * per + (b >> 3);
+    ok = tile < P.ntiles;
+    const int tx = tile % P.tiles_x;
+    const int rest = tile / P.tiles_x;
+    const int ty = rest % P.tiles_y;
+    const int tz = rest / P.tiles_y;
+    i = tx * kTileX + (threadIdx.x & (kTileX - 1));
+    j = ty * kTileY + (threadIdx.x / kTileX);
+    k = tz;
+    ok = ok && i < P.nx && j < P.ny;
+}
+
+// Velocity Verlet in the half-step form (Eq. 3-5) with viscous damping
+// evaluated with the half-step velocity, for one free particle; grips stay
+// clamped.  On entry w is the particle's stored velocity (full step at the
+// start of an increment, half step otherwise); F is the spring force at the
+// current positions.
+template <int DIM, int PREC, int MODE>
+__device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp,
+                                      typename State<DIM, PREC>::R *uph,
+                                      typename State<DIM, PREC>::R *upl,
+                                      const typename State<DIM, PREC>::R *F,
+                                      typename State<DIM, PREC>::R *w, double *red) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    const int pa = flag_phase(fp);
+    if (flag_grip(fp) != 0) {
+        // clamped: displacement carried over, velocity stays zero
+        if constexpr (MODE != kEnd) S::store_u(P.u_out, g, P.nsites, uph, upl);
+        if constexpr (MODE == kEnd) {
+            R z[DIM];
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) z[c] = R(0);
+            S::store_v(P.acc, g, P.nsites, z);
+        }
+        return;
+    }
+    const R h = R(0.5 * P.dt);
+    const R dt = R(P.dt);
+    const R gam = R(P.gamma);
+    R acc[DIM];
+    if constexpr (PREC == 1) {
+        const R im = R(1.0 / P.mass[pa]);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * im;
+    } else {
+        const R m = R(P.mass[pa]);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) / m;
+    }
+    if constexpr (MODE == kStart) {
+        // w holds the full-step velocity at the increment
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            w[c] = w[c] + h * acc[c];
+            comp_add(uph[c], upl[c], dt * w[c]);
+        }
+        S::store_u(P.u_out, g, P.nsites, uph, upl);
+        S::store_v(P.v, g, P.nsites, w);
+    } else if constexpr (MODE == kMid) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const R vfull = w[c] + h * acc[c];
+            w[c] = vfull + h * acc[c];
+            comp_add(uph[c], upl[c], dt * w[c]);
+        }
+        S::store_u(P.u_out, g, P.nsites, uph, upl);
+        S::store_v(P.v, g, P.nsites, w);
+    } else if constexpr (MODE == kEnd) {
+        // close the step on the full-step velocity
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) w[c] = w[c] + h * acc[c];
+        S::store_v(P.v, g, P.nsites, w);
+        S::store_v(P.acc, g, P.nsites, acc);
+        const double mm = P.mass[pa];
+#pragma unroll
+        for (int aa = 0; aa < DIM; ++aa) {
+#pragma unroll
+            for (int bb = 0; bb < DIM; ++bb) red[9 + aa * 3 + bb] += mm * double(w[aa]) * double(w[bb]);
+            red[19] += 0.5 * mm * double(w[aa]) * double(w[aa]);
+        }
+    }
+}
+
+// ------------------------------------------------------------ step kernel
+template <int DIM, int PREC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    using G = Geo<DIM>;
+    using Mask = typename G::Mask;
+    using TTy = typename TT<PREC>::type;
+
+    __shared__ TTy tt[kMaxTypes];
+    __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
+    for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    __syncthreads();
+
+    int i, j, k;
+    bool active;
+    tile_coords(P, i, j, k, active);
+    const int g = active ? i + P.nx * (j + P.ny * k) : 0;
+    const uint8_t fp = active ? P.flags[g] : kVoid;
+    active = active && fp != kVoid;
+
+    const R a = R(P.a);
+    const R hy = R(kHalfSqrt3 * P.a);
+
+    double red[MODE == kEnd ? kNumPartials : 1];
+#pragma unroll
+    for (int v = 0; v < (MODE == kEnd ? kNumPartials : 1); ++v) red[v] = 0.0;
+
+    if (active) {
+        R uph[DIM], upl[DIM];
+        S::load_u(P.u_in, g, P.nsites, uph, upl);
+        const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
+        Mask newmask = mask;
+        const int pa = flag_phase(fp);
+        const bool commit = (MODE != kEval) || P.commit;
+        R F[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) F[c] = R(0);
+        int rank = 0;
+#pragma unroll
+        for (int d = 0; d < G::ND; ++d) {
+            const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
+            const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+            if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
+            const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
+            const uint8_t fq = P.flags[q];
+            if (fq == kVoid) continue;
+            const bool fwd = d < G::NF;
+            const int myrank = rank;
+            if (fwd) ++rank;
+            if (mask & (Mask(1) << d)) continue;
+            R uqh[DIM], uql[DIM];
+            S::load_u(P.u_in, q, P.nsites, uqh, uql);
+            // lattice vector X0_q - X0_p
+            R e[DIM];
+            double e64[DIM];
+            if constexpr (DIM == 2) {
+                e[0] = R(G::ex(d)) * a;
+                e[1] = R(G::ey(d)) * hy;
+                e64[0] = G::ex(d) * P.a;
+                e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    e[c] = R(G::off(d, c)) * a;
+                    e64[c] = double(G::off(d, c)) * P.a;
+                }
+            }
+            R dv[DIM];
+            R r2 = R(0);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
+                r2 += dv[c] * dv[c];
+            }
+            const int pb = flag_phase(fq);
+            const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
+            const TTy T = tt[ti];
+            bool brk;
+            double margin = 0.0;
+            double d64[DIM];
+            double r64 = 0.0;
+            bool have64 = false;
+            if constexpr (PREC == 1) {
+                // FP32 test; inside the band (or above rc) the FP64 test decides
+                if (r2 > T.z - kBand2 * T.z) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
+                                           (double(uql[c]) - double(upl[c])));
+                        s2 += d64[c] * d64[c];
+                    }
+                    r64 = sqrt(s2);
+                    have64 = true;
+                    const double rc = P.types[ti].rc64;
+                    brk = r64 > rc;
+                    margin = (r64 - rc) / rc;
+                } else {
+                    brk = false;
+                }
+            } else {
+                r64 = sqrt(double(r2));
+                have64 = true;
+                brk = r64 > T.z;
+                if (brk) margin = (r64 - T.z) / T.z;
+            }
+            if (brk) {
+                if (commit) {
+                    newmask |= Mask(1) << d;
+                    if (fwd) {
+                        const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                        if (idx < P.ev_cap) {
+                            lsm_event ev;
+                            ev.increment = P.ctl->inc;
+                            ev.step = P.ctl->step_base + step_local;
+                            ev.spring_id = int64_t(P.sbase[g]) + myrank;
+                            ev.margin = margin;
+                            P.events[idx] = ev;
+                        }
+                    }
+                }
+                continue;
+            }
+            if constexpr (PREC == 1) {
+                const float rinv = rsqrtf(r2);
+                const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, dv[c], F[c]);
+            } else {
+                const double coef = T.x * (r64 - T.y) / r64;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    F[c] += coef * dv[c];
+                    d64[c] = dv[c];
+                }
+            }
+            if constexpr (MODE == kEnd) {
+                if (fwd) {
+                    // virial (Eq. 7) and potential energy (Eq. 1) in FP64
+                    const TypeRec &T64 = P.types[ti];
+                    if (!have64) {
+                        double s2 = 0.0;
+#pragma unroll
+                        for (int c = 0; c < DIM; ++c) {
+                            d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
+                                               (double(uql[c]) - double(upl[c])));
+                            s2 += d64[c] * d64[c];
+                        }
+                        r64 = sqrt(s2);
+                    }
+                    const double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
+#pragma unroll
+                    for (int aa = 0; aa < DIM; ++aa)
+#pragma unroll
+                        for (int bb = 0; bb < DIM; ++bb) red[aa * 3 + bb] += d64[aa] * (coef64 * d64[bb]);
+                    red[18] += 0.5 * T64.k64 * (r64 - T64.r0_64) * (r64 - T64.r0_64);
+                }
+            }
+        }
+        if (commit && newmask != mask) reinterpret_cast<Mask *>(P.mask)[g] = newmask;
+
+        if constexpr (MODE == kEval) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) P.f64[int64_t(g) * DIM + c] = double(F[c]);
+        } else {
+            R w[DIM];
+            if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
+            integrate_site<DIM, PREC, MODE>(P, g, fp, uph, upl, F, w, red);
+        }
+    }
+
+    if constexpr (MODE == kEnd) {
+        block_sum(red, red_lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int v = 0; v < kNumPartials; ++v) P.partials[int64_t(blockIdx.x) * kNumPartials + v] = red[v];
+        }
+    }
+}
+
+// ------------------------------------------------------- increment kernel
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k_increment(StepParams P, double eps_new, double d_eps,
+                                                   int inc, int affine) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (g == 0) {
+        P.ctl->eps = eps_new;
+        P.ctl->inc = inc;
+        P.ctl->step_base = 0;
+    }
+    if (g >= P.nsites) return;
+    const uint8_t f = P.flags[g];
+    if (f == kVoid) return;
+    const int i = int(g % P.nx);
+    const double c = double(i) * P.a;  // load coordinate of the site's column
+    R hi[DIM], lo[DIM];
+    S::load_u(P.u_in, int(g), P.nsites, hi, lo);
+    if (flag_grip(f)) {
+        const double ux = eps_new * c;
+        hi[0] = R(ux);
+        lo[0] = R(ux - double(hi[0]));
+#pragma unroll
+        for (int cc = 1; cc < DIM; ++cc) { hi[cc] = R(0); lo[cc] = R(0); }
+        R z[DIM];
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) z[cc] = R(0);
+        S::store_v(P.v, int(g), P.nsites, z);
+        S::store_v(P.acc, int(g), P.nsites, z);
+    } else if (affine) {
+        if constexpr (PREC == 1) {
+            const double ux = (double(hi[0]) + double(lo[0])) + d_eps * c;
+            hi[0] = R(ux);
+            lo[0] = R(ux - double(hi[0]));
+        } else {
+            hi[0] = hi[0] + d_eps * c;
+        }
+    }
+    S::store_u(P.u_in, int(g), P.nsites, hi, lo);
+}
+
+// ---------------------------------------------- kick + drift (no forces)
+// Continues a relaxation from a full step: v += dt/2 a, u += dt v.
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k_kick_drift(StepParams P) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (g >= P.nsites) return;
+    const uint8_t f = P.flags[g];
+    if (f == kVoid || flag_grip(f)) return;
+    const R h = R(0.5 * P.dt), dt = R(P.dt);
+    R hi[DIM], lo[DIM], w[DIM], acc[DIM];
+    S::load_u(P.u_in, int(g), P.nsites, hi, lo);
+    S::load_v(P.v, int(g), P.nsites, w);
+    S::load_v(P.acc, int(g), P.nsites, acc);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        w[c] = w[c] + h * acc[c];
+        comp_add(hi[c], lo[c], dt * w[c]);
+    }
+    S::store_u(P.u_in, int(g), P.nsites, hi, lo);
+    S::store_v(P.v, int(g), P.nsites, w);
+}
+
+// ------------------------------------------------------- record finalize
+__global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, DevRecord *rec, double omega,
+                                                     int nsteps, int dim) {
+    __shared__ double lds[kNumPartials][kBlock / 64];
+    double vals[kNumPartials];
+#pragma unroll
+    for (int v = 0; v < kNumPartials; ++v) vals[v] = 0.0;
+    for (int b = threadIdx.x; b < P.red_blocks; b += kBlock) {
+#pragma unroll
+        for (int v = 0; v < kNumPartials; ++v) vals[v] += P.partials[int64_t(b) * kNumPartials + v];
+    }
+    block_sum(vals, lds);
+    if (threadIdx.x == 0) {
+        DevRecord r;
+        r.eps = P.ctl->eps;
+        bool finite = isfinite(vals[18]) && isfinite(vals[19]);
+        for (int aa = 0; aa < 3; ++aa)
+            for (int bb = 0; bb < 3; ++bb) {
+                double s = 0.0;
+                if (aa < dim && bb < dim) s = (vals[aa * 3 + bb] - vals[9 + aa * 3 + bb]) / omega;
+                r.sigma[aa * 3 + bb] = s;
+                finite = finite && isfinite(s);
+            }
+        r.pe = vals[18];
+        r.ke = vals[19];
+        const uint32_t ne = P.ctl->n_events;
+        r.n_broken = int64_t(ne < P.ev_cap ? ne : P.ev_cap);
+        r.increment = P.ctl->inc;
+        r.step = P.ctl->step_base + nsteps;
+        r.status = finite ? LSM_OK : LSM_EUNSTABLE;
+        r.reserved = 0;
+        *rec = r;
+        P.ctl->step_base += nsteps;
+    }
+}
+
+
+// ------------------------------------------------------- 2D row sweep
+// Each wavefront owns kSweepCols columns of a vertical strip (plus one halo
+// column on each side) and a chunk of rows, which it sweeps upward.  Per row
+// a lane loads only its own site; the east neighbour and the sites of the
+// row above come from adjacent lanes through DPP moves.  Every lane
+// evaluates the three forward springs of its site (east, upper-left,
+// upper-right) once; the three backward forces of a site are the negated
+// forward forces of its west neighbour (this row, adjacent lane) and of its
+// two lower neighbours (previous row, carried in registers).  The force sum
+// has a fixed order per site, so results do not depend on the launch shape.
+
+// wave_shl:1 -> lane l reads lane l + 1; wave_shr:1 -> lane l reads lane l - 1
+// (the edge lane keeps its own value; edge lanes are never owned).
+__device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false); }
+__device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false); }
+__device__ inline float lane_next(float x) { return __int_as_float(lane_next(__float_as_int(x))); }
+__device__ inline float lane_prev(float x) { return __int_as_float(lane_prev(__float_as_int(x))); }
+__device__ inline double lane_next(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_next(int(b & 0xFFFFFFFFll)), hi = lane_next(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ inline double lane_prev(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_prev(int(b & 0xFFFFFFFFll)), hi = lane_prev(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <class R>
+struct SweepRow {
+    R uh[2], ul[2], v[2];
+    int f, m;
+};
+
+template <int PREC>
+__device__ inline void load_sweep_row(const StepParams &P, int i, bool col_ok, int jj, bool want_v,
+                                      SweepRow<typename State<2, PREC>::R> &r) {
+    using S = State<2, PREC>;
+    using R = typename S::R;
+    if (col_ok && jj >= 0 && jj < P.ny) {
+        const int g = i + P.nx * jj;
+        S::load_u(P.u_in, g, P.nsites, r.uh, r.ul);
+        r.f = P.flags[g];
+        r.m = reinterpret_cast<const uint8_t *>(P.mask)[g];
+        if (want_v) {
+            S::load_v(P.v, g, P.nsites, r.v);
+        } else {
+            r.v[0] = R(0); r.v[1] = R(0);
+        }
+    } else {
+        r.uh[0] = r.uh[1] = r.ul[0] = r.ul[1] = r.v[0] = r.v[1] = R(0);
+        r.f = kVoid;
+        r.m = 0;
+    }
+}
+
+// One forward spring of site p towards q (lattice vector (ex, ey)).  Returns
+// the force on p in f (zero if absent or broken), present = both ends are
+// particles, brk = broken at this evaluation.
+template <int PREC, class TTy>
+__device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, int mask, int d,
+                                  typename State<2, PREC>::R ex, typename State<2, PREC>::R ey,
+                                  double ex64, double ey64, const typename State<2, PREC>::R *ph,
+                                  const typename State<2, PREC>::R *pl,
+                                  const typename State<2, PREC>::R *qh,
+                                  const typename State<2, PREC>::R *ql, int fq,
+                                  typename State<2, PREC>::R *f, int &present, int &brk,
+                                  double &margin, int &ti) {
+    using R = typename State<2, PREC>::R;
+    f[0] = R(0);
+    f[1] = R(0);
+    present = (fp != kVoid) && (fq != kVoid);
+    brk = 0;
+    margin = 0.0;
+    ti = present ? flag_phase(fp) * LSM_MAX_PHASES + flag_phase(fq) : 0;
+    if (!present || (mask & (1 << d))) return;
+    R dv[2];
+    dv[0] = ex + ((qh[0] - ph[0]) + (ql[0] - pl[0]));
+    dv[1] = ey + ((qh[1] - ph[1]) + (ql[1] - pl[1]));
+    const R r2 = dv[0] * dv[0] + dv[1] * dv[1];
+    const TTy T = tt[ti];
+    if constexpr (PREC == 1) {
+        if (r2 > T.z - kBand2 * T.z) {
+            const double dx = ex64 + ((double(qh[0]) - double(ph[0])) + (double(ql[0]) - double(pl[0])));
+            const double dy = ey64 + ((double(qh[1]) - double(ph[1])) + (double(ql[1]) - double(pl[1])));
+            const double r64 = sqrt(dx * dx + dy * dy);
+            const double rc = types[ti].rc64;
+            brk = r64 > rc;
+            margin = (r64 - rc) / rc;
+        }
+        if (brk) return;
+        const float rinv = rsqrtf(r2);
+        const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
+        f[0] = coef * dv[0];
+        f[1] = coef * dv[1];
+    } else {
+        const double r = sqrt(r2);
+        brk = r > T.z;
+        if (brk) {
+            margin = (r - T.z) / T.z;
+            return;
+        }
+        const double coef = T.x * (r - T.y) / r;
+        f[0] = coef * dv[0];
+        f[1] = coef * dv[1];
+    }
+}
+
+// FP64 virial and potential energy of one intact spring (Eq. 7, Eq. 1).
+template <class R>
+__device__ inline void spring_stress64(const TypeRec &T, double ex64, double ey64, const R *ph,
+                                       const R *pl, const R *qh, const R *ql, double *red) {
+    double d[2];
+    d[0] = ex64 + ((double(qh[0]) - double(ph[0])) + (double(ql[0]) - double(pl[0])));
+    d[1] = ey64 + ((double(qh[1]) - double(ph[1])) + (double(ql[1]) - double(pl[1])));
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1]);
+    const double coef = T.k64 * (r - T.r0_64) / r;
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) red[aa * 3 + bb] += d[aa] * (coef * d[bb]);
+    red[18] += 0.5 * T.k64 * (r - T.r0_64) * (r - T.r0_64);
+}
+
+template <int PREC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
+    using S = State<2, PREC>;
+    using R = typename S::R;
+    using TTy = typename TT<PREC>::type;
+    __shared__ TTy tt[kMaxTypes];
+    __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
+    for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    __syncthreads();
+
+    double red[MODE == kEnd ? kNumPartials : 1];
+#pragma unroll
+    for (int v = 0; v < (MODE == kEnd ? kNumPartials : 1); ++v) red[v] = 0.0;
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int per = P.sw_nblocks >> 3;
+    const int L = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
+    const int w = L * (kBlock / 64) + wv;
+    if (w < P.sw_nwork) {
+        const int s = w % P.sw_strips;
+        const int c = w / P.sw_strips;
+        const int i = s * kSweepCols - 1 + lane;
+        const bool col_ok = i >= 0 && i < P.nx;
+        const bool own_lane = col_ok && lane >= 1 && lane <= kSweepCols;
+        const int j0 = c * P.sw_rows;
+        const int j1 = min(j0 + P.sw_rows, P.ny);
+        const int jstart = j0 > 0 ? j0 - 1 : 0;
+        const R a = R(P.a), hy = R(kHalfSqrt3 * P.a);
+        const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
+        const R half_a = R(0.5) * a;
+
+        SweepRow<R> r0, r1, r2;
+        load_sweep_row<PREC>(P, i, col_ok, jstart, jstart >= j0, r0);
+        load_sweep_row<PREC>(P, i, col_ok, jstart + 1 <= j1 ? jstart + 1 : -1, jstart + 1 >= j0, r1);
+        R pUL[2] = {R(0), R(0)}, pUR[2] = {R(0), R(0)};
+        int pbrk = 0;
+        for (int j = jstart; j < j1; ++j) {
+            load_sweep_row<PREC>(P, i, col_ok, j + 2 <= j1 ? j + 2 : -1, true, r2);
+            const int par = j & 1;
+            // neighbour sites: east (this row, next lane), upper-left / upper-right (row above)
+            R eh[2], el[2], ulh[2], ull[2], urh[2], url[2];
+            int ef, ulf, urf;
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                eh[cc] = lane_next(r0.uh[cc]);
+                el[cc] = PREC ? lane_next(r0.ul[cc]) : R(0);
+            }
+            ef = lane_next(r0.f);
+            if (par == 0) {
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    ulh[cc] = lane_prev(r1.uh[cc]);
+                    ull[cc] = PREC ? lane_prev(r1.ul[cc]) : R(0);
+                    urh[cc] = r1.uh[cc];
+                    url[cc] = r1.ul[cc];
+                }
+                ulf = lane_prev(r1.f);
+                urf = r1.f;
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    ulh[cc] = r1.uh[cc];
+                    ull[cc] = r1.ul[cc];
+                    urh[cc] = lane_next(r1.uh[cc]);
+                    url[cc] = PREC ? lane_next(r1.ul[cc]) : R(0);
+                }
+                ulf = r1.f;
+                urf = lane_next(r1.f);
+            }
+            R fe[2], ful[2], fur[2];
+            int pe, pul, pur, be, bul, bur, te, tul, tur;
+            double me, mul, mur;
+            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 0, a, R(0), a64, 0.0, r0.uh, r0.ul, eh, el, ef,
+                             fe, pe, be, me, te);
+            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 1, -half_a, hy, -0.5 * a64, hy64, r0.uh, r0.ul,
+                             ulh, ull, ulf, ful, pul, bul, mul, tul);
+            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 2, half_a, hy, 0.5 * a64, hy64, r0.uh, r0.ul,
+                             urh, url, urf, fur, pur, bur, mur, tur);
+            const int nb = be | (bul << 1) | (bur << 2);
+            if (j >= j0) {
+                R gW[2], gDR[2], gDL[2];
+                int bW, bDR, bDL;
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) gW[cc] = lane_prev(fe[cc]);
+                bW = lane_prev(nb) & 1;
+                if (par == 0) {
+                    // lower-right neighbour is this lane, lower-left the previous lane
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        gDR[cc] = pUL[cc];
+                        gDL[cc] = lane_prev(pUR[cc]);
+                    }
+                    bDR = pbrk & 1;
+                    bDL = (lane_prev(pbrk) >> 1) & 1;
+                } else {
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc) {
+                        gDR[cc] = lane_next(pUL[cc]);
+                        gDL[cc] = pUR[cc];
+                    }
+                    bDR = lane_next(pbrk) & 1;
+                    bDL = (pbrk >> 1) & 1;
+                }
+                if (own_lane && r0.f != kVoid) {
+                    const int g = i + P.nx * j;
+                    R F[2];
+#pragma unroll
+                    for (int cc = 0; cc < 2; ++cc)
+                        F[cc] = ((((fe[cc] + ful[cc]) + fur[cc]) - gW[cc]) - gDR[cc]) - gDL[cc];
+                    const int newmask = r0.m | nb | (bW << 3) | (bDR << 4) | (bDL << 5);
+                    if (newmask != r0.m) {
+                        reinterpret_cast<uint8_t *>(P.mask)[g] = uint8_t(newmask);
+                        const int brks[3] = {be, bul, bur};
+                        const double mgs[3] = {me, mul, mur};
+                        const int pres[3] = {pe, pul, pur};
+                        int rank = 0;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            if (brks[d]) {
+                                const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                                if (idx < P.ev_cap) {
+                                    lsm_event ev;
+                                    ev.increment = P.ctl->inc;
+                                    ev.step = P.ctl->step_base + step_local;
+                                    ev.spring_id = int64_t(P.sbase[g]) + rank;
+                                    ev.margin = mgs[d];
+                                    P.events[idx] = ev;
+                                }
+                            }
+                            rank += pres[d];
+                        }
+                    }
+                    if constexpr (MODE == kEnd) {
+                        const int mk = newmask;
+                        if (pe && !(mk & 1)) spring_stress64(P.types[te], a64, 0.0, r0.uh, r0.ul, eh, el, red);
+                        if (pul && !(mk & 2))
+                            spring_stress64(P.types[tul], -0.5 * a64, hy64, r0.uh, r0.ul, ulh, ull, red);
+                        if (pur && !(mk & 4))
+                            spring_stress64(P.types[tur], 0.5 * a64, hy64, r0.uh, r0.ul, urh, url, red);
+                    }
+                    integrate_site<2, PREC, MODE>(P, g, uint8_t(r0.f), r0.uh, r0.ul, F, r0.v, red);
+                }
+            }
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                pUL[cc] = ful[cc];
+                pUR[cc] = fur[cc];
+            }
+            pbrk = (nb >> 1) & 3;
+            r0 = r1;
+            r1 = r2;
+        }
+    }
+    if constexpr (MODE == kEnd) {
+        block_sum(red, red_lds);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int v = 0; v < kNumPartials; ++v) P.partials[int64_t(blockIdx.x) * kNumPartials + v] = red[v];
+        }
+    }
+}
+
+template <int DIM, int PREC>
+hipError_t launch_step_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
+    const dim3 grid(p.nblocks), block(kBlock);
+    switch (mode) {
+        case kStart: hipLaunchKernelGGL((k_step<DIM, PREC, kStart>), grid, block, 0, s, p, step_local); break;
+        case kMid: hipLaunchKernelGGL((k_step<DIM, PREC, kMid>), grid, block, 0, s, p, step_local); break;
+        case kEnd: hipLaunchKernelGGL((k_step<DIM, PREC, kEnd>), grid, block, 0, s, p, step_local); break;
+        default: hipLaunchKernelGGL((k_step<DIM, PREC, kEval>), grid, block, 0, s, p, step_local); break;
+    }
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_sweep_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
+    const dim3 grid(p.sw_nblocks), block(kBlock);
+    switch (mode) {
+        case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart>), grid, block, 0, s, p, step_local); break;
+        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid>), grid, block, 0, s, p, step_local); break;
+        default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd>), grid, block, 0, s, p, step_local); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t s, int step_local) {
+    return prec ? launch_sweep_t<1>(p, mode, s, step_local) : launch_sweep_t<0>(p, mode, s, step_local);
+}
+
+hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStream_t s, int step_local) {
+    if (dim == 2) return prec ? launch_step_t<2, 1>(p, mode, s, step_local) : launch_step_t<2, 0>(p, mode, s, step_local);
+    return prec ? launch_step_t<3, 1>(p, mode, s, step_local) : launch_step_t<3, 0>(p, mode, s, step_local);
+}
+
+hipError_t launch_increment(const StepParams &p, int dim, int prec, hipStream_t s, double eps_new,
+                            double d_eps, int inc, int affine) {
+    const dim3 grid(unsigned((p.nsites + 255) / 256)), block(256);
+    if (dim == 2) {
+        if (prec) hipLaunchKernelGGL((k_increment<2, 1>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+        else hipLaunchKernelGGL((k_increment<2, 0>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_increment<3, 1>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+        else hipLaunchKernelGGL((k_increment<3, 0>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t s) {
+    const dim3 grid(unsigned((p.nsites + 255) / 256)), block(256);
+    if (dim == 2) {
+        if (prec) hipLaunchKernelGGL((k_kick_drift<2, 1>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_kick_drift<2, 0>), grid, block, 0, s, p);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_kick_drift<3, 1>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_kick_drift<3, 0>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const StepParams &p, int dim, hipStream_t s, DevRecord *rec, double omega,
+                           int nsteps) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, p, rec, omega, nsteps, dim);
+    return hipGetLastError();
+}
+
+}  // namespace lsm

@@ -1,0 +1,327 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 runs match the oracle's stress within 1e-4 relative and
+FP32-compensated runs within 1e-3 (relative to max(|sigma|, 1e-3 peak));
+broken-spring sequences are identical up to the first near-tie event
+(margin <= 1e-9 for FP64, <= 1e-5 for FP32), after which fracture paths may
+legitimately diverge.  Every test prints the case it runs before touching
+the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import Net, Params
+from paper_2201_04565_amd import inputs
+from tests.parity import compare_events, compare_records
+
+pytestmark = pytest.mark.gpu
+
+NAN = float("nan")
+TOL = {"fp64": (1e-4, 1e-9), "fp32k": (1e-3, 1e-5)}
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lsm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2201_04565_amd import lsm as _lsm
+    _lsm.load_library()
+    return _lsm
+
+
+def oracle_for(img, wl, **over):
+    kw = dict(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
+              k_face=wl.get("k_face", 1.0), k_diag=wl.get("k_diag", 1.0), dt=wl["dt"],
+              gamma=wl["gamma"], void_value=wl.get("void_value", -1))
+    kw.update({k: v for k, v in over.items() if k in kw or k == "predictor"})
+    return Net.lattice(img, Params(**kw))
+
+
+def gpu_for(lsm, img, wl, precision, **over):
+    return lsm.Lattice.from_workload(wl, img, precision=precision, **over)
+
+
+def run_both(lsm, img, wl, precision, n_inc, steps, d_eps, **over):
+    o = oracle_for(img, wl, **over)
+    g = gpu_for(lsm, img, wl, precision, **over)
+    ro, rg = [], []
+    for _ in range(n_inc):
+        o.apply_increment(d_eps)
+        o.relax(steps)
+        ro.append(o.record())
+        g.apply_increment(d_eps)
+        g.relax(steps)
+        rg.append(g.read_state())
+    return o, g, ro, rg
+
+
+# ------------------------------------------------------------ full protocol
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_c1_full_protocol(lsm, precision):
+    wl = inputs.WORKLOADS["c1"]
+    say(f"c1 32x32 {precision} 20 inc x 500 steps")
+    o, g, ro, rg = run_both(lsm, inputs.c1_image(), wl, precision, wl["n_inc"], wl["steps"],
+                            wl["d_eps"])
+    rtol, tie = TOL[precision]
+    ev_o, ev_g = o.events(), g.read_broken()
+    assert len(ev_o) > 10
+    div_inc, k = compare_events(ev_o, ev_g, tie)
+    say(f"  {len(ev_o)} oracle events, {k} identical before the first near-tie; "
+        f"records compared up to increment {min(div_inc, wl['n_inc'] + 1)}")
+    n = compare_records(ro, rg, rtol, 2, upto_inc=div_inc)
+    assert n >= 5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_brick_crop_with_fracture(lsm, precision):
+    # brick-and-mortar crop spanning several tiles with a ragged tail,
+    # loaded fast enough to crack within a short run
+    img = inputs.brick_and_mortar(200, 61, seed=1)
+    wl = dict(inputs.WORKLOADS["c2"])
+    say(f"brick 200x61 {precision} 6 inc x 400 steps, d_eps 0.004")
+    o, g, ro, rg = run_both(lsm, img, wl, precision, 6, 400, 0.004)
+    rtol, tie = TOL[precision]
+    ev_o, ev_g = o.events(), g.read_broken()
+    assert len(ev_o) > 0
+    div_inc, k = compare_events(ev_o, ev_g, tie)
+    say(f"  {len(ev_o)} oracle events, {k} identical; divergence from increment {div_inc}")
+    compare_records(ro, rg, rtol, 2, upto_inc=div_inc)
+
+
+def test_c2_prefix_fp32k(lsm):
+    # the C2 loading (0.05 % per increment, 2000 steps) on a 384x160 crop
+    img = inputs.brick_and_mortar(384, 160, seed=1)
+    wl = inputs.WORKLOADS["c2"]
+    say("brick 384x160 fp32k 2 inc x 2000 steps (c2 loading)")
+    o, g, ro, rg = run_both(lsm, img, wl, "fp32k", 2, wl["steps"], wl["d_eps"])
+    compare_records(ro, rg, TOL["fp32k"][0], 2)
+    assert len(g.read_broken()) == len(o.events())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_3d_grf_with_fracture(lsm, precision):
+    img = inputs.gaussian_random_field_3d(20, corr_len=3.0, seed=2)
+    wl = inputs.WORKLOADS["c3"]
+    say(f"3d grf 20^3 {precision} 4 inc x 300 steps, d_eps 0.01")
+    o, g, ro, rg = run_both(lsm, img, wl, precision, 4, 300, 0.01)
+    rtol, tie = TOL[precision]
+    ev_o, ev_g = o.events(), g.read_broken()
+    div_inc, k = compare_events(ev_o, ev_g, tie)
+    say(f"  {len(ev_o)} oracle events, {k} identical; divergence from increment {div_inc}")
+    compare_records(ro, rg, rtol, 3, upto_inc=div_inc)
+
+
+def test_relax_continuation_and_grips_only(lsm):
+    img = inputs.c1_image()
+    wl = inputs.WORKLOADS["c1"]
+    say("c1 fp64 grips-only predictor, relax split 150 + 250")
+    o = oracle_for(img, wl, predictor=1)
+    g = gpu_for(lsm, img, wl, "fp64", predictor="grips")
+    for _ in range(3):
+        for x in (o, g):
+            x.apply_increment(0.01)
+            x.relax(150)
+            x.relax(250)
+    compare_records([o.record()], [g.read_state()], 1e-4, 2)
+    assert np.max(np.abs(g.x - o.x)) < 1e-9
+    assert np.max(np.abs(g.v - o.v)) < 1e-9
+
+
+# ------------------------------------------------------------- forces only
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_forces_ragged(lsm, precision, case):
+    if case == "2d":
+        img = inputs.bernoulli_two_phase(150, 37, 0.4, seed=5)
+        wl = dict(inputs.WORKLOADS["c1"], s=[[10.0, NAN], [NAN, 10.0]])
+    else:
+        img = inputs.gaussian_random_field_3d(16, corr_len=2.5, seed=4)[:, :13, :]
+        wl = dict(inputs.WORKLOADS["c3"], s=[[10.0]])
+    say(f"forces {case} {img.shape} {precision}")
+    o = oracle_for(img, wl)
+    g = gpu_for(lsm, img, wl, precision)
+    x = o.X0 + inputs.perturbation(o.n, o.dim, 0.05, seed=8)
+    o.x = x
+    g.x = x
+    Fo = o.forces()
+    Fg = g.eval_forces()
+    scale = np.max(np.abs(Fo))
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    assert np.max(np.abs(Fg - Fo)) <= tol * scale
+    assert np.max(np.abs(Fg.sum(axis=0))) <= (1e-12 if precision == "fp64" else 1e-5) * scale * 10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_break_set_exact(lsm, precision):
+    img = inputs.bernoulli_two_phase(70, 21, 0.5, seed=6)
+    wl = dict(inputs.WORKLOADS["c1"], s=[[0.08, NAN], [NAN, 0.03]])
+    say(f"break set 70x21 {precision}")
+    o = oracle_for(img, wl)
+    g = gpu_for(lsm, img, wl, precision)
+    x = o.X0 + inputs.perturbation(o.n, 2, 0.04, seed=9)
+    o.x = x
+    g.x = x
+    Fo = o.forces(commit=True)
+    Fg = g.eval_forces(commit=True)
+    bo = o.springs()["broken"]
+    bg = g.springs()["broken"]
+    assert 0 < bo.sum() < len(bo)
+    assert np.array_equal(bo, bg)
+    ev_o, ev_g = o.events(), g.read_broken()
+    assert np.array_equal(ev_o["id"], ev_g["id"])
+    assert np.allclose(ev_o["margin"], ev_g["margin"], rtol=1e-6, atol=1e-12)
+    assert np.allclose(Fg, Fo, rtol=0, atol=(1e-12 if precision == "fp64" else 2e-6) * np.abs(Fo).max())
+
+
+# ------------------------------------------------------- full-size sample
+def test_c2_full_size_first_steps(lsm):
+    img = inputs.c2_image()
+    wl = inputs.WORKLOADS["c2"]
+    say("c2 2048x2048 fp32k full size: 1 increment x 20 steps vs oracle")
+    g = gpu_for(lsm, img, wl, "fp32k")
+    g.apply_increment(wl["d_eps"])
+    g.relax(20)
+    rg = g.read_state()
+    xg = g.x
+    del g
+    o = oracle_for(img, wl)
+    o.apply_increment(wl["d_eps"])
+    o.relax(20)
+    ro = o.record()
+    compare_records([ro], [rg], 1e-3, 2)
+    idx = np.random.default_rng(0).choice(o.n, 20000, replace=False)
+    xo = o.x[idx]
+    assert np.max(np.abs(xg[idx] - xo)) < 1e-6
+
+
+# ------------------------------------------------------------- properties
+def test_bitwise_repeatable_and_checkpoint(lsm):
+    img = inputs.brick_and_mortar(130, 50, seed=3)
+    wl = inputs.WORKLOADS["c2"]
+    say("checkpoint / repeatability brick 130x50 fp32k")
+    a = gpu_for(lsm, img, wl, "fp32k")
+    b = gpu_for(lsm, img, wl, "fp32k")
+    for x in (a, b):
+        for _ in range(3):
+            x.apply_increment(0.003)
+            x.relax(300)
+    sa, sb = a.save_state(), b.save_state()
+    assert sa == sb
+    for _ in range(2):
+        a.apply_increment(0.003)
+        a.relax(300)
+    c = gpu_for(lsm, img, wl, "fp32k")
+    c.load_state(sb)
+    for _ in range(2):
+        c.apply_increment(0.003)
+        c.relax(300)
+    assert a.save_state() == c.save_state()
+    ra, rc = a.read_state(), c.read_state()
+    assert np.array_equal(ra["sigma"], rc["sigma"]) and ra["n_broken"] == rc["n_broken"]
+
+
+def test_unstable_is_reported(lsm):
+    img = np.zeros((8, 8), np.uint8)
+    say("instability dt=2.5 fp64")
+    g = lsm.Lattice(img, k=[[1.0]], s=[[1e300]], mass=[1.0], dt=2.5, gamma=0.0)
+    g.x = g.X0 + inputs.perturbation(g.n, 2, 1e-3, seed=1)
+    g.apply_increment(0.0)
+    g.relax(400)
+    rec = g.read_state(allow_unstable=True)
+    assert rec["status"] == lsm.LSM_EUNSTABLE
+    with pytest.raises(lsm.LsmError):
+        g.read_state()
+
+
+def test_state_roundtrip_and_call_order(lsm):
+    img = inputs.bernoulli_two_phase(33, 9, 0.5, seed=2)
+    wl = inputs.WORKLOADS["c1"]
+    say("state roundtrip 33x9")
+    for prec, tol in (("fp64", 0.0), ("fp32k", 1e-12)):
+        g = gpu_for(lsm, img, wl, prec)
+        x = g.X0 + inputs.perturbation(g.n, 2, 0.1, seed=3)
+        g.x = x
+        assert np.max(np.abs(g.x - x)) <= tol * 40
+        g.apply_increment(0.001)
+        with pytest.raises(lsm.LsmError) as e:
+            g.apply_increment(0.001)     # relax must come first
+        assert e.value.code == lsm.LSM_ESTATE
+        with pytest.raises(lsm.LsmError):
+            g.x = x                      # not between relaxations
+        g.relax(5)
+
+
+def test_empty_lattice(lsm):
+    say("all-void 3d lattice")
+    g = lsm.Lattice(np.full((3, 4, 5), 255, np.uint8), k=[[1.0]], s=[[0.1]], mass=[1.0],
+                    void_value=255)
+    g.apply_increment(0.01)
+    g.relax(3)
+    r = g.read_state()
+    assert r["n_broken"] == 0 and np.all(r["sigma"] == 0)
+
+
+# ------------------------------------------------------- kernel variants
+@pytest.mark.parametrize("variant", ["gather", "sweep"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_c1_kernel_variants(lsm, variant, precision):
+    wl = inputs.WORKLOADS["c1"]
+    img = inputs.c1_image()
+    say(f"c1 {variant} {precision} 10 inc x 500 steps")
+    o = oracle_for(img, wl)
+    g = gpu_for(lsm, img, wl, precision)
+    g.set_launch(variant, 5 if variant == "sweep" else 0)
+    ro, rg = [], []
+    for _ in range(10):
+        for x, rec in ((o, ro), (g, rg)):
+            x.apply_increment(wl["d_eps"])
+            x.relax(wl["steps"])
+        ro.append(o.record())
+        rg.append(g.read_state())
+    rtol, tie = TOL[precision]
+    div_inc, k = compare_events(o.events(), g.read_broken(), tie)
+    compare_records(ro, rg, rtol, 2, upto_inc=div_inc)
+
+
+def test_sweep_bitwise_independent_of_rows(lsm):
+    # ragged in both directions: 150 columns (3 strips), 77 rows
+    img = inputs.brick_and_mortar(150, 77, seed=4)
+    wl = inputs.WORKLOADS["c2"]
+    states, recs = [], []
+    for rows in (2, 5, 16, 200):
+        say(f"sweep rows={rows} brick 150x77 fp32k")
+        g = gpu_for(lsm, img, wl, "fp32k")
+        g.set_launch("sweep", rows)
+        for _ in range(6):
+            g.apply_increment(0.006)
+            g.relax(300)
+        states.append(g.save_state())
+        recs.append(g.read_state())
+    assert recs[0]["n_broken"] > 0
+    for st in states[1:]:
+        assert st == states[0]
+
+
+def test_gather_and_sweep_agree(lsm):
+    img = inputs.brick_and_mortar(130, 40, seed=5)
+    wl = inputs.WORKLOADS["c2"]
+    say("gather vs sweep brick 130x40 fp64")
+    out = []
+    for variant in ("gather", "sweep"):
+        g = gpu_for(lsm, img, wl, "fp64")
+        g.set_launch(variant)
+        for _ in range(2):
+            g.apply_increment(0.001)
+            g.relax(500)
+        out.append((g.read_state(), g.x))
+    (ra, xa), (rb, xb) = out
+    assert np.max(np.abs(xa - xb)) < 1e-12
+    assert np.allclose(ra["sigma"], rb["sigma"], rtol=1e-10, atol=1e-16)

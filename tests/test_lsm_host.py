@@ -1,0 +1,130 @@
+"""CPU tests of liblsm.so: exported symbols and the host-side logic (lattice
+builder, spring typing, argument validation).  No GPU calls are made."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import Net, Params
+from paper_2201_04565_amd import inputs, lsm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+NAN = float("nan")
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "lsm.h")).read()
+    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*(lsm_\w+)\(", txt, re.M)))
+
+
+def test_library_exports_every_header_function():
+    L = lsm.load_library()
+    names = header_functions()
+    assert len(names) >= 20
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(names) == set(lsm.EXPORTS)
+
+
+def _model(img, wl, **over):
+    kw = dict(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
+              k_face=wl.get("k_face", 1.0), k_diag=wl.get("k_diag", 1.0),
+              void_value=wl.get("void_value", -1), precision=wl.get("precision", "fp64"))
+    kw.update(over)
+    return lsm.HostModel(img, **kw)
+
+
+def _oracle(img, wl, **over):
+    kw = dict(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
+              k_face=wl.get("k_face", 1.0), k_diag=wl.get("k_diag", 1.0),
+              void_value=wl.get("void_value", -1))
+    kw.update(over)
+    return Net.lattice(img, Params(**kw))
+
+
+CASES = [
+    ("c1", lambda: inputs.c1_image()),
+    ("c2", lambda: inputs.brick_and_mortar(150, 97, seed=1)),
+    ("c4", lambda: inputs.circular_inclusions(64, seed=1003)),
+    ("c3", lambda: inputs.gaussian_random_field_3d(24, corr_len=3.0, seed=2)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_builder_matches_oracle(name, make):
+    img = make()
+    wl = inputs.WORKLOADS[name]
+    g = _model(img, wl)
+    o = _oracle(img, wl)
+    assert (g.n, g.m) == (o.n, o.m)
+    gs, os_ = g.springs(), o.springs()
+    assert np.array_equal(gs["p"], os_["p"]) and np.array_equal(gs["q"], os_["q"])
+    assert np.allclose(gs["k"], os_["k"], rtol=1e-15, atol=0)
+    assert np.allclose(gs["r0"], os_["r0"], rtol=1e-14, atol=0)
+    assert np.allclose(gs["rc"], os_["rc"], rtol=1e-14, atol=0)
+    assert np.allclose(g.X0, o.X0, rtol=0, atol=1e-12)
+
+
+def test_c2_full_size_counts():
+    # closed form (W-1) H + (2W-1)(H-1) at 2048^2
+    g = _model(inputs.c2_image(), inputs.WORKLOADS["c2"])
+    assert (g.n, g.m) == (4194304, 12574721)
+    # algorithmic bytes per step: 24 B state read + written, flag, mask per site
+    assert g.step_bytes() == 4194304 * 50
+
+
+def test_table2_paper_mode_types():
+    # explicit interface constants (paper's spring table), r0 = 10
+    k = [[2e-5, 1.25e-4], [1.25e-4, 2e-3]]
+    s = [[0.1, 0.04], [0.04, 0.01]]
+    img = np.array([[1, 0, 1], [0, 1, 0]], np.uint8)
+    g = lsm.HostModel(img, k=k, s=s, mass=[1.0, 1.0], a=10.0)
+    sp = g.springs()
+    ph = img.ravel()
+    for p, q, kk, rc in zip(sp["p"], sp["q"], sp["k"], sp["rc"]):
+        a, b = sorted((ph[p], ph[q]))
+        assert kk == k[a][b]
+        assert rc == pytest.approx(10.0 * (1 + s[a][b]), rel=1e-15)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(mass=[0.0, 1.0]), dict(dt=0.0), dict(gamma=-1.0), dict(a=-1.0),
+    dict(k=[[-1.0, NAN], [NAN, 1.0]]), dict(s=[[NAN, NAN], [NAN, 0.1]]),
+])
+def test_create_rejects_bad_config(bad):
+    kw = dict(k=[[0.1, NAN], [NAN, 1.0]], s=[[0.2, NAN], [NAN, 0.05]], mass=[1.0, 1.0])
+    kw.update(bad)
+    with pytest.raises(lsm.LsmError) as e:
+        lsm.HostModel(np.zeros((4, 4), np.uint8), **kw)
+    assert e.value.code == lsm.LSM_EINVAL
+
+
+def test_build_rejects_bad_image():
+    kw = dict(k=[[1.0]], s=[[0.1]], mass=[1.0])
+    with pytest.raises(lsm.LsmError) as e:
+        lsm.HostModel(np.full((3, 3), 7, np.uint8), **kw)   # phase 7 with one phase
+    assert e.value.code == lsm.LSM_EINVAL
+
+
+def test_empty_and_degenerate_images():
+    kw = dict(k=[[1.0]], s=[[0.1]], mass=[1.0], void_value=255)
+    g = lsm.HostModel(np.full((3, 5), 255, np.uint8), **kw)
+    assert (g.n, g.m) == (0, 0)
+    g = lsm.HostModel(np.zeros((1, 1), np.uint8), **kw)
+    assert (g.n, g.m) == (1, 0)
+    g = lsm.HostModel(np.zeros((1, 7), np.uint8), **kw)
+    assert (g.n, g.m) == (7, 6)
+
+
+def test_unbound_calls_report_state_errors():
+    L = lsm.load_library()
+    g = lsm.HostModel(np.zeros((4, 4), np.uint8), k=[[1.0]], s=[[0.1]], mass=[1.0])
+    assert L.lsm_apply_strain_increment(g._h, 0.01) == lsm.LSM_ESTATE
+    assert L.lsm_relax(g._h, 10) == lsm.LSM_ESTATE
+    R = lsm.Record()
+    assert L.lsm_read_state(g._h, C.byref(R)) == lsm.LSM_ESTATE
+    assert L.lsm_bind(g._h, None, 0, None) == lsm.LSM_EINVAL
+    assert L.lsm_strerror(lsm.LSM_EUNSTABLE).decode().startswith("non-finite")
