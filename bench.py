@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--steps-per-inc", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -88,6 +90,9 @@ def main():
     lat = lsm.Lattice.from_workload(wl, img, precision="fp32k", device="cuda:0")
     print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
           flush=True)
+    tuning = lat.autotune(100)
+    launch = lat.launch()
+    print(f"[bench] autotuned launch: {launch}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         lat.apply_increment(wl["d_eps"])
@@ -140,6 +145,7 @@ def main():
             "strain_at_end": rec["eps"],
             "broken_springs_at_end": rec["n_broken"],
             "step_kernel_us": avg_kernel_s * 1e6,
+            "launch": launch,
             "hbm_fraction_of_wall": step_bytes * timesteps / wall / 1e9 / HBM_PEAK_GBS,
         },
         "roofline": {
@@ -150,9 +156,18 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "bytes_per_launch": step_bytes,
-            "kernel": "k_step<2,1,kMid>",
+            "kernel": "k_sweep2d<1,1> (fp32, interior step)",
         },
     }
+    if args.copy_ref:
+        # plain copy kernel of known size: reads and writes copy_ref MiB once
+        n = args.copy_ref * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads and writes MIB MiB
+        torch.cuda.synchronize()
+        out["copy_ref_mib"] = args.copy_ref
     if not args.no_cpu:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)

@@ -116,6 +116,15 @@ typedef struct {
     double margin;
 } lsm_event;
 
+/* One launch configuration of the step kernel and its measured time. */
+typedef struct {
+    int32_t variant;       /* LSM_KERNEL_GATHER or LSM_KERNEL_SWEEP */
+    int32_t rows_per_wave; /* sweep row chunk */
+    int32_t prefetch;      /* sweep rows prefetched ahead */
+    int32_t reserved;
+    double us_per_step;    /* measured (lsm_autotune), 0 otherwise */
+} lsm_tuning;
+
 typedef struct lsm_handle lsm_handle;
 
 /* Creates a handle from a copy of *cfg.  Errors: LSM_EINVAL for an invalid
@@ -220,6 +229,23 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);
  * the 2D sweep.  Results are bitwise independent of rows_per_wave.  Only
  * between relaxations (LSM_ESTATE otherwise); drops cached graphs.        */
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave);
+
+/* Rows the 2D sweep prefetches ahead of the row it computes (1..3).
+ * Results are bitwise independent of it.  Same call-order rules as
+ * lsm_set_launch.                                                         */
+int lsm_set_prefetch(lsm_handle *h, int rows_ahead);
+
+/* Autotuner: times every candidate launch of the interior step kernel on
+ * the bound lattice (steps_per_trial even, 2..1000, replayed from a HIP
+ * graph and timed with HIP events), keeps the fastest and writes up to cap
+ * results (n_results = number of candidates).  The dynamic state is
+ * checkpointed to host memory before the trials and restored after them,
+ * so tuning never changes results.  Only between relaxations (LSM_ESTATE
+ * otherwise).  Synchronises.                                              */
+int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int cap, int *n_results);
+
+/* Current launch configuration.                                           */
+int lsm_get_launch(const lsm_handle *h, lsm_tuning *out);
 
 const char *lsm_last_error(const lsm_handle *h);
 const char *lsm_strerror(int status);

@@ -13,6 +13,10 @@ SOURCES = [os.path.join(CSRC, "lsm_kernels.hip"), os.path.join(CSRC, "lsm_host.c
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # fuse multiply-adds only inside one expression, so every inlined or
+    # unrolled copy of a formula rounds the same way (bitwise results do not
+    # depend on the launch shape)
+    "-ffp-contract=on",
     # packed FP32 instructions are kept out of all device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

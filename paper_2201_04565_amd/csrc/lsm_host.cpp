@@ -53,7 +53,8 @@ struct lsm_handle {
     double omega = 0.0;
     int tiles_x = 0, tiles_y = 0, ntiles = 0, nblocks = 0;
     int variant = LSM_KERNEL_AUTO;  // step kernel family
-    int sw_rows = 16;               // rows per wavefront of the 2D row sweep
+    int sw_rows = 4;                // rows per wavefront of the 2D row sweep
+    int sw_pf = 1;                  // rows prefetched ahead in the sweep
     size_t ub = 0, vb = 0, mb = 0;  // bytes per site of u, v, mask
     // device
     hipStream_t stream = nullptr;
@@ -197,6 +198,7 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     p.f64 = h->d_f64;
     p.commit = 1;
     p.sw_rows = h->sw_rows;
+    p.sw_pf = h->sw_pf;
     p.sw_strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
     p.sw_nwork = p.sw_strips * int((h->ny + h->sw_rows - 1) / h->sw_rows);
     p.sw_nblocks = ((p.sw_nwork + 4 * 8 - 1) / (4 * 8)) * 8;
@@ -209,7 +211,7 @@ bool use_sweep(const lsm_handle *h) { return h->dim == 2 && h->variant != LSM_KE
 // Start / interior / end step with the kernel family chosen for this lattice.
 hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_local) {
     if (use_sweep(h) && mode != lsm::kEval) {
-        p.red_blocks = p.sw_nblocks;
+        p.red_blocks = int(h->ny) * p.sw_strips;  // one partial per (row, strip)
         return lsm::launch_sweep2d(p, h->prec, mode, h->stream, step_local);
     }
     p.red_blocks = p.nblocks;
@@ -219,9 +221,8 @@ hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_l
 // Largest number of workgroups any end-of-relax kernel may use.
 int max_red_blocks(const lsm_handle *h) {
     const int strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
-    const int nwork = strips * int((h->ny + kMinSweepRows - 1) / kMinSweepRows);
-    const int sweep_blocks = ((nwork + 31) / 32) * 8;
-    return std::max(h->nblocks, sweep_blocks);
+    const int sweep_partials = h->dim == 2 ? int(h->ny) * strips : 0;
+    return std::max(h->nblocks, sweep_partials);
 }
 
 int sync(lsm_handle *h) {
@@ -854,9 +855,15 @@ int lsm_save_state(lsm_handle *h, void *buf, size_t *n) {
     HIPCHK(h, hipMemcpyAsync(o, h->d_mask, ns * h->mb, hipMemcpyDeviceToHost, h->stream)); o += ns * h->mb;
     std::memcpy(o, &ctl, sizeof(Ctl)); o += sizeof(Ctl);
     HIPCHK(h, hipMemcpyAsync(o, h->d_rec, sizeof(DevRecord), hipMemcpyDeviceToHost, h->stream)); o += sizeof(DevRecord);
-    if (nev) HIPCHK(h, hipMemcpyAsync(o, h->d_events, size_t(nev) * sizeof(lsm_event), hipMemcpyDeviceToHost, h->stream));
+    rc = sync(h);
+    if (rc) return rc;
+    // events in canonical (increment, step, spring) order: the device log is
+    // filled through an atomic counter, so its slot order is not reproducible
+    rc = fetch_events(h);
+    if (rc) return rc;
+    if (nev) std::memcpy(o, h->ev_sorted.data(), size_t(nev) * sizeof(lsm_event));
     *n = need;
-    return sync(h);
+    return LSM_OK;
 }
 
 int lsm_load_state(lsm_handle *h, const void *buf, size_t n) {
@@ -921,6 +928,18 @@ int lsm_read_timing(lsm_handle *h, double *ms, int64_t *steps) {
     return LSM_OK;
 }
 
+int lsm_set_prefetch(lsm_handle *h, int rows_ahead) {
+    if (!h) return LSM_EINVAL;
+    if (rows_ahead < 1 || rows_ahead > 3) return fail(h, LSM_EINVAL, "prefetch depth must be 1..3");
+    if (h->half) return fail(h, LSM_ESTATE, "change the launch only between relaxations");
+    if (rows_ahead != h->sw_pf) {
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+    }
+    h->sw_pf = rows_ahead;
+    return LSM_OK;
+}
+
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     if (!h) return LSM_EINVAL;
     if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP)
@@ -935,6 +954,91 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     }
     h->variant = variant;
     if (rows_per_wave) h->sw_rows = rows_per_wave;
+    return LSM_OK;
+}
+
+int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int cap, int *n_results) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (steps_per_trial < 2 || (steps_per_trial & 1) || steps_per_trial > kGraphChunk)
+        return fail(h, LSM_EINVAL, "steps_per_trial must be even, 2..1000");
+    if (h->half) return fail(h, LSM_ESTATE, "autotune only between relaxations");
+    if (cap < 0 || (cap > 0 && !results)) return LSM_EINVAL;
+    // the trials advance the dynamics: checkpoint the state and restore it
+    // afterwards, so tuning never changes results
+    size_t snap_n = 0;
+    rc = lsm_save_state(h, nullptr, &snap_n);
+    if (rc) return rc;
+    std::vector<char> snap(snap_n);
+    rc = lsm_save_state(h, snap.data(), &snap_n);
+    if (rc) return rc;
+    struct Cand { int variant, rows, pf; };
+    std::vector<Cand> cands;
+    if (h->dim == 2) {
+        for (int rows : {2, 4, 6, 8, 12, 16, 32})
+            for (int pf : {1, 2}) cands.push_back({LSM_KERNEL_SWEEP, rows, pf});
+    }
+    cands.push_back({LSM_KERNEL_GATHER, 0, 1});
+    const int saved_variant = h->variant, saved_rows = h->sw_rows, saved_pf = h->sw_pf;
+    hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
+    if (!e0 || !e1) return fail(h, LSM_EHIP, "hipEventCreate failed");
+    double best = 1e300;
+    Cand bestc = {saved_variant, saved_rows, saved_pf};
+    int nres = 0;
+    for (const Cand &c : cands) {
+        h->variant = c.variant;
+        if (c.rows) h->sw_rows = c.rows;
+        h->sw_pf = c.pf;
+        hipGraphExec_t exec = nullptr;
+        HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        int cc = h->cur;
+        hipError_t le = hipSuccess;
+        for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s) {
+            StepParams p = make_params(h, cc, cc ^ 1);
+            le = launch_phase(h, p, lsm::kMid, 1 + s);
+            cc ^= 1;
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(h, LSM_EHIP, "autotune capture failed");
+        }
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return fail(h, LSM_EHIP, "autotune instantiate failed");
+        HIPCHK(h, hipGraphLaunch(exec, h->stream));  // warm-up
+        HIPCHK(h, hipEventRecord(e0, h->stream));
+        HIPCHK(h, hipGraphLaunch(exec, h->stream));
+        HIPCHK(h, hipEventRecord(e1, h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        float ms = 0.0f;
+        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
+        (void)hipGraphExecDestroy(exec);
+        const double us = 1e3 * ms / steps_per_trial;
+        if (nres < cap) results[nres] = lsm_tuning{c.variant, c.rows, c.pf, 0, us};
+        ++nres;
+        if (us < best) {
+            best = us;
+            bestc = c;
+        }
+    }
+    h->ev_pool.push_back(e0);
+    h->ev_pool.push_back(e1);
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
+    h->variant = bestc.variant;
+    if (bestc.rows) h->sw_rows = bestc.rows;
+    h->sw_pf = bestc.pf;
+    (void)saved_rows;
+    (void)saved_pf;
+    if (n_results) *n_results = nres;
+    return lsm_load_state(h, snap.data(), snap_n);
+}
+
+int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
+    if (!h || !out) return LSM_EINVAL;
+    *out = lsm_tuning{h->variant, h->sw_rows, h->sw_pf, 0, 0.0};
     return LSM_OK;
 }
 

@@ -68,6 +68,8 @@ struct StepParams {
     // row-sweep decomposition of the 2D lattice: each wavefront owns 62
     // columns of a strip and sw_rows rows, sweeping upward
     int32_t sw_strips, sw_rows, sw_nwork, sw_nblocks;
+    int32_t sw_pf;          // rows prefetched ahead by each wavefront (1..3)
+    int32_t pad2;
 };
 
 // Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.

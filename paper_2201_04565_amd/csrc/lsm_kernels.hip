@@ -252,14 +252,13 @@ __device__ inline void tile_coords(const StepParams &P, int &i, int &j, int &k, 
 // start of an increment, half step otherwise); F is the spring force at the
 // current positions.
 template <int DIM, int PREC, int MODE>
-__device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp,
+__device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, double mass,
                                       typename State<DIM, PREC>::R *uph,
                                       typename State<DIM, PREC>::R *upl,
                                       const typename State<DIM, PREC>::R *F,
                                       typename State<DIM, PREC>::R *w, double *red) {
     using S = State<DIM, PREC>;
     using R = typename S::R;
-    const int pa = flag_phase(fp);
     if (flag_grip(fp) != 0) {
         // clamped: displacement carried over, velocity stays zero
         if constexpr (MODE != kEnd) S::store_u(P.u_out, g, P.nsites, uph, upl);
@@ -276,11 +275,11 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp,
     const R gam = R(P.gamma);
     R acc[DIM];
     if constexpr (PREC == 1) {
-        const R im = R(1.0 / P.mass[pa]);
+        const R im = R(1.0 / mass);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * im;
     } else {
-        const R m = R(P.mass[pa]);
+        const R m = R(mass);
 #pragma unroll
         for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) / m;
     }
@@ -308,7 +307,7 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp,
         for (int c = 0; c < DIM; ++c) w[c] = w[c] + h * acc[c];
         S::store_v(P.v, g, P.nsites, w);
         S::store_v(P.acc, g, P.nsites, acc);
-        const double mm = P.mass[pa];
+        const double mm = mass;
 #pragma unroll
         for (int aa = 0; aa < DIM; ++aa) {
 #pragma unroll
@@ -328,8 +327,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
     using TTy = typename TT<PREC>::type;
 
     __shared__ TTy tt[kMaxTypes];
+    __shared__ double mass_s[LSM_MAX_PHASES];
     __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
     for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    if (threadIdx.x < LSM_MAX_PHASES) mass_s[threadIdx.x] = P.mass[threadIdx.x];
     __syncthreads();
 
     int i, j, k;
@@ -486,7 +487,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
         } else {
             R w[DIM];
             if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
-            integrate_site<DIM, PREC, MODE>(P, g, fp, uph, upl, F, w, red);
+            integrate_site<DIM, PREC, MODE>(P, g, fp, mass_s[pa], uph, upl, F, w, red);
         }
     }
 
@@ -639,23 +640,26 @@ struct SweepRow {
 template <int PREC>
 __device__ inline void load_sweep_row(const StepParams &P, int i, bool col_ok, int jj, bool want_v,
                                       SweepRow<typename State<2, PREC>::R> &r) {
+    // Loads are unconditional from an always-valid site (site 0 when the row
+    // or column is outside the lattice) and masked afterwards, so no branch
+    // joins on a pending load.
     using S = State<2, PREC>;
     using R = typename S::R;
-    if (col_ok && jj >= 0 && jj < P.ny) {
-        const int g = i + P.nx * jj;
-        S::load_u(P.u_in, g, P.nsites, r.uh, r.ul);
-        r.f = P.flags[g];
-        r.m = reinterpret_cast<const uint8_t *>(P.mask)[g];
-        if (want_v) {
-            S::load_v(P.v, g, P.nsites, r.v);
-        } else {
-            r.v[0] = R(0); r.v[1] = R(0);
-        }
-    } else {
-        r.uh[0] = r.uh[1] = r.ul[0] = r.ul[1] = r.v[0] = r.v[1] = R(0);
-        r.f = kVoid;
-        r.m = 0;
+    const bool ok = col_ok && jj >= 0 && jj < P.ny;
+    const int g = ok ? i + P.nx * jj : 0;
+    R uh[2], ul[2], v[2];
+    S::load_u(P.u_in, g, P.nsites, uh, ul);
+    const int f = P.flags[g];
+    const int m = reinterpret_cast<const uint8_t *>(P.mask)[g];
+    if (want_v) S::load_v(P.v, g, P.nsites, v);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        r.uh[c] = ok ? uh[c] : R(0);
+        r.ul[c] = ok ? ul[c] : R(0);
+        r.v[c] = (ok && want_v) ? v[c] : R(0);
     }
+    r.f = ok ? f : int(kVoid);
+    r.m = ok ? m : 0;
 }
 
 // One forward spring of site p towards q (lattice vector (ex, ey)).  Returns
@@ -726,14 +730,16 @@ __device__ inline void spring_stress64(const TypeRec &T, double ex64, double ey6
     red[18] += 0.5 * T.k64 * (r - T.r0_64) * (r - T.r0_64);
 }
 
-template <int PREC, int MODE>
+template <int PREC, int MODE, int PF>
 __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
     using S = State<2, PREC>;
     using R = typename S::R;
     using TTy = typename TT<PREC>::type;
     __shared__ TTy tt[kMaxTypes];
+    __shared__ double mass_s[LSM_MAX_PHASES];
     __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
     for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    if (threadIdx.x < LSM_MAX_PHASES) mass_s[threadIdx.x] = P.mass[threadIdx.x];
     __syncthreads();
 
     double red[MODE == kEnd ? kNumPartials : 1];
@@ -758,52 +764,52 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
         const R half_a = R(0.5) * a;
 
-        SweepRow<R> r0, r1, r2;
-        load_sweep_row<PREC>(P, i, col_ok, jstart, jstart >= j0, r0);
-        load_sweep_row<PREC>(P, i, col_ok, jstart + 1 <= j1 ? jstart + 1 : -1, jstart + 1 >= j0, r1);
         R pUL[2] = {R(0), R(0)}, pUR[2] = {R(0), R(0)};
         int pbrk = 0;
-        for (int j = jstart; j < j1; ++j) {
-            load_sweep_row<PREC>(P, i, col_ok, j + 2 <= j1 ? j + 2 : -1, true, r2);
+        // Row j is computed from rc (row j) and ru (row j + 1) while rn
+        // receives row j + 2; the three buffers rotate roles so that no
+        // register copy forces an early wait on the prefetched row.
+        auto row_step = [&](int j, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
+            load_sweep_row<PREC>(P, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
             const int par = j & 1;
             // neighbour sites: east (this row, next lane), upper-left / upper-right (row above)
             R eh[2], el[2], ulh[2], ull[2], urh[2], url[2];
             int ef, ulf, urf;
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
-                eh[cc] = lane_next(r0.uh[cc]);
-                el[cc] = PREC ? lane_next(r0.ul[cc]) : R(0);
+                eh[cc] = lane_next(rc.uh[cc]);
+                el[cc] = PREC ? lane_next(rc.ul[cc]) : R(0);
             }
-            ef = lane_next(r0.f);
+            ef = lane_next(rc.f);
             if (par == 0) {
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
-                    ulh[cc] = lane_prev(r1.uh[cc]);
-                    ull[cc] = PREC ? lane_prev(r1.ul[cc]) : R(0);
-                    urh[cc] = r1.uh[cc];
-                    url[cc] = r1.ul[cc];
+                    ulh[cc] = lane_prev(ru.uh[cc]);
+                    ull[cc] = PREC ? lane_prev(ru.ul[cc]) : R(0);
+                    urh[cc] = ru.uh[cc];
+                    url[cc] = ru.ul[cc];
                 }
-                ulf = lane_prev(r1.f);
-                urf = r1.f;
+                ulf = lane_prev(ru.f);
+                urf = ru.f;
             } else {
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
-                    ulh[cc] = r1.uh[cc];
-                    ull[cc] = r1.ul[cc];
-                    urh[cc] = lane_next(r1.uh[cc]);
-                    url[cc] = PREC ? lane_next(r1.ul[cc]) : R(0);
+                    ulh[cc] = ru.uh[cc];
+                    ull[cc] = ru.ul[cc];
+                    urh[cc] = lane_next(ru.uh[cc]);
+                    url[cc] = PREC ? lane_next(ru.ul[cc]) : R(0);
                 }
-                ulf = r1.f;
-                urf = lane_next(r1.f);
+                ulf = ru.f;
+                urf = lane_next(ru.f);
             }
             R fe[2], ful[2], fur[2];
             int pe, pul, pur, be, bul, bur, te, tul, tur;
             double me, mul, mur;
-            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 0, a, R(0), a64, 0.0, r0.uh, r0.ul, eh, el, ef,
+            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, eh, el, ef,
                              fe, pe, be, me, te);
-            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 1, -half_a, hy, -0.5 * a64, hy64, r0.uh, r0.ul,
+            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 1, -half_a, hy, -0.5 * a64, hy64, rc.uh, rc.ul,
                              ulh, ull, ulf, ful, pul, bul, mul, tul);
-            fwd_spring<PREC>(tt, P.types, r0.f, r0.m, 2, half_a, hy, 0.5 * a64, hy64, r0.uh, r0.ul,
+            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 2, half_a, hy, 0.5 * a64, hy64, rc.uh, rc.ul,
                              urh, url, urf, fur, pur, bur, mur, tur);
             const int nb = be | (bul << 1) | (bur << 2);
             if (j >= j0) {
@@ -830,14 +836,14 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                     bDR = lane_next(pbrk) & 1;
                     bDL = (pbrk >> 1) & 1;
                 }
-                if (own_lane && r0.f != kVoid) {
+                if (own_lane && rc.f != kVoid) {
                     const int g = i + P.nx * j;
                     R F[2];
 #pragma unroll
                     for (int cc = 0; cc < 2; ++cc)
                         F[cc] = ((((fe[cc] + ful[cc]) + fur[cc]) - gW[cc]) - gDR[cc]) - gDL[cc];
-                    const int newmask = r0.m | nb | (bW << 3) | (bDR << 4) | (bDL << 5);
-                    if (newmask != r0.m) {
+                    const int newmask = rc.m | nb | (bW << 3) | (bDR << 4) | (bDL << 5);
+                    if (newmask != rc.m) {
                         reinterpret_cast<uint8_t *>(P.mask)[g] = uint8_t(newmask);
                         const int brks[3] = {be, bul, bur};
                         const double mgs[3] = {me, mul, mur};
@@ -861,13 +867,24 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                     }
                     if constexpr (MODE == kEnd) {
                         const int mk = newmask;
-                        if (pe && !(mk & 1)) spring_stress64(P.types[te], a64, 0.0, r0.uh, r0.ul, eh, el, red);
+                        if (pe && !(mk & 1)) spring_stress64(P.types[te], a64, 0.0, rc.uh, rc.ul, eh, el, red);
                         if (pul && !(mk & 2))
-                            spring_stress64(P.types[tul], -0.5 * a64, hy64, r0.uh, r0.ul, ulh, ull, red);
+                            spring_stress64(P.types[tul], -0.5 * a64, hy64, rc.uh, rc.ul, ulh, ull, red);
                         if (pur && !(mk & 4))
-                            spring_stress64(P.types[tur], 0.5 * a64, hy64, r0.uh, r0.ul, urh, url, red);
+                            spring_stress64(P.types[tur], 0.5 * a64, hy64, rc.uh, rc.ul, urh, url, red);
                     }
-                    integrate_site<2, PREC, MODE>(P, g, uint8_t(r0.f), r0.uh, r0.ul, F, r0.v, red);
+                    integrate_site<2, PREC, MODE>(P, g, uint8_t(rc.f), mass_s[flag_phase(rc.f)], rc.uh,
+                                                  rc.ul, F, rc.v, red);
+                }
+                if constexpr (MODE == kEnd) {
+                    // one partial per (row, strip): the reduction order does not
+                    // depend on how rows are chunked over wavefronts
+#pragma unroll
+                    for (int v = 0; v < kNumPartials; ++v) {
+                        const double t = wave_sum(red[v]);
+                        if (lane == 0) P.partials[(int64_t(j) * P.sw_strips + s) * kNumPartials + v] = t;
+                        red[v] = 0.0;
+                    }
                 }
             }
 #pragma unroll
@@ -876,17 +893,25 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                 pUR[cc] = fur[cc];
             }
             pbrk = (nb >> 1) & 3;
-            r0 = r1;
-            r1 = r2;
-        }
-    }
-    if constexpr (MODE == kEnd) {
-        block_sum(red, red_lds);
-        if (threadIdx.x == 0) {
+        };
+
+        // K rotating row buffers: row j lives in B[(j - jstart) % K]; the
+        // step for row j prefetches row j + PF + 1.
+        constexpr int K = PF + 2;
+        SweepRow<R> B[K];
 #pragma unroll
-            for (int v = 0; v < kNumPartials; ++v) P.partials[int64_t(blockIdx.x) * kNumPartials + v] = red[v];
+        for (int t = 0; t <= PF; ++t) {
+            const int jj = jstart + t;
+            load_sweep_row<PREC>(P, i, col_ok, jj <= j1 ? jj : -1, jj >= j0, B[t]);
+        }
+        for (int j = jstart; j < j1; j += K) {
+#pragma unroll
+            for (int t = 0; t < K; ++t) {
+                if (j + t < j1) row_step(j + t, B[t], B[(t + 1) % K], B[(t + PF + 1) % K]);
+            }
         }
     }
+    (void)red_lds;
 }
 
 template <int DIM, int PREC>
@@ -901,15 +926,23 @@ hipError_t launch_step_t(const StepParams &p, int mode, hipStream_t s, int step_
     return hipGetLastError();
 }
 
-template <int PREC>
-hipError_t launch_sweep_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
+template <int PREC, int PF>
+hipError_t launch_sweep_pf(const StepParams &p, int mode, hipStream_t s, int step_local) {
     const dim3 grid(p.sw_nblocks), block(kBlock);
     switch (mode) {
-        case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart>), grid, block, 0, s, p, step_local); break;
-        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid>), grid, block, 0, s, p, step_local); break;
-        default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd>), grid, block, 0, s, p, step_local); break;
+        case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart, PF>), grid, block, 0, s, p, step_local); break;
+        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid, PF>), grid, block, 0, s, p, step_local); break;
+        default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd, PF>), grid, block, 0, s, p, step_local); break;
     }
     return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t launch_sweep_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
+    // the prefetch depth only matters for the interior steps
+    if (mode != kMid || p.sw_pf <= 1) return launch_sweep_pf<PREC, 1>(p, mode, s, step_local);
+    if (p.sw_pf == 2) return launch_sweep_pf<PREC, 2>(p, mode, s, step_local);
+    return launch_sweep_pf<PREC, 3>(p, mode, s, step_local);
 }
 
 }  // namespace

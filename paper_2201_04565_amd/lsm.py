@@ -29,7 +29,8 @@ EXPORTS = (
     "lsm_n_broken", "lsm_get_springs", "lsm_get_reference", "lsm_get_positions",
     "lsm_get_velocities", "lsm_set_positions", "lsm_set_velocities", "lsm_eval_forces",
     "lsm_save_state", "lsm_load_state", "lsm_set_timing", "lsm_read_timing", "lsm_step_bytes",
-    "lsm_set_launch", "lsm_last_error", "lsm_strerror",
+    "lsm_set_launch", "lsm_set_prefetch", "lsm_autotune", "lsm_get_launch", "lsm_last_error",
+    "lsm_strerror",
 )
 
 
@@ -45,6 +46,11 @@ class Record(C.Structure):
     _fields_ = [("eps", C.c_double), ("sigma", C.c_double * 9), ("ke", C.c_double),
                 ("pe", C.c_double), ("n_broken", C.c_int64), ("increment", C.c_int32),
                 ("step", C.c_int32), ("status", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("rows_per_wave", C.c_int32), ("prefetch", C.c_int32),
+                ("reserved", C.c_int32), ("us_per_step", C.c_double)]
 
 
 class Event(C.Structure):
@@ -97,6 +103,9 @@ def load_library():
     L.lsm_read_timing.argtypes = [vp, P(dbl), P(i64)]
     L.lsm_step_bytes.argtypes = [vp, P(i64)]
     L.lsm_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.lsm_set_prefetch.argtypes = [vp, C.c_int]
+    L.lsm_autotune.argtypes = [vp, C.c_int, vp, C.c_int, P(C.c_int)]
+    L.lsm_get_launch.argtypes = [vp, P(Tuning)]
     L.lsm_last_error.argtypes = [vp]
     L.lsm_last_error.restype = C.c_char_p
     L.lsm_strerror.argtypes = [C.c_int]
@@ -311,6 +320,25 @@ class Lattice:
     def set_launch(self, variant="auto", rows_per_wave=0):
         v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
+
+    def set_prefetch(self, rows_ahead):
+        self._check(self._L.lsm_set_prefetch(self._h, int(rows_ahead)))
+
+    def autotune(self, steps_per_trial=100):
+        """Times the candidate launches on the lattice at rest and keeps the
+        fastest; returns [(variant, rows_per_wave, prefetch, us_per_step)]."""
+        buf = (Tuning * 64)()
+        n = C.c_int()
+        self._check(self._L.lsm_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
+        names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep"}
+        return [(names.get(t.variant, "auto"), t.rows_per_wave, t.prefetch, t.us_per_step)
+                for t in buf[:n.value]]
+
+    def launch(self):
+        t = Tuning()
+        self._check(self._L.lsm_get_launch(self._h, C.byref(t)))
+        names = {KERNEL_AUTO: "auto", KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep"}
+        return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -325,3 +325,24 @@ def test_gather_and_sweep_agree(lsm):
     (ra, xa), (rb, xb) = out
     assert np.max(np.abs(xa - xb)) < 1e-12
     assert np.allclose(ra["sigma"], rb["sigma"], rtol=1e-10, atol=1e-16)
+
+
+def test_autotune_keeps_results(lsm):
+    img = inputs.brick_and_mortar(190, 48, seed=6)
+    wl = inputs.WORKLOADS["c2"]
+    say("autotune brick 190x48 fp32k")
+    a = gpu_for(lsm, img, wl, "fp32k")
+    b = gpu_for(lsm, img, wl, "fp32k")
+    for x in (a, b):
+        x.apply_increment(0.003)
+        x.relax(200)
+    res = a.autotune(20)
+    assert len(res) > 5 and all(r[3] > 0 for r in res)
+    best = min(res, key=lambda r: r[3])
+    got = a.launch()
+    assert (got["variant"], got["rows_per_wave"], got["prefetch"])[0] == best[0]
+    assert a.save_state() == b.save_state()
+    for x in (a, b):
+        x.apply_increment(0.006)
+        x.relax(300)
+    assert a.save_state() == b.save_state()
