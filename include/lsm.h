@@ -250,6 +250,56 @@ int lsm_get_launch(const lsm_handle *h, lsm_tuning *out);
 const char *lsm_last_error(const lsm_handle *h);
 const char *lsm_strerror(int status);
 
+/* ---------------------------------------------------------------------
+ * Batches of independent 2D specimens, each taken to failure.
+ *
+ * The paper motivates the code by high-throughput data generation for
+ * machine learning (Abstract; Section 4): many specimens run the same
+ * displacement-controlled test.  A batch shares one configuration and
+ * loading history; every step is one launch over all specimens still
+ * running.  Specimen s stops after the first increment past its stress peak
+ * whose sigma_xx is below drop_fraction * peak, a non-finite state, or
+ * max_inc increments.  The modulus is the least-squares slope through the
+ * origin of sigma_xx against strain over the increments that ended with no
+ * broken spring (at least the first one); the strength is the peak.
+ * Device memory and stream ownership follow the single-lattice rules.
+ * --------------------------------------------------------------------- */
+typedef struct lsm_batch lsm_batch;
+
+typedef struct {
+    double drop_fraction; /* failure threshold relative to the peak (0.01) */
+} lsm_fail_rule;
+
+/* imgs[s]: host image of specimen s (x fastest); dims[3 s .. 3 s + 2] =
+ * (nx, ny, 1).  2D triangular lattices only (LSM_EINVAL otherwise).      */
+int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *imgs,
+                     const int64_t *dims, lsm_batch **out);
+void lsm_batch_destroy(lsm_batch *b);
+const char *lsm_batch_last_error(const lsm_batch *b);
+int lsm_batch_counts(const lsm_batch *b, int64_t *n_particles, int64_t *n_springs);
+int lsm_batch_workspace_bytes(const lsm_batch *b, size_t *bytes);
+int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream);
+
+/* Row chunk and prefetch depth of the batched sweep (before the run;
+ * results do not depend on them).                                         */
+int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch);
+
+/* Runs every specimen to failure (rule may be NULL for drop 0.01).  Once
+ * per batch; synchronises after every increment to apply the rule.        */
+int lsm_batch_run(lsm_batch *b, double d_eps, int64_t steps_per_inc, int32_t max_inc,
+                  const lsm_fail_rule *rule);
+
+/* Results: sigma_xx (n x max_inc, NaN after the specimen stopped),
+ * increments run, modulus, strength and broken springs per specimen; any
+ * output pointer may be NULL.                                             */
+int lsm_batch_read(lsm_batch *b, int32_t max_inc, double *sigma_xx, int32_t *n_inc,
+                   double *modulus, double *strength, int64_t *n_broken);
+
+/* HIP-event timing of the step graphs (as lsm_set_timing); site_steps is
+ * the sum over timed steps of the particles of the specimens running.     */
+int lsm_batch_set_timing(lsm_batch *b, int enable);
+int lsm_batch_read_timing(lsm_batch *b, double *ms, int64_t *steps, double *site_steps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,8 @@ def lib():
         L.orc_n_events.restype = i64
         L.orc_get_events.argtypes = [vp, vp, vp, vp, vp]
         L.orc_get_clock.argtypes = [vp, P(i32), P(i32), P(dbl)]
+        L.orc_run_to_failure.argtypes = [vp, dbl, i64, i32, dbl, vp, vp, vp, P(i32), P(dbl),
+                                         P(dbl)]
         _lib = L
     return _lib
 
@@ -177,6 +179,20 @@ class Net:
         rc = lib().orc_run(self._h, int(n_inc), int(steps_per_inc), float(d_eps), recs)
         out = [record_to_dict(r) for r in recs]
         return rc, out
+
+    def run_to_failure(self, d_eps, steps, max_inc, drop=0.01) -> dict:
+        """Uniaxial test to failure; see orc_run_to_failure."""
+        sxx = np.full(max_inc, np.nan)
+        eps = np.full(max_inc, np.nan)
+        nb = np.zeros(max_inc, dtype=np.int64)
+        n = C.c_int32()
+        mod, st = C.c_double(), C.c_double()
+        rc = lib().orc_run_to_failure(self._h, float(d_eps), int(steps), int(max_inc),
+                                      float(drop), _ptr(sxx), _ptr(eps), _ptr(nb), C.byref(n),
+                                      C.byref(mod), C.byref(st))
+        k = n.value
+        return dict(status=rc, n_inc=k, sigma_xx=sxx[:k], eps=eps[:k], n_broken=nb[:k],
+                    modulus=mod.value, strength=st.value)
 
     def forces(self, commit=False) -> np.ndarray:
         F = np.zeros((self.n, self.dim))

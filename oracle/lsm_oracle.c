@@ -575,3 +575,50 @@ void orc_get_clock(const orc_net *N, int32_t *inc, int32_t *step, double *eps)
     *step = N->step;
     *eps = N->eps;
 }
+
+/* ------------------------------------------------ run to failure (derived) */
+
+/* Uniaxial test to failure: increments of d_eps, each relaxed for steps
+ * steps, until the first increment after the stress peak whose sigma_xx
+ * falls below drop * peak, a non-finite state, or max_inc increments.
+ * Returns per-increment sigma_xx and broken counts, the number of
+ * increments run, the strength (peak sigma_xx) and the modulus: the least
+ * squares slope through the origin of sigma_xx against strain over the
+ * increments that ended with no broken spring (at least the first one). */
+int orc_run_to_failure(orc_net *N, double d_eps, int64_t steps, int32_t max_inc, double drop,
+                       double *sxx, double *eps_out, int64_t *nbroken, int32_t *n_inc,
+                       double *modulus, double *strength)
+{
+    double peak = -INFINITY;
+    int32_t peak_inc = 0, n = 0;
+    int status = ORC_OK;
+    orc_record R;
+    for (int32_t it = 1; it <= max_inc; ++it) {
+        int rc = orc_apply_increment(N, d_eps);
+        if (rc == ORC_OK) rc = orc_relax(N, steps);
+        if (rc != ORC_OK) return rc;
+        status = orc_record_state(N, &R);
+        sxx[it - 1] = R.sigma[0];
+        eps_out[it - 1] = R.eps;
+        nbroken[it - 1] = R.n_broken;
+        n = it;
+        if (status != ORC_OK) break;
+        if (R.sigma[0] > peak) {
+            peak = R.sigma[0];
+            peak_inc = it;
+        }
+        if (it > peak_inc && R.sigma[0] < drop * peak) break;
+    }
+    *n_inc = n;
+    *strength = peak;
+    int32_t k = 0;
+    while (k < n && nbroken[k] == 0) ++k;
+    if (k == 0) k = 1;
+    double num = 0.0, den = 0.0;
+    for (int32_t i = 0; i < k && i < n; ++i) {
+        num += eps_out[i] * sxx[i];
+        den += eps_out[i] * eps_out[i];
+    }
+    *modulus = den > 0.0 ? num / den : 0.0;
+    return status;
+}

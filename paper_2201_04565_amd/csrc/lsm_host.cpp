@@ -1051,3 +1051,556 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes) {
 }
 
 }  // extern "C"
+
+// =====================================================================
+// Batch of independent 2D specimens (uniaxial tests to failure).
+//
+// All specimens share one configuration and one loading history; their
+// sites are stored back to back in one structure-of-arrays state.  Every
+// step is one launch of the row-sweep kernel over the work items (strip x
+// row chunk) of all specimens still running, replayed from HIP graphs.
+// After each increment the per-specimen records are read back, the failure
+// rule is applied, and failed specimens leave the active work list.
+// =====================================================================
+
+using lsm::SpecDesc;
+using lsm::SweepItem;
+
+struct lsm_batch {
+    lsm_config cfg{};
+    int prec = 0;
+    int64_t nspec = 0, nsites = 0, ntot = 0, mtot = 0;
+    std::vector<int32_t> nx, ny;
+    std::vector<int64_t> base, npart, nspring;
+    std::vector<uint8_t> flags;
+    TypeRec types[lsm::kMaxTypes]{};
+    std::vector<SpecDesc> specs;
+    int64_t npartials = 0;
+    int sw_rows = 4, sw_pf = 1;
+    std::vector<SweepItem> items;  // active work items
+    std::vector<uint8_t> active;
+    // device
+    bool bound = false;
+    hipStream_t stream = nullptr;
+    Ctl *d_ctl = nullptr;
+    DevRecord *d_recs = nullptr;
+    TypeRec *d_types = nullptr;
+    uint8_t *d_flags = nullptr, *d_mask = nullptr;
+    void *d_U[2] = {nullptr, nullptr};
+    void *d_V = nullptr, *d_A = nullptr;
+    double *d_partials = nullptr;
+    SweepItem *d_items = nullptr;
+    int32_t *d_nitems = nullptr;
+    SpecDesc *d_specs = nullptr;
+    uint32_t *d_spec_broken = nullptr;
+    size_t max_items = 0;
+    int cur = 0;
+    int32_t inc = 0;
+    double eps = 0.0;
+    bool ran = false;
+    int capacity = 0;  // work items the captured graphs were sized for
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
+    std::vector<hipEvent_t> ev_pool;
+    int64_t timed_steps = 0;
+    double timed_site_steps = 0.0;
+    // results
+    std::vector<std::vector<double>> sxx;
+    std::vector<std::vector<int64_t>> nbk;
+    std::vector<int32_t> n_inc, status;
+    std::vector<double> modulus, strength;
+    std::string err;
+};
+
+namespace {
+
+int bfail(lsm_batch *b, int code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return bfail((b), LSM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int64_t batch_strips(int32_t nx) { return (nx + lsm::kSweepCols - 1) / lsm::kSweepCols; }
+
+void batch_items_for(const lsm_batch *b, int64_t s, std::vector<SweepItem> &out) {
+    const int32_t nx = b->nx[s], ny = b->ny[s];
+    const int32_t strips = int32_t(batch_strips(nx));
+    for (int32_t j0 = 0; j0 < ny; j0 += b->sw_rows)
+        for (int32_t st = 0; st < strips; ++st) {
+            SweepItem it{};
+            it.base = int32_t(b->base[s]);
+            it.nx = nx;
+            it.ny = ny;
+            it.i0 = st * lsm::kSweepCols - 1;
+            it.j0 = j0;
+            it.j1 = std::min(j0 + b->sw_rows, ny);
+            it.strip = st;
+            it.strips = strips;
+            it.pbase = b->specs[s].pbase;
+            it.spec = int32_t(s);
+            out.push_back(it);
+        }
+}
+
+int upload_items(lsm_batch *b) {
+    b->items.clear();
+    for (int64_t s = 0; s < b->nspec; ++s)
+        if (b->active[s]) batch_items_for(b, s, b->items);
+    const int32_t n = int32_t(b->items.size());
+    if (n) BHIPCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), size_t(n) * sizeof(SweepItem),
+                                     hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_nitems, &n, sizeof(n), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));  // n lives on this stack frame
+    return LSM_OK;
+}
+
+StepParams batch_params(const lsm_batch *b, int in_buf, int out_buf) {
+    StepParams p{};
+    p.nphase = b->cfg.nphase;
+    p.nsites = b->nsites;
+    p.a = b->cfg.a;
+    p.dt = b->cfg.dt;
+    p.gamma = b->cfg.damping;
+    for (int i = 0; i < LSM_MAX_PHASES; ++i) p.mass[i] = i < b->cfg.nphase ? b->cfg.mass[i] : 1.0;
+    p.flags = b->d_flags;
+    p.mask = b->d_mask;
+    p.u_in = b->d_U[in_buf];
+    p.u_out = b->d_U[out_buf];
+    p.v = b->d_V;
+    p.acc = b->d_A;
+    p.types = b->d_types;
+    p.ctl = b->d_ctl;
+    p.partials = b->d_partials;
+    p.commit = 1;
+    p.sw_rows = b->sw_rows;
+    p.sw_pf = b->sw_pf;
+    p.items = b->d_items;
+    p.n_items = b->d_nitems;
+    p.spec_broken = b->d_spec_broken;
+    return p;
+}
+
+void drop_batch_graphs(lsm_batch *b) {
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+int batch_mid_chunk(lsm_batch *b, int chunk, int local) {
+    const auto key = std::make_tuple(chunk, b->cur, local, b->capacity);
+    hipGraphExec_t exec = nullptr;
+    auto itg = b->graphs.find(key);
+    if (itg != b->graphs.end()) {
+        exec = itg->second;
+    } else {
+        BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int c = b->cur;
+        hipError_t le = hipSuccess;
+        for (int s = 0; s < chunk && le == hipSuccess; ++s) {
+            StepParams p = batch_params(b, c, c ^ 1);
+            le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, local + s, b->capacity);
+            c ^= 1;
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(b->stream, &graph);
+        if (le != hipSuccess || ce != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return bfail(b, LSM_EHIP, "batch graph capture failed");
+        }
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) return bfail(b, LSM_EHIP, "batch graph instantiate failed");
+        b->graphs[key] = exec;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (b->timing) {
+        auto get = [&]() -> hipEvent_t {
+            if (!b->ev_pool.empty()) {
+                hipEvent_t e = b->ev_pool.back();
+                b->ev_pool.pop_back();
+                return e;
+            }
+            hipEvent_t e = nullptr;
+            return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+        };
+        e0 = get();
+        e1 = get();
+        if (!e0 || !e1) return bfail(b, LSM_EHIP, "hipEventCreate failed");
+        BHIPCHK(b, hipEventRecord(e0, b->stream));
+    }
+    BHIPCHK(b, hipGraphLaunch(exec, b->stream));
+    if (b->timing) {
+        BHIPCHK(b, hipEventRecord(e1, b->stream));
+        b->tev.emplace_back(e0, e1);
+        b->timed_steps += chunk;
+        double sites = 0.0;
+        for (int64_t s = 0; s < b->nspec; ++s)
+            if (b->active[s]) sites += double(b->npart[s]);
+        b->timed_site_steps += sites * chunk;
+    }
+    b->cur ^= (chunk & 1);
+    return LSM_OK;
+}
+
+// Least-squares slope through the origin over the increments that ended
+// with no broken spring (at least the first), and the peak stress.
+void batch_derived(const std::vector<double> &sx, const std::vector<int64_t> &nb, double d_eps,
+                   double *mod, double *str) {
+    const size_t n = sx.size();
+    double peak = -INFINITY;
+    for (double v : sx) peak = std::max(peak, v);
+    size_t k = 0;
+    while (k < n && nb[k] == 0) ++k;
+    if (k == 0) k = 1;
+    double num = 0.0, den = 0.0;
+    double e = 0.0;
+    for (size_t i = 0; i < k && i < n; ++i) {
+        e += d_eps;
+        num += e * sx[i];
+        den += e * e;
+    }
+    *mod = den > 0.0 ? num / den : 0.0;
+    *str = n ? peak : 0.0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *imgs, const int64_t *dims,
+                     lsm_batch **out) {
+    if (!cfg || !out || n < 1 || !imgs || !dims) return LSM_EINVAL;
+    *out = nullptr;
+    if (cfg->lattice != LSM_LATTICE_TRI2D) return LSM_EINVAL;
+    // validate the configuration through the single-lattice constructor
+    lsm_handle *probe = nullptr;
+    int rc = lsm_create(cfg, &probe);
+    if (rc) return rc;
+    lsm_batch *b = new (std::nothrow) lsm_batch();
+    if (!b) {
+        lsm_destroy(probe);
+        return LSM_ENOMEM;
+    }
+    b->cfg = *cfg;
+    b->prec = cfg->precision == LSM_FP32_KAHAN ? 1 : 0;
+    std::memcpy(b->types, probe->types, sizeof(b->types));
+    lsm_destroy(probe);
+    b->nspec = n;
+    b->nx.resize(n);
+    b->ny.resize(n);
+    b->base.resize(n);
+    b->npart.resize(n);
+    b->nspring.resize(n);
+    b->specs.resize(n);
+    int64_t off = 0, pb = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t sx = dims[3 * s], sy = dims[3 * s + 1], sz = dims[3 * s + 2];
+        if (sx < 1 || sy < 1 || sz != 1 || !imgs[s]) {
+            delete b;
+            return LSM_EINVAL;
+        }
+        b->nx[s] = int32_t(sx);
+        b->ny[s] = int32_t(sy);
+        b->base[s] = off;
+        off += sx * sy;
+        if (off >= (int64_t(1) << 31) - 1) {
+            delete b;
+            return LSM_EINVAL;
+        }
+        b->specs[s].pbase = int32_t(pb);
+        b->specs[s].npart = int32_t(sy * batch_strips(int32_t(sx)));
+        pb += b->specs[s].npart;
+    }
+    b->nsites = off;
+    b->npartials = pb;
+    b->flags.assign(size_t(off), 0);
+    const int vv = cfg->void_value;
+    int64_t mtot = 0, ntot = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        const int64_t sx = b->nx[s], sy = b->ny[s];
+        const uint8_t *img = imgs[s];
+        uint8_t *fl = b->flags.data() + b->base[s];
+        int64_t cnt = 0;
+        for (int64_t g = 0; g < sx * sy; ++g) {
+            const int v = img[g];
+            if (vv >= 0 && v == vv) {
+                fl[g] = lsm::kVoid;
+                continue;
+            }
+            if (v >= cfg->nphase) {
+                delete b;
+                return LSM_EINVAL;
+            }
+            const int64_t i = g % sx;
+            const int grip = (i == 0) ? 1 : (i == sx - 1 ? 2 : 0);
+            fl[g] = uint8_t(v | (grip << 4));
+            ++cnt;
+        }
+        // forward springs (east, upper-left, upper-right) to non-void sites
+        int64_t ms = 0;
+        for (int64_t j = 0; j < sy; ++j)
+            for (int64_t i = 0; i < sx; ++i) {
+                if (fl[i + sx * j] == lsm::kVoid) continue;
+                const int *o[3] = {kFwd2Even[0], (j & 1) ? kFwd2Odd[1] : kFwd2Even[1],
+                                   (j & 1) ? kFwd2Odd[2] : kFwd2Even[2]};
+                for (int d = 0; d < 3; ++d) {
+                    const int64_t qi = i + o[d][0], qj = j + o[d][1];
+                    if (qi < 0 || qi >= sx || qj < 0 || qj >= sy) continue;
+                    if (fl[qi + sx * qj] == lsm::kVoid) continue;
+                    ++ms;
+                }
+            }
+        b->npart[s] = cnt;
+        b->nspring[s] = ms;
+        b->specs[s].omega = cnt > 0 ? double(cnt) * kHalfSqrt3 * cfg->a * cfg->a : 1.0;
+        ntot += cnt;
+        mtot += ms;
+    }
+    b->ntot = ntot;
+    b->mtot = mtot;
+    b->active.assign(size_t(n), 1);
+    std::vector<SweepItem> tmp;
+    for (int64_t s = 0; s < n; ++s) batch_items_for(b, s, tmp);
+    b->max_items = tmp.size();
+    *out = b;
+    return LSM_OK;
+}
+
+void lsm_batch_destroy(lsm_batch *b) {
+    if (!b) return;
+    if (b->bound) (void)hipStreamSynchronize(b->stream);
+    drop_batch_graphs(b);
+    for (auto &pr : b->tev) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : b->ev_pool) (void)hipEventDestroy(e);
+    delete b;
+}
+
+const char *lsm_batch_last_error(const lsm_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+int lsm_batch_counts(const lsm_batch *b, int64_t *n_particles, int64_t *n_springs) {
+    if (!b || !n_particles || !n_springs) return LSM_EINVAL;
+    *n_particles = b->ntot;
+    *n_springs = b->mtot;
+    return LSM_OK;
+}
+
+static size_t batch_layout(const lsm_batch *b, size_t *off) {
+    const size_t ns = size_t(b->nsites);
+    const size_t rb = b->prec ? 4 : 8;
+    const size_t sizes[13] = {
+        sizeof(Ctl),
+        sizeof(DevRecord) * size_t(b->nspec),
+        sizeof(TypeRec) * lsm::kMaxTypes,
+        ns,                                   // flags
+        ns,                                   // mask
+        ns * 16,                              // U0
+        ns * 16,                              // U1
+        ns * 2 * rb,                          // V
+        ns * 2 * rb,                          // A
+        size_t(b->npartials) * lsm::kNumPartials * 8,
+        std::max<size_t>(b->max_items, 1) * sizeof(SweepItem),
+        sizeof(int32_t),
+        size_t(b->nspec) * (sizeof(SpecDesc) + sizeof(uint32_t)),
+    };
+    size_t o = 0;
+    for (int i = 0; i < 13; ++i) {
+        off[i] = o;
+        o += align256(sizes[i]);
+    }
+    return o;
+}
+
+int lsm_batch_workspace_bytes(const lsm_batch *b, size_t *bytes) {
+    if (!b || !bytes) return LSM_EINVAL;
+    size_t off[13];
+    *bytes = batch_layout(b, off);
+    return LSM_OK;
+}
+
+int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream) {
+    if (!b || !dptr) return LSM_EINVAL;
+    if (b->bound) return bfail(b, LSM_ESTATE, "already bound");
+    if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return bfail(b, LSM_EINVAL, "workspace must be 256-byte aligned");
+    size_t off[13];
+    const size_t need = batch_layout(b, off);
+    if (bytes < need) return bfail(b, LSM_ENOMEM, "workspace too small");
+    char *w = static_cast<char *>(dptr);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->d_ctl = reinterpret_cast<Ctl *>(w + off[0]);
+    b->d_recs = reinterpret_cast<DevRecord *>(w + off[1]);
+    b->d_types = reinterpret_cast<TypeRec *>(w + off[2]);
+    b->d_flags = reinterpret_cast<uint8_t *>(w + off[3]);
+    b->d_mask = reinterpret_cast<uint8_t *>(w + off[4]);
+    b->d_U[0] = w + off[5];
+    b->d_U[1] = w + off[6];
+    b->d_V = w + off[7];
+    b->d_A = w + off[8];
+    b->d_partials = reinterpret_cast<double *>(w + off[9]);
+    b->d_items = reinterpret_cast<SweepItem *>(w + off[10]);
+    b->d_nitems = reinterpret_cast<int32_t *>(w + off[11]);
+    b->d_specs = reinterpret_cast<SpecDesc *>(w + off[12]);
+    b->d_spec_broken = reinterpret_cast<uint32_t *>(w + off[12] + size_t(b->nspec) * sizeof(SpecDesc));
+    BHIPCHK(b, hipMemsetAsync(w, 0, need, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_types, b->types, sizeof(b->types), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_flags, b->flags.data(), b->flags.size(), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_specs, b->specs.data(), b->specs.size() * sizeof(SpecDesc),
+                              hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    b->bound = true;
+    return upload_items(b);
+}
+
+int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch) {
+    if (!b) return LSM_EINVAL;
+    if (b->ran) return bfail(b, LSM_ESTATE, "set the launch before running");
+    if (rows_per_wave < kMinSweepRows || rows_per_wave > kMaxSweepRows || prefetch < 1 || prefetch > 3)
+        return bfail(b, LSM_EINVAL, "launch out of range");
+    b->sw_rows = rows_per_wave;
+    b->sw_pf = prefetch;
+    drop_batch_graphs(b);
+    std::vector<SweepItem> tmp;
+    for (int64_t s = 0; s < b->nspec; ++s) batch_items_for(b, s, tmp);
+    if (tmp.size() > b->max_items) {
+        // more items than the workspace was sized for: only shapes with at
+        // most as many items are accepted after binding
+        if (b->bound) return bfail(b, LSM_EINVAL, "rows_per_wave too small for the bound workspace");
+        b->max_items = tmp.size();
+    }
+    return b->bound ? upload_items(b) : LSM_OK;
+}
+
+int lsm_batch_run(lsm_batch *b, double d_eps, int64_t steps_per_inc, int32_t max_inc,
+                  const lsm_fail_rule *rule) {
+    if (!b) return LSM_EINVAL;
+    if (!b->bound) return bfail(b, LSM_ESTATE, "bind the batch first");
+    if (b->ran) return bfail(b, LSM_ESTATE, "a batch runs once");
+    if (!std::isfinite(d_eps) || steps_per_inc < 1 || steps_per_inc > (int64_t(1) << 30) || max_inc < 1)
+        return bfail(b, LSM_EINVAL, "bad run arguments");
+    const double drop = rule ? rule->drop_fraction : 0.01;
+    b->ran = true;
+    const int64_t n = b->nspec;
+    b->sxx.assign(size_t(n), {});
+    b->nbk.assign(size_t(n), {});
+    b->n_inc.assign(size_t(n), 0);
+    b->status.assign(size_t(n), LSM_OK);
+    b->modulus.assign(size_t(n), 0.0);
+    b->strength.assign(size_t(n), 0.0);
+    std::vector<double> peak(size_t(n), -INFINITY);
+    std::vector<int32_t> peak_inc(size_t(n), 0);
+    std::vector<DevRecord> recs(static_cast<size_t>(n));
+    int rc = upload_items(b);
+    if (rc) return rc;
+    b->capacity = int(b->items.size());
+    for (int32_t it = 1; it <= max_inc && !b->items.empty(); ++it) {
+        const double eps_new = b->eps + d_eps;
+        const int nitems = int(b->items.size());
+        if (nitems * 2 < b->capacity) {  // shrink the launch when half the work has retired
+            drop_batch_graphs(b);
+            b->capacity = nitems;
+        }
+        StepParams p = batch_params(b, b->cur, b->cur ^ 1);
+        BHIPCHK(b, lsm::launch_increment_batch(p, b->prec, b->stream, eps_new, d_eps, it,
+                                               b->cfg.predictor == LSM_PRED_AFFINE, b->capacity));
+        BHIPCHK(b, lsm::launch_sweep2d_batch(p, b->prec, lsm::kStart, b->stream, 0, b->capacity));
+        b->cur ^= 1;
+        int64_t rem = steps_per_inc - 1;
+        int local = 1;
+        while (rem > 0) {
+            const int chunk = int(std::min<int64_t>(rem, kGraphChunk));
+            rc = batch_mid_chunk(b, chunk, local);
+            if (rc) return rc;
+            rem -= chunk;
+            local += chunk;
+        }
+        StepParams pe = batch_params(b, b->cur, b->cur);
+        BHIPCHK(b, lsm::launch_sweep2d_batch(pe, b->prec, lsm::kEnd, b->stream, int(steps_per_inc), b->capacity));
+        BHIPCHK(b, lsm::launch_finalize_batch(pe, 2, b->stream, b->d_recs, b->d_specs, int(n), int(steps_per_inc)));
+        BHIPCHK(b, hipMemcpyAsync(recs.data(), b->d_recs, size_t(n) * sizeof(DevRecord), hipMemcpyDeviceToHost,
+                                  b->stream));
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        b->eps = eps_new;
+        b->inc = it;
+        bool retired = false;
+        for (int64_t s = 0; s < n; ++s) {
+            if (!b->active[s]) continue;
+            const DevRecord &r = recs[s];
+            b->sxx[s].push_back(r.sigma[0]);
+            b->nbk[s].push_back(r.n_broken);
+            b->n_inc[s] = it;
+            bool done = false;
+            if (r.status != LSM_OK) {
+                b->status[s] = LSM_EUNSTABLE;
+                done = true;
+            } else {
+                if (r.sigma[0] > peak[s]) {
+                    peak[s] = r.sigma[0];
+                    peak_inc[s] = it;
+                }
+                if (it > peak_inc[s] && r.sigma[0] < drop * peak[s]) done = true;
+            }
+            if (done) {
+                b->active[s] = 0;
+                retired = true;
+            }
+        }
+        if (retired) {
+            rc = upload_items(b);
+            if (rc) return rc;
+        }
+    }
+    for (int64_t s = 0; s < n; ++s) batch_derived(b->sxx[s], b->nbk[s], d_eps, &b->modulus[s], &b->strength[s]);
+    return LSM_OK;
+}
+
+int lsm_batch_read(lsm_batch *b, int32_t max_inc, double *sigma_xx, int32_t *n_inc, double *modulus,
+                   double *strength, int64_t *n_broken) {
+    if (!b || max_inc < 1) return LSM_EINVAL;
+    if (!b->ran) return bfail(b, LSM_ESTATE, "run the batch first");
+    for (int64_t s = 0; s < b->nspec; ++s) {
+        if (sigma_xx)
+            for (int32_t k = 0; k < max_inc; ++k)
+                sigma_xx[s * max_inc + k] = k < int32_t(b->sxx[s].size()) ? b->sxx[s][k] : NAN;
+        if (n_inc) n_inc[s] = b->n_inc[s];
+        if (modulus) modulus[s] = b->modulus[s];
+        if (strength) strength[s] = b->strength[s];
+        if (n_broken) n_broken[s] = b->nbk[s].empty() ? 0 : b->nbk[s].back();
+    }
+    return LSM_OK;
+}
+
+int lsm_batch_set_timing(lsm_batch *b, int enable) {
+    if (!b) return LSM_EINVAL;
+    b->timing = enable != 0;
+    return LSM_OK;
+}
+
+int lsm_batch_read_timing(lsm_batch *b, double *ms, int64_t *steps, double *site_steps) {
+    if (!b || !ms || !steps) return LSM_EINVAL;
+    if (b->bound) BHIPCHK(b, hipStreamSynchronize(b->stream));
+    double tot = 0.0;
+    for (auto &pr : b->tev) {
+        float t = 0.0f;
+        BHIPCHK(b, hipEventElapsedTime(&t, pr.first, pr.second));
+        tot += t;
+        b->ev_pool.push_back(pr.first);
+        b->ev_pool.push_back(pr.second);
+    }
+    b->tev.clear();
+    *ms = tot;
+    *steps = b->timed_steps;
+    if (site_steps) *site_steps = b->timed_site_steps;
+    b->timed_steps = 0;
+    b->timed_site_steps = 0.0;
+    return LSM_OK;
+}
+
+}  // extern "C"

@@ -42,6 +42,22 @@ typedef lsm_record DevRecord;
 
 enum Mode { kStart = 0, kMid = 1, kEnd = 2, kEval = 3 };
 
+// One wavefront work item of the 2D row sweep over a batch of specimens:
+// specimen s (site block [base, base + nx*ny)), strip of columns starting at
+// i0 = strip * kSweepCols - 1, owned rows [j0, j1).  End-of-relax partials of
+// row j go to pbase + j * strips + strip.
+struct SweepItem {
+    int32_t base, nx, ny, i0;
+    int32_t j0, j1, strip, strips;
+    int32_t pbase, spec, pad0, pad1;
+};
+
+// Per-specimen reduction range and reference volume.
+struct SpecDesc {
+    int32_t pbase, npart;
+    double omega;
+};
+
 struct StepParams {
     int32_t nx, ny, nz;
     int32_t tiles_x, tiles_y, ntiles, nblocks;
@@ -70,6 +86,10 @@ struct StepParams {
     int32_t sw_strips, sw_rows, sw_nwork, sw_nblocks;
     int32_t sw_pf;          // rows prefetched ahead by each wavefront (1..3)
     int32_t pad2;
+    // batch of specimens (2D sweep only)
+    const SweepItem *items;  // active work items
+    const int32_t *n_items;  // number of active work items (device)
+    uint32_t *spec_broken;   // broken-spring count per specimen
 };
 
 // Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.
@@ -81,6 +101,14 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
 hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t stream,
                           int step_local);
 hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
+// Batch versions: the grid covers `capacity` work items; items beyond
+// *p.n_items exit at once.
+hipError_t launch_sweep2d_batch(const StepParams &p, int prec, int mode, hipStream_t stream,
+                                int step_local, int capacity);
+hipError_t launch_increment_batch(const StepParams &p, int prec, hipStream_t stream, double eps_new,
+                                  double d_eps, int inc, int affine, int capacity);
+hipError_t launch_finalize_batch(const StepParams &p, int dim, hipStream_t stream, DevRecord *recs,
+                                 const SpecDesc *specs, int nspec, int nsteps);
 hipError_t launch_finalize(const StepParams &p, int dim, hipStream_t stream, DevRecord *rec,
                            double omega, int nsteps);
 

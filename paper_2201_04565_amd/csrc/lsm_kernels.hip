@@ -638,15 +638,15 @@ struct SweepRow {
 };
 
 template <int PREC>
-__device__ inline void load_sweep_row(const StepParams &P, int i, bool col_ok, int jj, bool want_v,
-                                      SweepRow<typename State<2, PREC>::R> &r) {
-    // Loads are unconditional from an always-valid site (site 0 when the row
-    // or column is outside the lattice) and masked afterwards, so no branch
-    // joins on a pending load.
+__device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok,
+                                      int jj, bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
+    // Loads are unconditional from an always-valid site (the specimen's
+    // first site when the row or column is outside it) and masked
+    // afterwards, so no branch joins on a pending load.
     using S = State<2, PREC>;
     using R = typename S::R;
-    const bool ok = col_ok && jj >= 0 && jj < P.ny;
-    const int g = ok ? i + P.nx * jj : 0;
+    const bool ok = col_ok && jj >= 0 && jj < it.ny;
+    const int g = it.base + (ok ? i + it.nx * jj : 0);
     R uh[2], ul[2], v[2];
     S::load_u(P.u_in, g, P.nsites, uh, ul);
     const int f = P.flags[g];
@@ -660,6 +660,31 @@ __device__ inline void load_sweep_row(const StepParams &P, int i, bool col_ok, i
     }
     r.f = ok ? f : int(kVoid);
     r.m = ok ? m : 0;
+}
+
+// Work item of wavefront w: computed for a single lattice, read from the
+// item table for a batch.  Returns false for wavefronts without work.
+template <int BATCH>
+__device__ inline bool sweep_item(const StepParams &P, int w, SweepItem &it) {
+    if constexpr (BATCH) {
+        if (w >= *P.n_items) return false;
+        it = P.items[w];
+    } else {
+        if (w >= P.sw_nwork) return false;
+        const int s = w % P.sw_strips;
+        const int c = w / P.sw_strips;
+        it.base = 0;
+        it.nx = P.nx;
+        it.ny = P.ny;
+        it.i0 = s * kSweepCols - 1;
+        it.j0 = c * P.sw_rows;
+        it.j1 = min(it.j0 + P.sw_rows, P.ny);
+        it.strip = s;
+        it.strips = P.sw_strips;
+        it.pbase = 0;
+        it.spec = 0;
+    }
+    return true;
 }
 
 // One forward spring of site p towards q (lattice vector (ex, ey)).  Returns
@@ -730,7 +755,7 @@ __device__ inline void spring_stress64(const TypeRec &T, double ex64, double ey6
     red[18] += 0.5 * T.k64 * (r - T.r0_64) * (r - T.r0_64);
 }
 
-template <int PREC, int MODE, int PF>
+template <int PREC, int MODE, int PF, int BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
     using S = State<2, PREC>;
     using R = typename S::R;
@@ -751,14 +776,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
     const int per = P.sw_nblocks >> 3;
     const int L = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
     const int w = L * (kBlock / 64) + wv;
-    if (w < P.sw_nwork) {
-        const int s = w % P.sw_strips;
-        const int c = w / P.sw_strips;
-        const int i = s * kSweepCols - 1 + lane;
-        const bool col_ok = i >= 0 && i < P.nx;
+    SweepItem it;
+    if (sweep_item<BATCH>(P, w, it)) {
+        const int i = it.i0 + lane;
+        const bool col_ok = i >= 0 && i < it.nx;
         const bool own_lane = col_ok && lane >= 1 && lane <= kSweepCols;
-        const int j0 = c * P.sw_rows;
-        const int j1 = min(j0 + P.sw_rows, P.ny);
+        const int j0 = it.j0;
+        const int j1 = it.j1;
         const int jstart = j0 > 0 ? j0 - 1 : 0;
         const R a = R(P.a), hy = R(kHalfSqrt3 * P.a);
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
@@ -770,7 +794,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         // receives row j + 2; the three buffers rotate roles so that no
         // register copy forces an early wait on the prefetched row.
         auto row_step = [&](int j, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
-            load_sweep_row<PREC>(P, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
+            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
             const int par = j & 1;
             // neighbour sites: east (this row, next lane), upper-left / upper-right (row above)
             R eh[2], el[2], ulh[2], ull[2], urh[2], url[2];
@@ -837,7 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                     bDL = (pbrk >> 1) & 1;
                 }
                 if (own_lane && rc.f != kVoid) {
-                    const int g = i + P.nx * j;
+                    const int g = it.base + i + it.nx * j;
                     R F[2];
 #pragma unroll
                     for (int cc = 0; cc < 2; ++cc)
@@ -845,6 +869,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                     const int newmask = rc.m | nb | (bW << 3) | (bDR << 4) | (bDL << 5);
                     if (newmask != rc.m) {
                         reinterpret_cast<uint8_t *>(P.mask)[g] = uint8_t(newmask);
+                        if constexpr (BATCH) {
+                            // batches keep a per-specimen count instead of a log
+                            const int nnew = be + bul + bur;
+                            if (nnew) atomicAdd(&P.spec_broken[it.spec], uint32_t(nnew));
+                        } else {
                         const int brks[3] = {be, bul, bur};
                         const double mgs[3] = {me, mul, mur};
                         const int pres[3] = {pe, pul, pur};
@@ -864,6 +893,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                             }
                             rank += pres[d];
                         }
+                        }
                     }
                     if constexpr (MODE == kEnd) {
                         const int mk = newmask;
@@ -882,7 +912,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
                     for (int v = 0; v < kNumPartials; ++v) {
                         const double t = wave_sum(red[v]);
-                        if (lane == 0) P.partials[(int64_t(j) * P.sw_strips + s) * kNumPartials + v] = t;
+                        if (lane == 0)
+                            P.partials[(int64_t(it.pbase) + int64_t(j) * it.strips + it.strip) * kNumPartials + v] = t;
                         red[v] = 0.0;
                     }
                 }
@@ -902,7 +933,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
         for (int t = 0; t <= PF; ++t) {
             const int jj = jstart + t;
-            load_sweep_row<PREC>(P, i, col_ok, jj <= j1 ? jj : -1, jj >= j0, B[t]);
+            load_sweep_row<PREC>(P, it, i, col_ok, jj <= j1 ? jj : -1, jj >= j0, B[t]);
         }
         for (int j = jstart; j < j1; j += K) {
 #pragma unroll
@@ -926,29 +957,143 @@ hipError_t launch_step_t(const StepParams &p, int mode, hipStream_t s, int step_
     return hipGetLastError();
 }
 
-template <int PREC, int PF>
-hipError_t launch_sweep_pf(const StepParams &p, int mode, hipStream_t s, int step_local) {
-    const dim3 grid(p.sw_nblocks), block(kBlock);
+template <int PREC, int PF, int BATCH>
+hipError_t launch_sweep_pf(const StepParams &p, int mode, hipStream_t s, int step_local, int nblocks) {
+    const dim3 grid(nblocks), block(kBlock);
     switch (mode) {
-        case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart, PF>), grid, block, 0, s, p, step_local); break;
-        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid, PF>), grid, block, 0, s, p, step_local); break;
-        default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd, PF>), grid, block, 0, s, p, step_local); break;
+        case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart, PF, BATCH>), grid, block, 0, s, p, step_local); break;
+        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid, PF, BATCH>), grid, block, 0, s, p, step_local); break;
+        default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd, PF, BATCH>), grid, block, 0, s, p, step_local); break;
     }
     return hipGetLastError();
 }
 
-template <int PREC>
-hipError_t launch_sweep_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
+template <int PREC, int BATCH>
+hipError_t launch_sweep_t(const StepParams &p, int mode, hipStream_t s, int step_local, int nblocks) {
     // the prefetch depth only matters for the interior steps
-    if (mode != kMid || p.sw_pf <= 1) return launch_sweep_pf<PREC, 1>(p, mode, s, step_local);
-    if (p.sw_pf == 2) return launch_sweep_pf<PREC, 2>(p, mode, s, step_local);
-    return launch_sweep_pf<PREC, 3>(p, mode, s, step_local);
+    if (mode != kMid || p.sw_pf <= 1) return launch_sweep_pf<PREC, 1, BATCH>(p, mode, s, step_local, nblocks);
+    if (p.sw_pf == 2) return launch_sweep_pf<PREC, 2, BATCH>(p, mode, s, step_local, nblocks);
+    return launch_sweep_pf<PREC, 3, BATCH>(p, mode, s, step_local, nblocks);
+}
+
+// Increment for a batch: grips to eps * i * a, affine predictor elsewhere,
+// over the owned sites of each active work item.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_increment_batch(StepParams P, double eps_new, double d_eps,
+                                                            int inc, int affine) {
+    using S = State<2, PREC>;
+    using R = typename S::R;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P.ctl->eps = eps_new;
+        P.ctl->inc = inc;
+        P.ctl->step_base = 0;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int w = int(blockIdx.x) * (kBlock / 64) + wv;
+    SweepItem it;
+    if (!sweep_item<1>(P, w, it)) return;
+    const int i = it.i0 + lane;
+    if (!(i >= 0 && i < it.nx && lane >= 1 && lane <= kSweepCols)) return;
+    const double c = double(i) * P.a;
+    for (int j = it.j0; j < it.j1; ++j) {
+        const int g = it.base + i + it.nx * j;
+        const uint8_t f = P.flags[g];
+        if (f == kVoid) continue;
+        R hi[2], lo[2];
+        S::load_u(P.u_in, g, P.nsites, hi, lo);
+        if (flag_grip(f)) {
+            const double ux = eps_new * c;
+            hi[0] = R(ux);
+            lo[0] = R(ux - double(hi[0]));
+            hi[1] = R(0);
+            lo[1] = R(0);
+            const R z[2] = {R(0), R(0)};
+            S::store_v(P.v, g, P.nsites, z);
+            S::store_v(P.acc, g, P.nsites, z);
+        } else if (affine) {
+            if constexpr (PREC == 1) {
+                const double ux = (double(hi[0]) + double(lo[0])) + d_eps * c;
+                hi[0] = R(ux);
+                lo[0] = R(ux - double(hi[0]));
+            } else {
+                hi[0] = hi[0] + d_eps * c;
+            }
+        }
+        S::store_u(P.u_in, g, P.nsites, hi, lo);
+    }
+}
+
+// Per-specimen record: one workgroup per specimen sums its partials in a
+// fixed order.
+__global__ __launch_bounds__(kBlock) void k_finalize_batch(StepParams P, DevRecord *recs,
+                                                           const SpecDesc *specs, int nsteps, int dim) {
+    __shared__ double lds[kNumPartials][kBlock / 64];
+    const SpecDesc sd = specs[blockIdx.x];
+    double vals[kNumPartials];
+#pragma unroll
+    for (int v = 0; v < kNumPartials; ++v) vals[v] = 0.0;
+    for (int b = threadIdx.x; b < sd.npart; b += kBlock) {
+#pragma unroll
+        for (int v = 0; v < kNumPartials; ++v)
+            vals[v] += P.partials[(int64_t(sd.pbase) + b) * kNumPartials + v];
+    }
+    block_sum(vals, lds);
+    if (threadIdx.x == 0) {
+        DevRecord r;
+        r.eps = P.ctl->eps;
+        bool finite = isfinite(vals[18]) && isfinite(vals[19]);
+        for (int aa = 0; aa < 3; ++aa)
+            for (int bb = 0; bb < 3; ++bb) {
+                double s = 0.0;
+                if (aa < dim && bb < dim) s = (vals[aa * 3 + bb] - vals[9 + aa * 3 + bb]) / sd.omega;
+                r.sigma[aa * 3 + bb] = s;
+                finite = finite && isfinite(s);
+            }
+        r.pe = vals[18];
+        r.ke = vals[19];
+        r.n_broken = int64_t(P.spec_broken[blockIdx.x]);
+        r.increment = P.ctl->inc;
+        r.step = nsteps;
+        r.status = finite ? LSM_OK : LSM_EUNSTABLE;
+        r.reserved = 0;
+        recs[blockIdx.x] = r;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t s, int step_local) {
-    return prec ? launch_sweep_t<1>(p, mode, s, step_local) : launch_sweep_t<0>(p, mode, s, step_local);
+    return prec ? launch_sweep_t<1, 0>(p, mode, s, step_local, p.sw_nblocks)
+                : launch_sweep_t<0, 0>(p, mode, s, step_local, p.sw_nblocks);
+}
+
+static int batch_blocks(int capacity) {
+    const int wgs = (capacity + kBlock / 64 - 1) / (kBlock / 64);
+    return ((wgs + 7) / 8) * 8;
+}
+
+hipError_t launch_sweep2d_batch(const StepParams &p, int prec, int mode, hipStream_t s, int step_local,
+                                int capacity) {
+    StepParams q = p;
+    q.sw_nblocks = batch_blocks(capacity);
+    return prec ? launch_sweep_t<1, 1>(q, mode, s, step_local, q.sw_nblocks)
+                : launch_sweep_t<0, 1>(q, mode, s, step_local, q.sw_nblocks);
+}
+
+hipError_t launch_increment_batch(const StepParams &p, int prec, hipStream_t s, double eps_new,
+                                  double d_eps, int inc, int affine, int capacity) {
+    const dim3 grid(unsigned((capacity + kBlock / 64 - 1) / (kBlock / 64))), block(kBlock);
+    if (prec) hipLaunchKernelGGL((k_increment_batch<1>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+    else hipLaunchKernelGGL((k_increment_batch<0>), grid, block, 0, s, p, eps_new, d_eps, inc, affine);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const StepParams &p, int dim, hipStream_t s, DevRecord *recs,
+                                 const SpecDesc *specs, int nspec, int nsteps) {
+    if (nspec <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize_batch, dim3(nspec), dim3(kBlock), 0, s, p, recs, specs, nsteps, dim);
+    return hipGetLastError();
 }
 
 hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStream_t s, int step_local) {

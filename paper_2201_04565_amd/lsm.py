@@ -393,3 +393,128 @@ class HostModel:
         b = C.c_int64()
         self._check(self._L.lsm_step_bytes(self._h, C.byref(b)))
         return b.value
+
+
+BATCH_EXPORTS = (
+    "lsm_batch_create", "lsm_batch_destroy", "lsm_batch_last_error", "lsm_batch_counts",
+    "lsm_batch_workspace_bytes", "lsm_batch_bind", "lsm_batch_set_launch", "lsm_batch_run",
+    "lsm_batch_read", "lsm_batch_set_timing", "lsm_batch_read_timing",
+)
+
+
+class FailRule(C.Structure):
+    _fields_ = [("drop_fraction", C.c_double)]
+
+
+def _load_batch(L):
+    if getattr(L, "_batch_ready", False):
+        return L
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    P = C.POINTER
+    L.lsm_batch_create.argtypes = [P(Config), i64, vp, vp, P(vp)]
+    L.lsm_batch_destroy.argtypes = [vp]
+    L.lsm_batch_destroy.restype = None
+    L.lsm_batch_last_error.argtypes = [vp]
+    L.lsm_batch_last_error.restype = C.c_char_p
+    L.lsm_batch_counts.argtypes = [vp, P(i64), P(i64)]
+    L.lsm_batch_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+    L.lsm_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
+    L.lsm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.lsm_batch_run.argtypes = [vp, dbl, i64, i32, P(FailRule)]
+    L.lsm_batch_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    L.lsm_batch_set_timing.argtypes = [vp, C.c_int]
+    L.lsm_batch_read_timing.argtypes = [vp, P(dbl), P(i64), P(dbl)]
+    L._batch_ready = True
+    return L
+
+
+class Batch:
+    """Independent 2D specimens run to failure in shared launches."""
+
+    def __init__(self, images, *, k, s, mass, a=1.0, dt=0.01, gamma=0.1, precision="fp32k",
+                 predictor="affine", void_value=-1, device="cuda:0", stream=None):
+        import torch
+
+        L = _load_batch(load_library())
+        self._L = L
+        self._h = None
+        imgs = [np.ascontiguousarray(im, dtype=np.uint8) for im in images]
+        if not imgs or any(im.ndim != 2 for im in imgs):
+            raise ValueError("a batch needs 2D images")
+        self._imgs = imgs  # keep alive during creation
+        cfg = make_config(lattice=TRI2D, k=k, s=s, mass=mass, a=a, dt=dt, gamma=gamma,
+                          precision=precision, predictor=predictor, void_value=void_value)
+        n = len(imgs)
+        ptrs = (C.c_void_p * n)(*[im.ctypes.data for im in imgs])
+        dims = np.array([[im.shape[1], im.shape[0], 1] for im in imgs], dtype=np.int64)
+        h = C.c_void_p()
+        rc = L.lsm_batch_create(C.byref(cfg), n, ptrs, _ptr(dims), C.byref(h))
+        if rc != LSM_OK:
+            raise LsmError(rc, L.lsm_strerror(rc).decode())
+        self._h = h
+        self.n = n
+        np_, ms = C.c_int64(), C.c_int64()
+        L.lsm_batch_counts(h, C.byref(np_), C.byref(ms))
+        self.n_particles, self.n_springs = np_.value, ms.value
+        nb = C.c_size_t()
+        self._check(L.lsm_batch_workspace_bytes(h, C.byref(nb)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self._check(L.lsm_batch_bind(h, C.c_void_p(self.workspace.data_ptr()), nb.value,
+                                     C.c_void_p(self.stream.cuda_stream)))
+        self.max_inc = None
+
+    @classmethod
+    def from_workload(cls, wl: dict, images, **over):
+        kw = dict(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0), dt=wl["dt"],
+                  gamma=wl["gamma"], precision=wl.get("precision", "fp32k"),
+                  void_value=wl.get("void_value", -1))
+        kw.update(over)
+        return cls(images, **kw)
+
+    def _check(self, rc):
+        if rc == LSM_OK:
+            return rc
+        msg = self._L.lsm_batch_last_error(self._h).decode() if self._h else ""
+        raise LsmError(rc, f"{self._L.lsm_strerror(rc).decode()}: {msg}")
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            self._L.lsm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, rows_per_wave=4, prefetch=1):
+        self._check(self._L.lsm_batch_set_launch(self._h, int(rows_per_wave), int(prefetch)))
+
+    def run(self, d_eps, steps_per_inc, max_inc, drop=0.01):
+        rule = FailRule(float(drop))
+        self._check(self._L.lsm_batch_run(self._h, float(d_eps), int(steps_per_inc),
+                                          int(max_inc), C.byref(rule)))
+        self.max_inc = int(max_inc)
+
+    def read(self) -> dict:
+        mi = self.max_inc
+        sxx = np.zeros((self.n, mi))
+        ninc = np.zeros(self.n, np.int32)
+        mod = np.zeros(self.n)
+        st = np.zeros(self.n)
+        nb = np.zeros(self.n, np.int64)
+        self._check(self._L.lsm_batch_read(self._h, mi, _ptr(sxx), _ptr(ninc), _ptr(mod),
+                                           _ptr(st), _ptr(nb)))
+        return dict(sigma_xx=sxx, n_inc=ninc, modulus=mod, strength=st, n_broken=nb)
+
+    def set_timing(self, on):
+        self._check(self._L.lsm_batch_set_timing(self._h, int(bool(on))))
+
+    def read_timing(self):
+        ms, steps, ss = C.c_double(), C.c_int64(), C.c_double()
+        self._check(self._L.lsm_batch_read_timing(self._h, C.byref(ms), C.byref(steps),
+                                                  C.byref(ss)))
+        return ms.value, steps.value, ss.value

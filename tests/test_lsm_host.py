@@ -16,8 +16,12 @@ NAN = float("nan")
 
 
 def header_functions():
-    txt = open(os.path.join(ROOT, "include", "lsm.h")).read()
-    return sorted(set(re.findall(r"^(?:int|void|const char \*)\s*(lsm_\w+)\(", txt, re.M)))
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", hdr)).read()
+            names |= set(re.findall(r"^(?:int|void|const char \*)\s*(lsm_\w+)\(", txt, re.M))
+    return sorted(names)
 
 
 def test_library_exports_every_header_function():
@@ -26,7 +30,7 @@ def test_library_exports_every_header_function():
     assert len(names) >= 20
     for nm in names:
         assert hasattr(L, nm), nm
-    assert set(names) == set(lsm.EXPORTS)
+    assert set(names) == set(lsm.EXPORTS) | set(lsm.BATCH_EXPORTS)
 
 
 def _model(img, wl, **over):

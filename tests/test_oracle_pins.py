@@ -580,3 +580,43 @@ def test_increment_predictor(predictor):
     expect = 0.01 * c[free] if predictor == 0 else 0.0
     assert np.allclose(ux[free], expect, rtol=0, atol=1e-15)
     assert np.all(net.x[:, 1] == net.X0[:, 1])
+
+
+def test_run_to_failure_rule_and_modulus():
+    # the derived quantities follow their definitions on the oracle's own
+    # per-increment records (checked here against a plain re-run)
+    img = inputs.circular_inclusions(24, seed=1003)
+    w = inputs.WORKLOADS["c4"]
+    prm = Params(k=w["k"], s=w["s"], mass=w["mass"], dt=w["dt"], gamma=w["gamma"])
+    a = Net.lattice(img, prm)
+    res = a.run_to_failure(0.01, 300, 40)
+    b = Net.lattice(img, prm)
+    recs = []
+    for _ in range(res["n_inc"]):
+        b.apply_increment(0.01)
+        b.relax(300)
+        recs.append(b.record())
+    sxx = np.array([r["sigma"][0, 0] for r in recs])
+    nb = np.array([r["n_broken"] for r in recs])
+    assert np.array_equal(sxx, res["sigma_xx"]) and np.array_equal(nb, res["n_broken"])
+    assert res["strength"] == sxx.max()
+    ip = int(np.argmax(sxx))
+    if res["n_inc"] < 40:
+        # stops at the first increment after the peak below 1 % of it
+        below = [k for k in range(ip + 1, len(sxx)) if sxx[k] < 0.01 * sxx[ip]]
+        assert below and below[0] == len(sxx) - 1
+    k = max(int(np.argmax(nb > 0)) if (nb > 0).any() else len(nb), 1)
+    e = np.array([r["eps"] for r in recs])[:k]
+    assert res["modulus"] == pytest.approx((e * sxx[:k]).sum() / (e * e).sum(), rel=1e-14)
+    assert res["modulus"] > 0 and res["n_inc"] >= 2
+
+
+def test_modulus_of_uniform_specimen_near_closed_form():
+    # a uniform specimen with unbreakable springs: the relaxed stress per
+    # unit strain approaches E = 2k/sqrt3 (finite-size and grip effects
+    # keep it within a few percent for a 40 x 24 specimen)
+    img = np.zeros((24, 40), np.uint8)
+    net = Net.lattice(img, uniform_params(k=1.0, s=10.0, dt=0.05, gamma=0.5))
+    res = net.run_to_failure(1e-4, 6000, 2)
+    E = 2.0 / math.sqrt(3.0)
+    assert abs(res["modulus"] / E - 1.0) < 0.15
