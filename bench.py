@@ -64,6 +64,82 @@ def cpu_baseline(wl, img, steps: int):
                        f"(+ step-0 evaluation), FP64, single thread, {dt:.1f} s")
 
 
+def batched_c4(args, torch, inputs, lsm):
+    """Specimens/hour of the batched path on the 4096-specimen inclusion
+    workload, beside the same kernels run one specimen at a time and the
+    oracle on the host, all under the same failure rule."""
+    import numpy as np
+
+    wl = inputs.WORKLOADS["c4"]
+    imgs = inputs.batch_specimens(args.batch_n)
+    sizes = np.array([im.shape[0] for im in imgs])
+    b = lsm.Batch.from_workload(wl, imgs, precision="fp32k", device="cuda:0")
+    b.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(wl["d_eps"], wl["steps"], wl["max_inc"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, steps, site_steps = b.read_timing()
+    res = b.read()
+    n_inc = res["n_inc"]
+    out = dict(workload=f"{len(imgs)} inclusion specimens, sides {sorted(set(sizes.tolist()))}, "
+                        f"0.5% x {wl['steps']} steps to failure (cap {wl['max_inc']}), fp32",
+               particles=b.n_particles, springs=b.n_springs, wall_s=wall,
+               specimens_per_hour=len(imgs) / wall * 3600.0,
+               mean_increments=float(n_inc.mean()),
+               step_graph_GBs=site_steps * 50 / (ms * 1e-3) / 1e9)
+    del b
+    torch.cuda.empty_cache()
+    # plain: the same kernels, one specimen at a time, on a stratified sample
+    per_size = {}
+    for L in sorted(set(sizes.tolist())):
+        idx = [i for i in range(len(imgs)) if sizes[i] == L][: args.plain_per_size]
+        tt = []
+        for i in idx:
+            lat = lsm.Lattice.from_workload(wl, imgs[i], precision="fp32k", device="cuda:0")
+            lat.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(int(n_inc[i])):
+                lat.apply_increment(wl["d_eps"])
+                lat.relax(wl["steps"])
+            lat.read_state()
+            tt.append(time.perf_counter() - t1)
+            del lat
+        per_size[L] = float(np.mean(tt))
+    plain_total = sum(per_size[int(L)] for L in sizes)
+    out["plain_specimens_per_hour"] = len(imgs) / plain_total * 3600.0
+    out["plain_sample"] = f"{args.plain_per_size} specimens per side, mean s/specimen {per_size}"
+    out["batched_over_plain"] = out["specimens_per_hour"] / out["plain_specimens_per_hour"]
+    return out
+
+
+def cpu_c4(args, inputs):
+    """Oracle on one host core: one specimen per side for a prefix of
+    increments, extrapolated to the batch's increments (per-step cost is
+    constant because broken springs stay in the list)."""
+    import numpy as np
+
+    import oracle
+    wl = inputs.WORKLOADS["c4"]
+    prm = oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], dt=wl["dt"], gamma=wl["gamma"])
+    imgs = inputs.batch_specimens(args.batch_n)
+    sizes = np.array([im.shape[0] for im in imgs])
+    per_step = {}
+    for L in sorted(set(sizes.tolist())):
+        i = int(np.nonzero(sizes == L)[0][0])
+        net = oracle.Net.lattice(imgs[i], prm)
+        t0 = time.perf_counter()
+        for _ in range(args.cpu_c4_inc):
+            net.apply_increment(wl["d_eps"])
+            net.relax(wl["steps"])
+        per_step[L] = (time.perf_counter() - t0) / (args.cpu_c4_inc * wl["steps"])
+    total = sum(per_step[int(L)] * wl["max_inc"] * wl["steps"] for L in sizes)
+    return dict(value=len(imgs) / total * 3600.0, unit="specimens/hour", cores=1, kind="oracle",
+                sample=f"one specimen per side, {args.cpu_c4_inc} increments each, "
+                       f"extrapolated to {wl['max_inc']} increments per specimen")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +148,10 @@ def main():
     ap.add_argument("--steps-per-inc", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched C4 measurement")
+    ap.add_argument("--batch-n", type=int, default=4096)
+    ap.add_argument("--plain-per-size", type=int, default=2)
+    ap.add_argument("--cpu-c4-inc", type=int, default=1)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
@@ -168,6 +248,13 @@ def main():
             torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads and writes MIB MiB
         torch.cuda.synchronize()
         out["copy_ref_mib"] = args.copy_ref
+    if not args.no_batch:
+        del lat
+        torch.cuda.empty_cache()
+        print("[bench] batched specimens", file=sys.stderr, flush=True)
+        out["batched"] = batched_c4(args, torch, inputs, lsm)
+        if not args.no_cpu:
+            out["batched"]["cpu_baseline"] = cpu_c4(args, inputs)
     if not args.no_cpu:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)

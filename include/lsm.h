@@ -300,6 +300,61 @@ int lsm_batch_read(lsm_batch *b, int32_t max_inc, double *sigma_xx, int32_t *n_i
 int lsm_batch_set_timing(lsm_batch *b, int enable);
 int lsm_batch_read_timing(lsm_batch *b, double *ms, int64_t *steps, double *site_steps);
 
+/* ---------------------------------------------------------------------
+ * Surrogate network: a small CNN from a two-phase image to the batched
+ * model's stress-strain curve and modulus (the paper's motivation of fast
+ * data generation for machine-learning materials design: Abstract,
+ * Section 4).  Five 3x3 convolutions (ReLU; 2x2 average pooling after the
+ * first four; channels[l] outputs), global average pooling, a ReLU dense
+ * layer of `hidden` units and a linear layer of `outputs`.  Convolutions
+ * with >= 32 input channels run on BF16 matrix cores with FP32
+ * accumulation; master weights, gradients, Adam moments and dense layers
+ * are FP32.  Parameters are one FP32 vector: for each conv layer l the
+ * weights [Cout][3][3][Cin] then the bias [Cout]; then the dense layers
+ * [out][in] weights and bias (offsets: lsm_cnn_layout).  Device pointers
+ * below (x, y, target, dy, loss) are caller-owned device memory; the
+ * workspace follows the single-lattice rules.
+ * --------------------------------------------------------------------- */
+typedef struct {
+    int32_t batch;       /* largest batch */
+    int32_t height;      /* image side, multiple of 16 */
+    int32_t width;       /* equal to height */
+    int32_t channels[5]; /* conv output channels, multiples of 32 */
+    int32_t hidden;
+    int32_t outputs;
+} lsm_cnn_config;
+
+typedef struct lsm_cnn lsm_cnn;
+
+int lsm_cnn_create(const lsm_cnn_config *cfg, lsm_cnn **out);
+void lsm_cnn_destroy(lsm_cnn *c);
+const char *lsm_cnn_last_error(const lsm_cnn *c);
+int lsm_cnn_param_count(const lsm_cnn *c, int64_t *n);
+/* offsets and sizes of each layer's weights and bias in the parameter
+ * vector (7 entries: 5 conv, 2 dense; w_n = weight count)                 */
+int lsm_cnn_layout(const lsm_cnn *c, int64_t *w_off, int64_t *b_off, int64_t *w_n);
+int lsm_cnn_workspace_bytes(const lsm_cnn *c, size_t *bytes);
+int lsm_cnn_bind(lsm_cnn *c, void *dptr, size_t bytes, void *hip_stream);
+/* host FP32 parameter vector in / out (set also clears the Adam moments);
+ * synchronise                                                             */
+int lsm_cnn_set_params(lsm_cnn *c, const float *host);
+int lsm_cnn_get_params(lsm_cnn *c, float *host);
+int lsm_cnn_get_grads(lsm_cnn *c, float *host);
+/* x: device uint8 images [batch][height][width] (phase 0/1); y (may be
+ * NULL): device FP32 [batch][outputs].  Keeps activations for backward.   */
+int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y);
+/* mean squared error of the last forward against device target
+ * [batch][outputs]; writes the output gradient (device, may be NULL) and
+ * the loss (device float, may be NULL)                                    */
+int lsm_cnn_mse(lsm_cnn *c, const float *target, float *dy, float *loss);
+/* gradients of all parameters for output gradient dy (device; NULL uses
+ * the one from lsm_cnn_mse); overwrites the gradient vector               */
+int lsm_cnn_backward(lsm_cnn *c, const float *dy);
+int lsm_cnn_adam_step(lsm_cnn *c, float lr, float beta1, float beta2, float eps, int64_t t);
+/* one implicit-GEMM convolution (layers 1..4, bias + ReLU) on device BF16
+ * NHWC buffers with this network's weights (kernel tests)                 */
+int lsm_cnn_conv_forward(lsm_cnn *c, int layer, const void *in, void *out, int64_t batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsm.so")
-SOURCES = [os.path.join(CSRC, "lsm_kernels.hip"), os.path.join(CSRC, "lsm_host.cpp")]
+SOURCES = [os.path.join(CSRC, "lsm_kernels.hip"), os.path.join(CSRC, "lsm_host.cpp"),
+           os.path.join(CSRC, "lsm_cnn.hip")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -26,8 +27,10 @@ HIPCC_FLAGS = [
 def build_library(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", SOURCES[0], "-x", "hip",
-           SOURCES[1], "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC]
+    for src in SOURCES:
+        cmd += ["-x", "hip", src]
+    cmd += ["-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

@@ -30,7 +30,8 @@ def test_library_exports_every_header_function():
     assert len(names) >= 20
     for nm in names:
         assert hasattr(L, nm), nm
-    assert set(names) == set(lsm.EXPORTS) | set(lsm.BATCH_EXPORTS)
+    from paper_2201_04565_amd import cnn
+    assert set(names) == set(lsm.EXPORTS) | set(lsm.BATCH_EXPORTS) | set(cnn.CNN_EXPORTS)
 
 
 def _model(img, wl, **over):
@@ -132,3 +133,25 @@ def test_unbound_calls_report_state_errors():
     assert L.lsm_read_state(g._h, C.byref(R)) == lsm.LSM_ESTATE
     assert L.lsm_bind(g._h, None, 0, None) == lsm.LSM_EINVAL
     assert L.lsm_strerror(lsm.LSM_EUNSTABLE).decode().startswith("non-finite")
+
+
+def test_cnn_layout_matches_oracle_definition():
+    from oracle import cnn_oracle as co
+    from paper_2201_04565_amd import cnn
+    L = cnn._load()
+    cfg = cnn.CnnConfig(8, 32, 32, (C.c_int32 * 5)(32, 64, 128, 128, 256), 256, 65)
+    h = C.c_void_p()
+    assert L.lsm_cnn_create(C.byref(cfg), C.byref(h)) == 0
+    n = C.c_int64()
+    L.lsm_cnn_param_count(h, C.byref(n))
+    spec, n_or = co.layout([32, 64, 128, 128, 256], 256, 65)
+    assert n.value == n_or
+    wo = np.zeros(7, np.int64); bo = np.zeros(7, np.int64); wn = np.zeros(7, np.int64)
+    L.lsm_cnn_layout(h, wo.ctypes.data_as(C.c_void_p), bo.ctypes.data_as(C.c_void_p),
+                     wn.ctypes.data_as(C.c_void_p))
+    for l, sp in enumerate(spec):
+        assert (wo[l], wn[l]) == sp["w"] and bo[l] == sp["b"][0]
+    bad = cnn.CnnConfig(8, 24, 24, (C.c_int32 * 5)(32, 64, 128, 128, 256), 256, 65)
+    h2 = C.c_void_p()
+    assert L.lsm_cnn_create(C.byref(bad), C.byref(h2)) == lsm.LSM_EINVAL
+    L.lsm_cnn_destroy(h)
