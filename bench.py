@@ -140,6 +140,36 @@ def cpu_c4(args, inputs):
                        f"extrapolated to {wl['max_inc']} increments per specimen")
 
 
+def surrogate_c5(args):
+    """Batched model + surrogate pipeline on 128 x 128 inclusion specimens:
+    labels from the batched model, a 5-member ensemble trained on them, a 5 %
+    spread gate with fallback to the model; specimens/hour of the pipeline
+    and of the batched model alone, and the modulus error against the
+    model's own labels."""
+    from paper_2201_04565_amd import surrogate as S
+
+    t0 = time.perf_counter()
+    img_tr = S.specimen_images(args.sur_train, 10 ** 6)
+    img_te = S.specimen_images(args.sur_test, 2 * 10 ** 6)
+    lab_tr = S.label(img_tr)
+    lab_te = S.label(img_te)
+    sur = S.Surrogate(k=5, batch=512, seed=0)
+    sur.fit(img_tr, S.targets(lab_tr), epochs=args.sur_epochs, lr=2e-3)
+    res = S.evaluate(sur, img_te, lab_te, gate=0.05)
+    res.update(
+        workload=f"{args.sur_train} train / {args.sur_test} test 128x128 inclusion specimens, "
+                 f"labels = 64-point sigma_xx curve + modulus (64 x 0.5% x 500 steps, fp32), "
+                 f"5-member BF16 CNN ensemble, {args.sur_epochs} epochs, gate 5% spread",
+        label_specimens_per_hour=len(img_tr) / lab_tr.seconds * 3600.0,
+        batched_model_specimens_per_hour=len(img_te) / lab_te.seconds * 3600.0,
+        train_s=sur.train_seconds,
+        train_TFLOPs=3 * 0.425e9 * 5 * args.sur_epochs * (len(img_tr) // 512) * 512
+        / sur.train_seconds / 1e12,
+        total_s=time.perf_counter() - t0)
+    res["pipeline_over_batched_model"] = res["specimens_per_hour"] / res["batched_model_specimens_per_hour"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +182,10 @@ def main():
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--plain-per-size", type=int, default=2)
     ap.add_argument("--cpu-c4-inc", type=int, default=1)
+    ap.add_argument("--surrogate", action="store_true", help="also run the surrogate pipeline")
+    ap.add_argument("--sur-train", type=int, default=16384)
+    ap.add_argument("--sur-test", type=int, default=2048)
+    ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
@@ -255,6 +289,9 @@ def main():
         out["batched"] = batched_c4(args, torch, inputs, lsm)
         if not args.no_cpu:
             out["batched"]["cpu_baseline"] = cpu_c4(args, inputs)
+    if args.surrogate:
+        print("[bench] surrogate pipeline", file=sys.stderr, flush=True)
+        out["surrogate"] = surrogate_c5(args)
     if not args.no_cpu:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)

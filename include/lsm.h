@@ -319,7 +319,7 @@ typedef struct {
     int32_t batch;       /* largest batch */
     int32_t height;      /* image side, multiple of 16 */
     int32_t width;       /* equal to height */
-    int32_t channels[5]; /* conv output channels, multiples of 32 */
+    int32_t channels[5]; /* conv output channels: 32, 64, 128 or 256 each */
     int32_t hidden;
     int32_t outputs;
 } lsm_cnn_config;

@@ -60,34 +60,40 @@ __global__ __launch_bounds__(kBlk) void k_conv1_fwd(const uint8_t *x, const floa
         const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
         v[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
     }
-    for (int c = 0; c < C; ++c) {
-        float s = b[c];
+    // eight channels per 16-byte store (C is a multiple of 32)
+    for (int c0 = 0; c0 < C; c0 += 8) {
+        u16 h[8];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) s = fmaf(w[c * 9 + t], v[t], s);
-        out[p * C + c] = f2bf(fmaxf(s, 0.0f));
+        for (int e = 0; e < 8; ++e) {
+            float s = b[c0 + e];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) s = fmaf(w[(c0 + e) * 9 + t], v[t], s);
+            h[e] = f2bf(fmaxf(s, 0.0f));
+        }
+        *reinterpret_cast<uint4 *>(out + p * C + c0) = *reinterpret_cast<const uint4 *>(h);
     }
 }
 
 // ------------------------------------------------------ implicit-GEMM conv
 // out[p, co] = act(sum_{tap, ci} in[shift(p, tap), ci] * wt[co, tap, ci] + bias[co])
 // in: [B, H, W, Cin] BF16, wt: [Cout, 9, Cin] BF16, out: [B, H, W, Cout] BF16.
-// Workgroup tile 64 pixels x 64 channels; each wavefront 32 x 32 (2 x 2
-// MFMA tiles of 16 x 16, K = 32 per instruction).
-template <bool BIAS_RELU>
+// Each wavefront owns WM x WN MFMA tiles of 16 x 16 (WM * 16 pixels x WN *
+// 16 channels); the four wavefronts of a workgroup stack along pixels.  Per
+// K step of 32 a lane issues WM + WN 16-byte loads for WM * WN MFMAs.
+template <bool BIAS_RELU, int WM, int WN>
 __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt, const float *bias,
                                                    u16 *out, int B, int H, int W, int Cin, int Cout) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int64_t npix = int64_t(B) * H * W;
-    const int64_t p0 = int64_t(blockIdx.x) * 64 + (wv & 1) * 32;
-    const int c0 = blockIdx.y * 64 + (wv >> 1) * 32;
+    const int64_t p0 = (int64_t(blockIdx.x) * 4 + wv) * (WM * 16);
+    const int c0 = blockIdx.y * (WN * 16);
     const int r16 = lane & 15, kq = lane >> 4;  // row within the 16-tile, K quarter
-    // the two pixels this lane feeds as A rows
-    int py[2], px[2];
-    int64_t pn[2];
-    bool pok[2];
+    int py[WM], px[WM];
+    int64_t pn[WM];
+    bool pok[WM];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < WM; ++r) {
         const int64_t p = p0 + r * 16 + r16;
         pok[r] = p < npix;
         const int64_t pp = pok[r] ? p : 0;
@@ -95,48 +101,54 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
         py[r] = int((pp / W) % H);
         pn[r] = pp / (int64_t(H) * W);
     }
-    f32x4 acc[2][2];
+    f32x4 acc[WM][WN];
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < WM; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < WN; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int K = 9 * Cin;
+    const u16 *wrow[WN];
+    bool cok[WN];
+#pragma unroll
+    for (int c = 0; c < WN; ++c) {
+        const int co = c0 + c * 16 + r16;
+        cok[c] = co < Cout;
+        wrow[c] = wt + int64_t(cok[c] ? co : 0) * K + 8 * kq;
+    }
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        int64_t abase[2];
-        bool aok[2];
+        const u16 *arow[WM];
+        bool aok[WM];
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
+        for (int r = 0; r < WM; ++r) {
             const int sy = py[r] + dy, sx = px[r] + dx;
             aok[r] = pok[r] && sy >= 0 && sy < H && sx >= 0 && sx < W;
-            abase[r] = aok[r] ? ((pn[r] * H + sy) * W + sx) * Cin : 0;
+            arow[r] = in + (aok[r] ? ((pn[r] * H + sy) * W + sx) * Cin : 0) + 8 * kq;
         }
         for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-            Frag a[2], bfr[2];
+            Frag a[WM], bfr[WN];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const uint4 t = *reinterpret_cast<const uint4 *>(in + abase[r] + ci0 + 8 * kq);
+            for (int r = 0; r < WM; ++r) {
+                const uint4 t = *reinterpret_cast<const uint4 *>(arow[r] + ci0);
                 a[r].u = aok[r] ? t : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const int co = c0 + c * 16 + r16;
-                const int coc = co < Cout ? co : 0;
-                const uint4 t = *reinterpret_cast<const uint4 *>(wt + int64_t(coc) * K + tap * Cin + ci0 + 8 * kq);
-                bfr[c].u = co < Cout ? t : make_uint4(0, 0, 0, 0);
+            for (int c = 0; c < WN; ++c) {
+                const uint4 t = *reinterpret_cast<const uint4 *>(wrow[c] + tap * Cin + ci0);
+                bfr[c].u = cok[c] ? t : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < WM; ++r)
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
+                for (int c = 0; c < WN; ++c)
                     acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bfr[c].v, acc[r][c], 0, 0, 0);
         }
     }
     // D layout: lane holds rows 4 * kq + i (pixels), column r16 (channel)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int r = 0; r < WM; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < WN; ++c) {
             const int co = c0 + c * 16 + r16;
             if (co >= Cout) continue;
             const float bv = BIAS_RELU ? bias[co] : 0.0f;
@@ -150,6 +162,8 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
             }
         }
 }
+
+constexpr int kConvWM = 4, kConvWN = 4;  // 64 pixels x 64 channels per wavefront
 
 // ------------------------------------------------------- weight gradient
 // dw[co, tap, ci] = sum_p dout[p, co] * in[shift(p, tap), ci], split over
@@ -243,40 +257,79 @@ __global__ __launch_bounds__(kBlk) void k_sum_splits(const float *partial, float
 }
 
 // db[c] partials: column sums of a [npix, C] BF16 matrix over pixel chunks.
+// Thread t reads channel t % C of pixels t / C, t / C + 256 / C, ... (rows
+// are contiguous, so a wavefront reads whole rows); the 256 / C partial sums
+// of a channel are then added in a fixed order.
 __global__ __launch_bounds__(kBlk) void k_colsum_bf16(const u16 *g, float *partial, int64_t npix, int C,
                                                      int64_t pix_per_split) {
-    const int c = blockIdx.x * kBlk + threadIdx.x;
-    if (c >= C) return;
-    const int64_t b0 = int64_t(blockIdx.y) * pix_per_split;
+    __shared__ float red[kBlk];
+    const int c = threadIdx.x % C;
+    const int lanes = kBlk / C;  // pixels read per pass (C divides 256)
+    const int sub = threadIdx.x / C;
+    const int64_t b0 = int64_t(blockIdx.x) * pix_per_split;
     const int64_t b1 = b0 + pix_per_split < npix ? b0 + pix_per_split : npix;
     float s = 0.0f;
-    for (int64_t p = b0; p < b1; ++p) s += bf2f(g[p * C + c]);
-    partial[int64_t(blockIdx.y) * C + c] = s;
+    if (sub < lanes)
+        for (int64_t p = b0 + sub; p < b1; p += lanes) s += bf2f(g[p * C + c]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.0f;
+        for (int k = 0; k < lanes; ++k) t += red[k * C + threadIdx.x];
+        partial[int64_t(blockIdx.x) * C + threadIdx.x] = t;
+    }
 }
 
-// Weight gradient of the one-channel first layer: dw[co][tap] partials.
+// Weight gradient of the one-channel first layer: partials [split][co][10]
+// (9 taps, then the bias).  Wavefront w of a workgroup handles channels
+// 8 w .. 8 w + 7 (workgroups along y cover further groups); its 64 lanes
+// stride over the split's pixels and the lane sums are combined by a fixed
+// wavefront reduction.
+__device__ inline float wave_sum_f(float x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
 __global__ __launch_bounds__(kBlk) void k_conv1_wgrad(const uint8_t *x, const u16 *dout, float *partial, int B,
                                                      int H, int W, int C, int64_t pix_per_split) {
-    const int j = threadIdx.x;  // (co, tap) pair, C * 9 <= 288 handled in two passes
+    const int lane = threadIdx.x & 63;
+    const int grp = (blockIdx.y * (kBlk / 64)) + (threadIdx.x >> 6);
+    if (grp * 8 >= C) return;  // whole wavefronts leave together
     const int64_t npix = int64_t(B) * H * W;
     const int64_t b0 = int64_t(blockIdx.x) * pix_per_split;
     const int64_t b1 = b0 + pix_per_split < npix ? b0 + pix_per_split : npix;
-    for (int jj = j; jj < C * 10; jj += kBlk) {
-        const int co = jj / 10, tap = jj % 10;  // tap 9 = bias
-        float s = 0.0f;
-        for (int64_t p = b0; p < b1; ++p) {
-            const float g = bf2f(dout[p * C + co]);
-            if (tap == 9) {
-                s += g;
-                continue;
-            }
-            const int xx = int(p % W), yy = int((p / W) % H);
-            const int64_t n = p / (int64_t(H) * W);
-            const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-            if (sy >= 0 && sy < H && sx >= 0 && sx < W) s = fmaf(g, float(x[(n * H + sy) * W + sx]), s);
+    float acc[8][10];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[e][k] = 0.0f;
+    for (int64_t p = b0 + lane; p < b1; p += 64) {
+        const uint4 gv = *reinterpret_cast<const uint4 *>(dout + p * C + grp * 8);
+        const u16 *gh = reinterpret_cast<const u16 *>(&gv);
+        const int xx = int(p % W), yy = int((p / W) % H);
+        const int64_t n = p / (int64_t(H) * W);
+        float v[10];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
+            v[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
         }
-        partial[int64_t(blockIdx.x) * C * 10 + jj] = s;
+        v[9] = 1.0f;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const float g = bf2f(gh[e]);
+#pragma unroll
+            for (int k = 0; k < 10; ++k) acc[e][k] = fmaf(g, v[k], acc[e][k]);
+        }
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const float t = wave_sum_f(acc[e][k]);
+            if (lane == 0) partial[(int64_t(blockIdx.x) * C + grp * 8 + e) * 10 + k] = t;
+        }
 }
 
 // ------------------------------------------------------ pooling and GAP
@@ -535,7 +588,8 @@ int lsm_cnn_create(const lsm_cnn_config *cfg, lsm_cnn **out) {
         k.outputs < 1)
         return LSM_EINVAL;
     for (int l = 0; l < kLayers; ++l)
-        if (k.channels[l] < 32 || k.channels[l] % 32) return LSM_EINVAL;
+        if (k.channels[l] != 32 && k.channels[l] != 64 && k.channels[l] != 128 && k.channels[l] != 256)
+            return LSM_EINVAL;
     lsm_cnn *c = new (std::nothrow) lsm_cnn();
     if (!c) return LSM_ENOMEM;
     c->cfg = k;
@@ -690,8 +744,9 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
         const int H = c->Hs[l];
         if (l > 0) {
             const int64_t npix = int64_t(B) * H * H;
-            const dim3 grid(unsigned((npix + 63) / 64), unsigned((c->C[l + 1] + 63) / 64));
-            hipLaunchKernelGGL((k_conv_mfma<true>), grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->wf[l],
+            const dim3 grid(unsigned((npix + 64 * kConvWM - 1) / (64 * kConvWM)),
+                            unsigned((c->C[l + 1] + 16 * kConvWN - 1) / (16 * kConvWN)));
+            hipLaunchKernelGGL((k_conv_mfma<true, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->wf[l],
                                c->p + c->b_off[l], c->act[l], B, H, H, c->C[l], c->C[l + 1]);
             CHIP(c, hipGetLastError());
         }
@@ -764,16 +819,17 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
                                int(sp));
             // bias gradient
-            hipLaunchKernelGGL(k_colsum_bf16, dim3(nblk(cout), unsigned(sp)), dim3(kBlk), 0, c->stream, c->dact[l],
-                               c->part, npix, int(cout), int64_t(kSplitPix));
+            hipLaunchKernelGGL(k_colsum_bf16, dim3(unsigned(sp)), dim3(kBlk), 0, c->stream, c->dact[l], c->part, npix,
+                               int(cout), int64_t(kSplitPix));
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout)), dim3(kBlk), 0, c->stream, c->part, c->g + c->b_off[l],
                                cout, int(sp));
             CHIP(c, hipGetLastError());
             // input gradient: implicit GEMM with the flipped weights, then the
             // pooling and ReLU of the layer below
             const int64_t npin = npix;
-            const dim3 g2(unsigned((npin + 63) / 64), unsigned((cin + 63) / 64));
-            hipLaunchKernelGGL((k_conv_mfma<false>), g2, dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
+            const dim3 g2(unsigned((npin + 64 * kConvWM - 1) / (64 * kConvWM)),
+                          unsigned((cin + 16 * kConvWN - 1) / (16 * kConvWN)));
+            hipLaunchKernelGGL((k_conv_mfma<false, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
                                c->dpool[l - 1], B, H, H, int(cout), int(cin));
             CHIP(c, hipGetLastError());
             const int Hp = c->Hs[l - 1];
@@ -781,8 +837,9 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                                c->dpool[l - 1], c->act[l - 1], c->dact[l - 1], B, Hp, Hp, int(cin));
             CHIP(c, hipGetLastError());
         } else {
-            hipLaunchKernelGGL(k_conv1_wgrad, dim3(unsigned(sp)), dim3(kBlk), 0, c->stream, c->x_last, c->dact[0],
-                               c->part, B, H, H, int(cout), int64_t(kSplitPix));
+            const unsigned groups = unsigned((cout / 8 + kBlk / 64 - 1) / (kBlk / 64));
+            hipLaunchKernelGGL(k_conv1_wgrad, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
+                               c->dact[0], c->part, B, H, H, int(cout), int64_t(kSplitPix));
             // part layout [split][co][10]: taps then bias
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout * 10)), dim3(kBlk), 0, c->stream, c->part,
                                c->part + sp * cout * 10, cout * 10, int(sp));
@@ -822,8 +879,9 @@ int lsm_cnn_conv_forward(lsm_cnn *c, int layer, const void *in, void *out, int64
     if (!c->bound) return cfail(c, LSM_ESTATE, "bind first");
     const int H = c->Hs[layer];
     const int64_t npix = batch * H * H;
-    const dim3 grid(unsigned((npix + 63) / 64), unsigned((c->C[layer + 1] + 63) / 64));
-    hipLaunchKernelGGL((k_conv_mfma<true>), grid, dim3(kBlk), 0, c->stream, static_cast<const u16 *>(in), c->wf[layer],
+    const dim3 grid(unsigned((npix + 64 * kConvWM - 1) / (64 * kConvWM)),
+                    unsigned((c->C[layer + 1] + 16 * kConvWN - 1) / (16 * kConvWN)));
+    hipLaunchKernelGGL((k_conv_mfma<true, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream, static_cast<const u16 *>(in), c->wf[layer],
                        c->p + c->b_off[layer], static_cast<u16 *>(out), int(batch), H, H, c->C[layer], c->C[layer + 1]);
     CHIP(c, hipGetLastError());
     return LSM_OK;
