@@ -178,6 +178,10 @@ def main():
     ap.add_argument("--steps-per-inc", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--launch", default="4,1", metavar="ROWS,PREFETCH",
+                    help="sweep launch: rows per wavefront, prefetch depth")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the launch with lsm_autotune instead of --launch")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched C4 measurement")
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--plain-per-size", type=int, default=2)
@@ -204,9 +208,14 @@ def main():
     lat = lsm.Lattice.from_workload(wl, img, precision="fp32k", device="cuda:0")
     print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
           flush=True)
-    tuning = lat.autotune(100)
+    if args.autotune:
+        lat.autotune(100)
+    else:
+        rows, pf = (int(v) for v in args.launch.split(","))
+        lat.set_launch("sweep", rows)
+        lat.set_prefetch(pf)
     launch = lat.launch()
-    print(f"[bench] autotuned launch: {launch}", file=sys.stderr, flush=True)
+    print(f"[bench] launch: {launch}", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         lat.apply_increment(wl["d_eps"])

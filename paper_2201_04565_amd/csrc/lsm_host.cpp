@@ -674,8 +674,11 @@ static int read_u(lsm_handle *h, std::vector<double> &u) {
             } else if (h->dim == 2) {
                 val = reinterpret_cast<const double *>(raw.data())[g * 2 + c];
             } else if (h->prec) {
-                const float *f = reinterpret_cast<const float *>(raw.data());
-                val = double(f[c * ns + g]) + double(f[(3 + c) * ns + g]);
+                // float4 plane (x_hi, y_hi, z_hi, x_lo), then float2 plane (y_lo, z_lo)
+                const float *a = reinterpret_cast<const float *>(raw.data()) + g * 4;
+                const float *b = reinterpret_cast<const float *>(raw.data()) + ns * 4 + g * 2;
+                const float lo = c == 0 ? a[3] : b[c - 1];
+                val = double(a[c]) + double(lo);
             } else {
                 val = reinterpret_cast<const double *>(raw.data())[c * ns + g];
             }
@@ -699,9 +702,13 @@ static int write_u(lsm_handle *h, const std::vector<double> &u) {
             } else if (h->dim == 2) {
                 reinterpret_cast<double *>(raw.data())[g * 2 + c] = val;
             } else if (h->prec) {
-                float *f = reinterpret_cast<float *>(raw.data());
-                f[c * ns + g] = hi;
-                f[(3 + c) * ns + g] = lo;
+                float *a = reinterpret_cast<float *>(raw.data()) + g * 4;
+                float *b = reinterpret_cast<float *>(raw.data()) + ns * 4 + g * 2;
+                a[c] = hi;
+                if (c == 0)
+                    a[3] = lo;
+                else
+                    b[c - 1] = lo;
             } else {
                 reinterpret_cast<double *>(raw.data())[c * ns + g] = val;
             }

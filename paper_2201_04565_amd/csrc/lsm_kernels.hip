@@ -75,19 +75,19 @@ struct State<2, 0> {
     }
 };
 
-// 3D, FP32 compensated: six planes (x_hi, y_hi, z_hi, x_lo, y_lo, z_lo), v three planes.
+// 3D, FP32 compensated: u as a float4 plane (x_hi, y_hi, z_hi, x_lo) followed
+// by a float2 plane (y_lo, z_lo) -- two loads per neighbour; v three planes.
 template <>
 struct State<3, 1> {
     using R = float;
     __device__ static void load_u(const void *U, int g, int64_t ns, float hi[3], float lo[3]) {
-        const float *P = reinterpret_cast<const float *>(U);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { hi[c] = P[c * ns + g]; lo[c] = P[(3 + c) * ns + g]; }
+        const float4 a = reinterpret_cast<const float4 *>(U)[g];
+        const float2 b = reinterpret_cast<const float2 *>(reinterpret_cast<const float4 *>(U) + ns)[g];
+        hi[0] = a.x; hi[1] = a.y; hi[2] = a.z; lo[0] = a.w; lo[1] = b.x; lo[2] = b.y;
     }
     __device__ static void store_u(void *U, int g, int64_t ns, const float hi[3], const float lo[3]) {
-        float *P = reinterpret_cast<float *>(U);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { P[c * ns + g] = hi[c]; P[(3 + c) * ns + g] = lo[c]; }
+        reinterpret_cast<float4 *>(U)[g] = make_float4(hi[0], hi[1], hi[2], lo[0]);
+        reinterpret_cast<float2 *>(reinterpret_cast<float4 *>(U) + ns)[g] = make_float2(lo[1], lo[2]);
     }
     __device__ static void load_v(const void *V, int g, int64_t ns, float v[3]) {
         const float *P = reinterpret_cast<const float *>(V);
@@ -358,20 +358,38 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) F[c] = R(0);
         int rank = 0;
+        // neighbours in groups of kGrp: all loads of a group are issued
+        // unconditionally (from the site itself when the neighbour is outside
+        // the lattice) before any of them is used
+        constexpr int kGrp = 6;
 #pragma unroll
-        for (int d = 0; d < G::ND; ++d) {
+        for (int d0 = 0; d0 < G::ND; d0 += kGrp) {
+        int qs[kGrp];
+        bool inb[kGrp];
+        uint8_t fqs[kGrp];
+        R uqhs[kGrp][DIM], uqls[kGrp][DIM];
+#pragma unroll
+        for (int t = 0; t < kGrp; ++t) {
+            const int d = d0 + t;
             const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
             const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-            if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
-            const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
-            const uint8_t fq = P.flags[q];
+            inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+            qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+            fqs[t] = P.flags[qs[t]];
+            S::load_u(P.u_in, qs[t], P.nsites, uqhs[t], uqls[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < kGrp; ++t) {
+            const int d = d0 + t;
+            if (!inb[t]) continue;
+            const uint8_t fq = fqs[t];
             if (fq == kVoid) continue;
             const bool fwd = d < G::NF;
             const int myrank = rank;
             if (fwd) ++rank;
             if (mask & (Mask(1) << d)) continue;
-            R uqh[DIM], uql[DIM];
-            S::load_u(P.u_in, q, P.nsites, uqh, uql);
+            const R *uqh = uqhs[t];
+            const R *uql = uqls[t];
             // lattice vector X0_q - X0_p
             R e[DIM];
             double e64[DIM];
@@ -478,6 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
                     red[18] += 0.5 * T64.k64 * (r64 - T64.r0_64) * (r64 - T64.r0_64);
                 }
             }
+        }
         }
         if (commit && newmask != mask) reinterpret_cast<Mask *>(P.mask)[g] = newmask;
 
