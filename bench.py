@@ -29,6 +29,13 @@ HBM_PEAK_GBS = 8000.0
 METRIC = ("spring-steps/s (% HBM roofline); specimens/hour batched+surrogate "
           "@≤5% error")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_step_traffic.json")
+WORKLOAD_NAMES = {
+    "c2": "c2 brick-and-mortar 2048x2048 triangular lattice, fp32 forces with compensated fp32 "
+          "displacements, 0.05% strain increments x 2000 steps",
+    "c3": "c3 256^3 simple-cubic voxel lattice from a thresholded Gaussian random field (40% solid, "
+          "largest cluster), face + edge springs, fp32 forces with compensated fp32 displacements, "
+          "0.05% strain increments x 2000 steps",
+}
 KERNEL_SRC = os.path.join(ROOT, "paper_2201_04565_amd", "csrc", "lsm_kernels.hip")
 
 
@@ -53,15 +60,17 @@ def measured_traffic():
 def cpu_baseline(wl, img, steps: int):
     """The FP64 oracle, single thread, on one increment of the same lattice."""
     import oracle
-    prm = oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], dt=wl["dt"], gamma=wl["gamma"])
+    prm = oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
+                        k_face=wl.get("k_face", 1.0), k_diag=wl.get("k_diag", 1.0),
+                        dt=wl["dt"], gamma=wl["gamma"], void_value=wl.get("void_value", -1))
     net = oracle.Net.lattice(img, prm)
     t0 = time.perf_counter()
     net.apply_increment(wl["d_eps"])
     net.relax(steps)
     dt = time.perf_counter() - t0
     return dict(value=net.m * steps / dt, unit="spring-steps/s", cores=1, kind="oracle",
-                sample=f"full 2048x2048 lattice, 1 increment x {steps} steps "
-                       f"(+ step-0 evaluation), FP64, single thread, {dt:.1f} s")
+                sample=f"full {'x'.join(str(d) for d in img.shape[::-1])} lattice, 1 increment x "
+                       f"{steps} steps (+ step-0 evaluation), FP64, single thread, {dt:.1f} s")
 
 
 def batched_c4(args, torch, inputs, lsm):
@@ -140,6 +149,55 @@ def cpu_c4(args, inputs):
                        f"extrapolated to {wl['max_inc']} increments per specimen")
 
 
+def cnn_forward_flops(size=128, channels=(32, 64, 128, 128, 256), hidden=256, outputs=65):
+    """Multiply-adds x 2 of one forward pass (convolutions and dense layers)."""
+    f, cin, h = 0, 1, size
+    for i, c in enumerate(channels):
+        f += 2 * h * h * c * 9 * cin
+        cin = c
+        if i < len(channels) - 1:
+            h //= 2
+    return f + 2 * (cin * hidden + hidden * outputs)
+
+
+def cnn_kernels(torch, batch=512, size=128, iters=10):
+    """Surrogate network kernels alone: one training step (forward, loss,
+    backward, Adam) and one inference pass on a batch of 128 x 128 images,
+    timed with events on the network's stream; rated against the BF16 dense
+    matrix-core peak (2.5 PFLOP/s), a training step counted as 3 forwards."""
+    import numpy as np
+
+    from paper_2201_04565_amd import cnn, inputs
+    from paper_2201_04565_amd.surrogate import _he_normal
+
+    net = cnn.Network(size=size, batch=batch, outputs=65)
+    net.set_params(_he_normal(net, 0))
+    imgs = np.stack([inputs.circular_inclusions(size, seed=10 ** 7 + i) for i in range(batch)])
+    x = torch.from_numpy(imgs).cuda()
+    t = torch.from_numpy(np.random.default_rng(0).normal(size=(batch, 65)).astype(np.float32)).cuda()
+    for _ in range(3):
+        net.train_step(x, t, 1e-4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    for _ in range(iters):
+        net.train_step(x, t, 1e-4)
+    e1.record(net.stream)
+    e1.synchronize()
+    train_ms = e0.elapsed_time(e1) / iters
+    e0.record(net.stream)
+    for _ in range(iters):
+        net.forward(x)
+    e1.record(net.stream)
+    e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / iters
+    f = cnn_forward_flops(size) * batch
+    return dict(batch=batch, size=size, train_step_ms=train_ms, forward_ms=fwd_ms,
+                train_TFLOPs=3 * f / (train_ms * 1e-3) / 1e12,
+                forward_TFLOPs=f / (fwd_ms * 1e-3) / 1e12,
+                forward_frac_of_bf16_peak=f / (fwd_ms * 1e-3) / 2.5e15,
+                inference_images_per_s=batch / (fwd_ms * 1e-3))
+
+
 def surrogate_c5(args):
     """Batched model + surrogate pipeline on 128 x 128 inclusion specimens:
     labels from the batched model, a 5-member ensemble trained on them, a 5 %
@@ -148,13 +206,17 @@ def surrogate_c5(args):
     model's own labels."""
     from paper_2201_04565_amd import surrogate as S
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
     img_tr = S.specimen_images(args.sur_train, 10 ** 6)
     img_te = S.specimen_images(args.sur_test, 2 * 10 ** 6)
-    lab_tr = S.label(img_tr)
-    lab_te = S.label(img_te)
+    log(f"images generated ({time.perf_counter() - t0:.1f} s)")
+    lab_tr = S.label(img_tr, log=log)
+    lab_te = S.label(img_te, log=log)
     sur = S.Surrogate(k=5, batch=512, seed=0)
-    sur.fit(img_tr, S.targets(lab_tr), epochs=args.sur_epochs, lr=2e-3)
+    sur.fit(img_tr, S.targets(lab_tr), epochs=args.sur_epochs, lr=2e-3, log=log)
     res = S.evaluate(sur, img_te, lab_te, gate=0.05)
     res.update(
         workload=f"{args.sur_train} train / {args.sur_test} test 128x128 inclusion specimens, "
@@ -163,7 +225,7 @@ def surrogate_c5(args):
         label_specimens_per_hour=len(img_tr) / lab_tr.seconds * 3600.0,
         batched_model_specimens_per_hour=len(img_te) / lab_te.seconds * 3600.0,
         train_s=sur.train_seconds,
-        train_TFLOPs=3 * 0.425e9 * 5 * args.sur_epochs * (len(img_tr) // 512) * 512
+        train_TFLOPs=3 * cnn_forward_flops() * 5 * args.sur_epochs * (len(img_tr) // 512) * 512
         / sur.train_seconds / 1e12,
         total_s=time.perf_counter() - t0)
     res["pipeline_over_batched_model"] = res["specimens_per_hour"] / res["batched_model_specimens_per_hour"]
@@ -173,10 +235,13 @@ def surrogate_c5(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=198, help="timed loading increments")
+    ap.add_argument("--workload", choices=("c2", "c3"), default="c2",
+                    help="c2: 2048^2 brick-and-mortar (default); c3: 256^3 random-field voxels")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed loading increments (default 198 for c2, 5 for c3)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed loading increments")
     ap.add_argument("--steps-per-inc", type=int, default=None)
-    ap.add_argument("--cpu-steps", type=int, default=100)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--launch", default="4,1", metavar="ROWS,PREFETCH",
                     help="sweep launch: rows per wavefront, prefetch depth")
@@ -187,12 +252,15 @@ def main():
     ap.add_argument("--plain-per-size", type=int, default=2)
     ap.add_argument("--cpu-c4-inc", type=int, default=1)
     ap.add_argument("--surrogate", action="store_true", help="also run the surrogate pipeline")
+    ap.add_argument("--cnn-bench", action="store_true", help="also time the surrogate network kernels")
     ap.add_argument("--sur-train", type=int, default=16384)
     ap.add_argument("--sur-test", type=int, default=2048)
     ap.add_argument("--sur-epochs", type=int, default=20)
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 198 if args.workload == "c2" else 5
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -202,13 +270,15 @@ def main():
 
     from paper_2201_04565_amd import inputs, lsm
 
-    wl = inputs.WORKLOADS["c2"]
+    wl = inputs.WORKLOADS[args.workload]
     spi = args.steps_per_inc or wl["steps"]
-    img = inputs.c2_image()
+    img = inputs.c2_image() if args.workload == "c2" else inputs.c3_image()
     lat = lsm.Lattice.from_workload(wl, img, precision="fp32k", device="cuda:0")
     print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
           flush=True)
-    if args.autotune:
+    if args.workload == "c3":
+        pass  # 3D: one thread per particle (the sweep is 2D only)
+    elif args.autotune:
         lat.autotune(100)
     else:
         rows, pf = (int(v) for v in args.launch.split(","))
@@ -260,8 +330,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "c2 brick-and-mortar 2048x2048 triangular lattice, fp32 forces with "
-                        "compensated fp32 displacements, 0.05% strain increments x 2000 steps",
+            "workload": WORKLOAD_NAMES[args.workload],
             "particles": lat.n,
             "springs": springs,
             "steps_per_increment": spi,
@@ -277,9 +346,10 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
+            "traffic": traffic if args.workload == "c2" else None,
             "bytes_per_launch": step_bytes,
-            "kernel": "k_sweep2d<1,1> (fp32, interior step)",
+            "kernel": ("k_sweep2d<1,1> (fp32, interior step)" if args.workload == "c2"
+                       else "k_step<3,1,1> (fp32, interior step, one thread per particle)"),
         },
     }
     if args.copy_ref:
@@ -298,12 +368,16 @@ def main():
         out["batched"] = batched_c4(args, torch, inputs, lsm)
         if not args.no_cpu:
             out["batched"]["cpu_baseline"] = cpu_c4(args, inputs)
+    if args.cnn_bench:
+        print("[bench] surrogate network kernels", file=sys.stderr, flush=True)
+        out["cnn"] = cnn_kernels(torch)
     if args.surrogate:
         print("[bench] surrogate pipeline", file=sys.stderr, flush=True)
         out["surrogate"] = surrogate_c5(args)
     if not args.no_cpu:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps if args.workload == "c2"
+                                           else max(args.cpu_steps // 30, 2))
     print(json.dumps(out))
 
 

@@ -83,7 +83,9 @@ class Network:
         self._check(L.lsm_cnn_workspace_bytes(h, C.byref(nb)))
         self.device = torch.device(device)
         self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
-        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        # default: torch's current stream, so results are ordered with the
+        # caller's own torch work; another stream is synchronised both ways
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._check(L.lsm_cnn_bind(h, _dptr(self.workspace), nb.value,
                                    C.c_void_p(self.stream.cuda_stream)))
         self.y = torch.empty((batch, outputs), dtype=torch.float32, device=self.device)
@@ -133,32 +135,50 @@ class Network:
         return out
 
     # ------------------------------------------------------------- compute
-    def _on_stream(self, t):
+    def _enter(self):
         # inputs produced on torch's current stream must be ready on ours
-        self.stream.wait_stream(self.torch.cuda.current_stream(self.device))
-        return t
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _leave(self, *inputs):
+        # outputs must be ready for the caller's stream, and inputs must not
+        # be recycled by the caching allocator while our stream reads them
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            for t in inputs:
+                if t is not None:
+                    t.record_stream(self.stream)
 
     def forward(self, x_u8):
-        """x_u8: uint8 CUDA tensor [B, size, size] -> FP32 [B, outputs] (a view)."""
+        """x_u8: uint8 CUDA tensor [B, size, size] -> FP32 [B, outputs] (a view).
+
+        The backward pass reads x_u8 again: keep it unchanged until then."""
         B = x_u8.shape[0]
-        self._on_stream(x_u8)
+        self._enter()
         self._check(self._L.lsm_cnn_forward(self._h, _dptr(x_u8), B, _dptr(self.y)))
+        self._x = x_u8
+        self._leave(x_u8)
         return self.y[:B]
 
     def mse(self, target):
-        self._on_stream(target)
+        self._enter()
         self._check(self._L.lsm_cnn_mse(self._h, _dptr(target), None, _dptr(self.loss)))
+        self._leave(target)
         return self.loss
 
     def backward(self, dy=None):
-        if dy is not None:
-            self._on_stream(dy)
+        self._enter()
         self._check(self._L.lsm_cnn_backward(self._h, _dptr(dy)))
+        self._leave(dy, getattr(self, "_x", None))
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         self.t += 1
+        self._enter()
         self._check(self._L.lsm_cnn_adam_step(self._h, float(lr), float(beta1), float(beta2),
                                               float(eps), self.t))
+        self._leave()
 
     def train_step(self, x_u8, target, lr):
         self.forward(x_u8)
@@ -169,9 +189,10 @@ class Network:
 
     def conv_forward(self, layer, x_bf16, out_bf16):
         B = x_bf16.shape[0]
-        self._on_stream(x_bf16)
+        self._enter()
         self._check(self._L.lsm_cnn_conv_forward(self._h, int(layer), _dptr(x_bf16),
                                                  _dptr(out_bf16), B))
+        self._leave(x_bf16, out_bf16)
 
     def synchronize(self):
         self.stream.synchronize()

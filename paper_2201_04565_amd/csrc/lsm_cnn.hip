@@ -14,6 +14,13 @@
 // (reduction over pixels) stages transposed tiles in LDS and is split over
 // pixel ranges with a fixed-order second pass (deterministic).  Master
 // weights, Adam moments and dense layers are FP32.
+//
+// Pooling never makes a pass of its own: the first layer (one input
+// channel) is computed and pooled by one kernel and recomputed from the
+// image in its backward pass; the other pooled layers pool in the conv
+// epilogue and keep a 4-bit ReLU mask per pooled pixel, which the next
+// layer's input-gradient epilogue uses to write the full-resolution gradient
+// directly.  Only the last conv output is stored at full resolution.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -46,31 +53,51 @@ union Frag {
 };
 
 // ------------------------------------------------------------------ conv 1
-// One input channel (the phase image, uint8 0/1): direct FP32 convolution,
-// each thread one output pixel x all output channels, ReLU, BF16 out.
-__global__ __launch_bounds__(kBlk) void k_conv1_fwd(const uint8_t *x, const float *w, const float *b,
-                                                   u16 *out, int B, int H, int W, int C) {
-    const int64_t p = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (p >= int64_t(B) * H * W) return;
-    const int xx = int(p % W), yy = int((p / W) % H);
-    const int64_t n = p / (int64_t(H) * W);
-    float v[9];
+// First layer fused with its 2x2 pooling: one thread per pooled pixel, all
+// C channels.  Each of the four conv outputs is rounded to BF16 after the
+// ReLU and the four are averaged in the order (0,0), (0,1), (1,0), (1,1):
+// the same values as storing the conv output and pooling it, without the
+// full-resolution map ever reaching memory (the backward pass recomputes its
+// sign from the image).
+__device__ inline void conv1_patch(const uint8_t *x, int H, int W, int64_t n, int yo, int xo, float v[4][4]) {
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
-        v[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
+    for (int r = 0; r < 4; ++r) {
+        const int sy = 2 * yo - 1 + r;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int sx = 2 * xo - 1 + c;
+            v[r][c] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
+        }
     }
-    // eight channels per 16-byte store (C is a multiple of 32)
+}
+
+// conv output (before ReLU) of channel c at sub-pixel (dy, dx) of the patch
+__device__ inline float conv1_at(const float *w, const float *b, int c, const float v[4][4], int dy, int dx) {
+    float s = b[c];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) s = fmaf(w[c * 9 + t], v[dy + t / 3][dx + t % 3], s);
+    return s;
+}
+
+__global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const float *w, const float *b,
+                                                        u16 *pool, int B, int H, int W, int C) {
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t q = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    if (q >= int64_t(B) * Ho * Wo) return;
+    const int xo = int(q % Wo), yo = int((q / Wo) % Ho);
+    const int64_t n = q / (int64_t(Ho) * Wo);
+    float v[4][4];
+    conv1_patch(x, H, W, n, yo, xo, v);
     for (int c0 = 0; c0 < C; c0 += 8) {
         u16 h[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            float s = b[c0 + e];
+            float s4 = 0.0f;
 #pragma unroll
-            for (int t = 0; t < 9; ++t) s = fmaf(w[(c0 + e) * 9 + t], v[t], s);
-            h[e] = f2bf(fmaxf(s, 0.0f));
+            for (int d = 0; d < 4; ++d) s4 += bf2f(f2bf(fmaxf(conv1_at(w, b, c0 + e, v, d >> 1, d & 1), 0.0f)));
+            h[e] = f2bf(0.25f * s4);
         }
-        *reinterpret_cast<uint4 *>(out + p * C + c0) = *reinterpret_cast<const uint4 *>(h);
+        *reinterpret_cast<uint4 *>(pool + q * C + c0) = *reinterpret_cast<const uint4 *>(h);
     }
 }
 
@@ -78,11 +105,66 @@ __global__ __launch_bounds__(kBlk) void k_conv1_fwd(const uint8_t *x, const floa
 // out[p, co] = act(sum_{tap, ci} in[shift(p, tap), ci] * wt[co, tap, ci] + bias[co])
 // in: [B, H, W, Cin] BF16, wt: [Cout, 9, Cin] BF16, out: [B, H, W, Cout] BF16.
 // Each wavefront owns WM x WN MFMA tiles of 16 x 16 (WM * 16 pixels x WN *
-// 16 channels); the four wavefronts of a workgroup stack along pixels.  Per
-// K step of 32 a lane issues WM + WN 16-byte loads for WM * WN MFMAs.
-template <bool BIAS_RELU, int WM, int WN>
-__global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt, const float *bias,
-                                                   u16 *out, int B, int H, int W, int Cin, int Cout) {
+// 16 channels); the four wavefronts of a workgroup stack along pixels.  The
+// reduction runs in K steps of 32 (step kk covers tap kk / (Cin / 32),
+// channels 32 (kk mod (Cin / 32)) onwards, i.e. weight columns 32 kk ..):
+// a lane issues WM + WN 16-byte loads per step, one step ahead of the
+// WM * WN MFMAs that consume them (two register stages).
+template <int WM, int WN>
+struct ConvOperands {
+    Frag a[WM], b[WN];
+};
+
+template <int WM, int WN>
+__device__ inline void conv_load_step(ConvOperands<WM, WN> &o, int kk, int ksteps_per_tap, const u16 *in,
+                                      const int64_t *pbase, const int *py, const int *px, const bool *pok, int H,
+                                      int W, int Cin, const u16 *const *wrow, const bool *cok, int kq) {
+    const int tap = kk / ksteps_per_tap;
+    const int ci0 = (kk - tap * ksteps_per_tap) * 32;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int64_t shift = (int64_t(dy) * W + dx) * Cin + ci0 + 8 * kq;
+#pragma unroll
+    for (int r = 0; r < WM; ++r) {
+        const int sy = py[r] + dy, sx = px[r] + dx;
+        const bool ok = pok[r] && sy >= 0 && sy < H && sx >= 0 && sx < W;
+        const uint4 t = *reinterpret_cast<const uint4 *>(in + (ok ? pbase[r] + shift : 0));
+        o.a[r].u = ok ? t : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < WN; ++c) {
+        const uint4 t = *reinterpret_cast<const uint4 *>(wrow[c] + kk * 32);
+        o.b[c].u = cok[c] ? t : make_uint4(0, 0, 0, 0);
+    }
+}
+
+template <int WM, int WN>
+__device__ inline void conv_mfma_step(f32x4 (&acc)[WM][WN], const ConvOperands<WM, WN> &o) {
+#pragma unroll
+    for (int r = 0; r < WM; ++r)
+#pragma unroll
+        for (int c = 0; c < WN; ++c)
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(o.a[r].v, o.b[c].v, acc[r][c], 0, 0, 0);
+}
+
+// Epilogues of the implicit-GEMM convolution.
+//  kEpiStore  out = bf16(relu(acc + bias)), one value per pixel
+//  kEpiRaw    out = bf16(acc) (input gradient kept at its own resolution)
+//  kEpiPool   forward conv followed by 2x2 average pooling: rows of a
+//             16-row tile are four 2x2 quads (row m: quad m / 4, position
+//             m mod 4 = (dy, dx) = (m / 2 mod 2, m mod 2)), so each lane holds
+//             a whole quad of one channel; it stores the pooled value
+//             bf16(0.25 (a0 + a1 + a2 + a3)) of the BF16 ReLU outputs a_i and
+//             the 4-bit mask of a_i > 0 (one byte per pooled pixel and channel)
+//  kEpiExpand input gradient of a layer whose input was pooled: the
+//             gradient g = bf16(acc) of a pooled pixel becomes
+//             bf16(0.25 g) on each of the four pixels below it whose ReLU
+//             output was positive (mask from kEpiPool), 0 elsewhere
+enum { kEpiStore = 0, kEpiRaw = 1, kEpiPool = 2, kEpiExpand = 3 };
+
+template <int EPI, int WM, int WN>
+__global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                                                   const uint8_t *mask_in, uint8_t *mask_out, int B, int H, int W,
+                                                   int Cin, int Cout) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int64_t npix = int64_t(B) * H * W;
@@ -90,16 +172,28 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
     const int c0 = blockIdx.y * (WN * 16);
     const int r16 = lane & 15, kq = lane >> 4;  // row within the 16-tile, K quarter
     int py[WM], px[WM];
-    int64_t pn[WM];
+    int64_t pbase[WM];
     bool pok[WM];
 #pragma unroll
     for (int r = 0; r < WM; ++r) {
         const int64_t p = p0 + r * 16 + r16;
         pok[r] = p < npix;
         const int64_t pp = pok[r] ? p : 0;
-        px[r] = int(pp % W);
-        py[r] = int((pp / W) % H);
-        pn[r] = pp / (int64_t(H) * W);
+        if constexpr (EPI == kEpiPool) {
+            // pp / 4 is a quad of the pooled grid, pp mod 4 its position
+            const int Wq = W / 2, Hq = H / 2;
+            const int64_t q = pp >> 2;
+            const int sub = int(pp & 3);
+            const int qx = int(q % Wq), qy = int((q / Wq) % Hq);
+            const int64_t n = q / (int64_t(Hq) * Wq);
+            px[r] = 2 * qx + (sub & 1);
+            py[r] = 2 * qy + (sub >> 1);
+            pbase[r] = ((n * H + py[r]) * W + px[r]) * Cin;
+        } else {
+            px[r] = int(pp % W);
+            py[r] = int((pp / W) % H);
+            pbase[r] = pp * Cin;
+        }
     }
     f32x4 acc[WM][WN];
 #pragma unroll
@@ -115,33 +209,17 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
         cok[c] = co < Cout;
         wrow[c] = wt + int64_t(cok[c] ? co : 0) * K + 8 * kq;
     }
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        const u16 *arow[WM];
-        bool aok[WM];
-#pragma unroll
-        for (int r = 0; r < WM; ++r) {
-            const int sy = py[r] + dy, sx = px[r] + dx;
-            aok[r] = pok[r] && sy >= 0 && sy < H && sx >= 0 && sx < W;
-            arow[r] = in + (aok[r] ? ((pn[r] * H + sy) * W + sx) * Cin : 0) + 8 * kq;
-        }
-        for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-            Frag a[WM], bfr[WN];
-#pragma unroll
-            for (int r = 0; r < WM; ++r) {
-                const uint4 t = *reinterpret_cast<const uint4 *>(arow[r] + ci0);
-                a[r].u = aok[r] ? t : make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int c = 0; c < WN; ++c) {
-                const uint4 t = *reinterpret_cast<const uint4 *>(wrow[c] + tap * Cin + ci0);
-                bfr[c].u = cok[c] ? t : make_uint4(0, 0, 0, 0);
-            }
-#pragma unroll
-            for (int r = 0; r < WM; ++r)
-#pragma unroll
-                for (int c = 0; c < WN; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bfr[c].v, acc[r][c], 0, 0, 0);
+    const int kpt = Cin / 32;
+    const int nk = 9 * kpt;
+    ConvOperands<WM, WN> s0, s1;
+    conv_load_step<WM, WN>(s0, 0, kpt, in, pbase, py, px, pok, H, W, Cin, wrow, cok, kq);
+    for (int kk = 0; kk < nk; kk += 2) {
+        if (kk + 1 < nk) conv_load_step<WM, WN>(s1, kk + 1, kpt, in, pbase, py, px, pok, H, W, Cin, wrow, cok, kq);
+        conv_mfma_step<WM, WN>(acc, s0);
+        if (kk + 1 < nk) {
+            if (kk + 2 < nk)
+                conv_load_step<WM, WN>(s0, kk + 2, kpt, in, pbase, py, px, pok, H, W, Cin, wrow, cok, kq);
+            conv_mfma_step<WM, WN>(acc, s1);
         }
     }
     // D layout: lane holds rows 4 * kq + i (pixels), column r16 (channel)
@@ -151,29 +229,68 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
         for (int c = 0; c < WN; ++c) {
             const int co = c0 + c * 16 + r16;
             if (co >= Cout) continue;
-            const float bv = BIAS_RELU ? bias[co] : 0.0f;
+            if constexpr (EPI == kEpiPool) {
+                const int64_t q = (p0 >> 2) + r * 4 + kq;  // this lane's quad
+                if (4 * q >= npix) continue;
+                const float bv = bias[co];
+                float s4 = 0.0f;
+                unsigned m = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t p = p0 + r * 16 + 4 * kq + i;
-                if (p >= npix) continue;
-                float v = acc[r][c][i] + bv;
-                if (BIAS_RELU) v = fmaxf(v, 0.0f);
-                out[p * Cout + co] = f2bf(v);
+                for (int i = 0; i < 4; ++i) {
+                    const float a = bf2f(f2bf(fmaxf(acc[r][c][i] + bv, 0.0f)));
+                    s4 += a;
+                    m |= (a > 0.0f ? 1u : 0u) << i;
+                }
+                out[q * Cout + co] = f2bf(0.25f * s4);
+                mask_out[q * Cout + co] = uint8_t(m);
+            } else if constexpr (EPI == kEpiExpand) {
+                // output pixels are the pooled grid (H x W) of a 2H x 2W layer
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t p = p0 + r * 16 + 4 * kq + i;
+                    if (p >= npix) continue;
+                    const float g = 0.25f * bf2f(f2bf(acc[r][c][i]));
+                    const u16 h = f2bf(g);
+                    const unsigned m = mask_in[p * Cout + co];
+                    const int x = int(p % W), y = int((p / W) % H);
+                    const int64_t n = p / (int64_t(H) * W);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const int64_t o = ((n * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * Cout + co;
+                        out[o] = (m >> d) & 1u ? h : u16(0);
+                    }
+                }
+            } else {
+                const float bv = EPI == kEpiStore ? bias[co] : 0.0f;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int64_t p = p0 + r * 16 + 4 * kq + i;
+                    if (p >= npix) continue;
+                    float v = acc[r][c][i] + bv;
+                    if (EPI == kEpiStore) v = fmaxf(v, 0.0f);
+                    out[p * Cout + co] = f2bf(v);
+                }
             }
         }
 }
 
 constexpr int kConvWM = 4, kConvWN = 4;  // 64 pixels x 64 channels per wavefront
 
+// four wavefronts of WM * 16 pixels per workgroup along x, WN * 16 channels along y
+inline dim3 conv_grid(int64_t npix, int cout) {
+    return dim3(unsigned((npix + 64 * kConvWM - 1) / (64 * kConvWM)), unsigned((cout + 16 * kConvWN - 1) / (16 * kConvWN)));
+}
+
 // ------------------------------------------------------- weight gradient
 // dw[co, tap, ci] = sum_p dout[p, co] * in[shift(p, tap), ci], split over
 // pixel ranges: partial[split][co][tap][ci] (FP32).  Workgroup tile: 64 co x
 // 64 ci for one tap; K = 64 pixels per LDS stage.
 __global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u16 *dout, float *partial,
-                                                         int B, int H, int W, int Cin, int Cout,
-                                                         int64_t pix_per_split) {
+                                                         float *bias_partial, int B, int H, int W, int Cin,
+                                                         int Cout, int64_t pix_per_split) {
     __shared__ u16 sd[64][64 + 8];  // [co][pixel]
     __shared__ u16 sx[64][64 + 8];  // [ci][pixel]
+    __shared__ float sb[4][64];     // bias sums per wavefront
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int co_t = blockIdx.x * 64, ci_t = (blockIdx.y % ((Cin + 63) / 64)) * 64;
@@ -185,6 +302,12 @@ __global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u
     const int64_t pend = pbeg + pix_per_split < npix ? pbeg + pix_per_split : npix;
     const int r16 = lane & 15, kq = lane >> 4;
     const int wco = (wv >> 1) * 32, wci = (wv & 1) * 32;
+    // the centre-tap workgroups of the first input-channel tile also sum
+    // dout over their pixels: the bias gradient
+    const bool do_bias = tap == 4 && ci_t == 0;
+    float bsum[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) bsum[e] = 0.0f;
     f32x4 acc[2][2];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
@@ -213,6 +336,10 @@ __global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u
             for (int e = 0; e < 8; ++e) {
                 sd[cc + e][lp] = ed[e];
                 sx[cc + e][lp] = ex[e];
+            }
+            if (do_bias) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bsum[8 * h + e] += bf2f(ed[e]);
             }
         }
         __syncthreads();
@@ -244,83 +371,94 @@ __global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u
                 if (co >= Cout) continue;
                 partial[((int64_t(split) * Cout + co) * 9 + tap) * Cin + ci] = acc[r][c][i];
             }
+        }    if (do_bias) {  // uniform per workgroup
+        // lanes with equal lane % 4 hold the same 16 channels: butterfly
+        // over the other lane bits, then the four wavefronts in order
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            float v = bsum[e];
+#pragma unroll
+            for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            bsum[e] = v;
         }
+        if (lane < 4) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) sb[wv][lane * 16 + e] = bsum[e];
+        }
+        __syncthreads();
+        if (threadIdx.x < 64 && co_t + int(threadIdx.x) < Cout) {
+            const float t = ((sb[0][threadIdx.x] + sb[1][threadIdx.x]) + sb[2][threadIdx.x]) + sb[3][threadIdx.x];
+            bias_partial[int64_t(split) * Cout + co_t + threadIdx.x] = t;
+        }
+    }
 }
 
-// Fixed-order sum of split partials (and bias gradient partials).
+// Fixed-order sum of split partials: four interleaved running sums (splits
+// k = 0, 1, 2, 3 mod 4) so the loads overlap, combined as (s0 + s1) + (s2 + s3).
 __global__ __launch_bounds__(kBlk) void k_sum_splits(const float *partial, float *out, int64_t n, int splits) {
     const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
     if (i >= n) return;
-    float s = 0.0f;
-    for (int k = 0; k < splits; ++k) s += partial[int64_t(k) * n + i];
-    out[i] = s;
-}
-
-// db[c] partials: column sums of a [npix, C] BF16 matrix over pixel chunks.
-// Thread t reads channel t % C of pixels t / C, t / C + 256 / C, ... (rows
-// are contiguous, so a wavefront reads whole rows); the 256 / C partial sums
-// of a channel are then added in a fixed order.
-__global__ __launch_bounds__(kBlk) void k_colsum_bf16(const u16 *g, float *partial, int64_t npix, int C,
-                                                     int64_t pix_per_split) {
-    __shared__ float red[kBlk];
-    const int c = threadIdx.x % C;
-    const int lanes = kBlk / C;  // pixels read per pass (C divides 256)
-    const int sub = threadIdx.x / C;
-    const int64_t b0 = int64_t(blockIdx.x) * pix_per_split;
-    const int64_t b1 = b0 + pix_per_split < npix ? b0 + pix_per_split : npix;
-    float s = 0.0f;
-    if (sub < lanes)
-        for (int64_t p = b0 + sub; p < b1; p += lanes) s += bf2f(g[p * C + c]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < C) {
-        float t = 0.0f;
-        for (int k = 0; k < lanes; ++k) t += red[k * C + threadIdx.x];
-        partial[int64_t(blockIdx.x) * C + threadIdx.x] = t;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int k = 0;
+    for (; k + 4 <= splits; k += 4) {
+        s0 += partial[int64_t(k) * n + i];
+        s1 += partial[int64_t(k + 1) * n + i];
+        s2 += partial[int64_t(k + 2) * n + i];
+        s3 += partial[int64_t(k + 3) * n + i];
     }
+    for (; k < splits; ++k) s0 += partial[int64_t(k) * n + i];
+    out[i] = (s0 + s1) + (s2 + s3);
 }
 
 // Weight gradient of the one-channel first layer: partials [split][co][10]
 // (9 taps, then the bias).  Wavefront w of a workgroup handles channels
-// 8 w .. 8 w + 7 (workgroups along y cover further groups); its 64 lanes
-// stride over the split's pixels and the lane sums are combined by a fixed
-// wavefront reduction.
+// 8 w .. 8 w + 7 (workgroups along y cover further groups).
 __device__ inline float wave_sum_f(float x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
     return x;
 }
 
-__global__ __launch_bounds__(kBlk) void k_conv1_wgrad(const uint8_t *x, const u16 *dout, float *partial, int B,
-                                                     int H, int W, int C, int64_t pix_per_split) {
+// Backward of the fused first layer: from the pooled gradient dpool, the
+// conv-output gradient of sub-pixel d is bf16(dpool / 4) where the
+// recomputed BF16 ReLU output is positive, else 0; it is multiplied into the
+// 9 image taps and the bias.  Pooled pixels of a split are strided over the
+// lanes; a fixed wavefront reduction combines the lanes.
+__global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const float *w, const float *b,
+                                                   const u16 *dpool, float *partial, int B, int H, int W, int C,
+                                                   int64_t q_per_split) {
     const int lane = threadIdx.x & 63;
     const int grp = (blockIdx.y * (kBlk / 64)) + (threadIdx.x >> 6);
     if (grp * 8 >= C) return;  // whole wavefronts leave together
-    const int64_t npix = int64_t(B) * H * W;
-    const int64_t b0 = int64_t(blockIdx.x) * pix_per_split;
-    const int64_t b1 = b0 + pix_per_split < npix ? b0 + pix_per_split : npix;
+    const int Ho = H / 2, Wo = W / 2;
+    const int64_t nq = int64_t(B) * Ho * Wo;
+    const int64_t b0 = int64_t(blockIdx.x) * q_per_split;
+    const int64_t b1 = b0 + q_per_split < nq ? b0 + q_per_split : nq;
     float acc[8][10];
 #pragma unroll
     for (int e = 0; e < 8; ++e)
 #pragma unroll
         for (int k = 0; k < 10; ++k) acc[e][k] = 0.0f;
-    for (int64_t p = b0 + lane; p < b1; p += 64) {
-        const uint4 gv = *reinterpret_cast<const uint4 *>(dout + p * C + grp * 8);
+    for (int64_t q = b0 + lane; q < b1; q += 64) {
+        const uint4 gv = *reinterpret_cast<const uint4 *>(dpool + q * C + grp * 8);
         const u16 *gh = reinterpret_cast<const u16 *>(&gv);
-        const int xx = int(p % W), yy = int((p / W) % H);
-        const int64_t n = p / (int64_t(H) * W);
-        float v[10];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int sy = yy + t / 3 - 1, sx = xx + t % 3 - 1;
-            v[t] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
-        }
-        v[9] = 1.0f;
+        const int xo = int(q % Wo), yo = int((q / Wo) % Ho);
+        const int64_t n = q / (int64_t(Ho) * Wo);
+        float v[4][4];
+        conv1_patch(x, H, W, n, yo, xo, v);
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const float g = bf2f(gh[e]);
+            const int c = grp * 8 + e;
+            const float g = 0.25f * bf2f(gh[e]);
 #pragma unroll
-            for (int k = 0; k < 10; ++k) acc[e][k] = fmaf(g, v[k], acc[e][k]);
+            for (int d = 0; d < 4; ++d) {
+                const int dy = d >> 1, dx = d & 1;
+                const float act = bf2f(f2bf(fmaxf(conv1_at(w, b, c, v, dy, dx), 0.0f)));
+                const float da = bf2f(f2bf(act > 0.0f ? g : 0.0f));
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc[e][t] = fmaf(da, v[dy + t / 3][dx + t % 3], acc[e][t]);
+                acc[e][9] += da;
+            }
         }
     }
 #pragma unroll
@@ -333,40 +471,6 @@ __global__ __launch_bounds__(kBlk) void k_conv1_wgrad(const uint8_t *x, const u1
 }
 
 // ------------------------------------------------------ pooling and GAP
-__global__ __launch_bounds__(kBlk) void k_pool2_fwd(const u16 *in, u16 *out, int B, int H, int W, int C) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    const int Ho = H / 2, Wo = W / 2;
-    if (i >= int64_t(B) * Ho * Wo * C) return;
-    const int c = int(i % C);
-    const int64_t q = i / C;
-    const int xo = int(q % Wo), yo = int((q / Wo) % Ho);
-    const int64_t n = q / (int64_t(Ho) * Wo);
-    float s = 0.0f;
-#pragma unroll
-    for (int d = 0; d < 4; ++d) s += bf2f(in[((n * H + 2 * yo + d / 2) * W + 2 * xo + d % 2) * C + c]);
-    out[i] = f2bf(0.25f * s);
-}
-
-// gradient of pooling, times the ReLU mask of the pooled layer's output
-__global__ __launch_bounds__(kBlk) void k_pool2_bwd_relu(const u16 *dpool, const u16 *act, u16 *dact, int B, int H,
-                                                        int W, int C) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (i >= int64_t(B) * H * W * C) return;
-    const int c = int(i % C);
-    const int64_t q = i / C;
-    const int x = int(q % W), y = int((q / W) % H);
-    const int64_t n = q / (int64_t(H) * W);
-    const float g = 0.25f * bf2f(dpool[((n * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c]);
-    dact[i] = f2bf(bf2f(act[i]) > 0.0f ? g : 0.0f);
-}
-
-// ReLU mask applied to an input gradient in place
-__global__ __launch_bounds__(kBlk) void k_relu_mask(u16 *g, const u16 *act, int64_t n) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (i >= n) return;
-    if (!(bf2f(act[i]) > 0.0f)) g[i] = 0;
-}
-
 __global__ __launch_bounds__(kBlk) void k_gap_fwd(const u16 *in, float *out, int B, int HW, int C) {
     const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
     if (i >= int64_t(B) * C) return;
@@ -512,8 +616,11 @@ struct lsm_cnn {
     // device
     float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     u16 *wf[kLayers]{}, *wd[kLayers]{};
-    u16 *act[kLayers]{}, *pool[kLayers]{};    // conv outputs (post ReLU) and pooled
-    u16 *dact[kLayers]{}, *dpool[kLayers]{};  // their gradients
+    // act: last conv output (post ReLU); pool: pooled outputs of the other
+    // layers; mask: their ReLU masks (4 bits per pooled pixel and channel);
+    // dact: conv output gradients; dpool: gradient of the first pooled map
+    u16 *act = nullptr, *pool[kLayers]{}, *dact[kLayers]{}, *dpool0 = nullptr;
+    uint8_t *mask[kLayers]{};
     float *gap = nullptr, *h1 = nullptr, *y = nullptr;
     float *dgap = nullptr, *dh1 = nullptr, *dy = nullptr;
     float *part = nullptr;
@@ -554,12 +661,17 @@ size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
     s.push_back(P * 4);  // v
     for (int l = 1; l < kLayers; ++l) s.push_back(size_t(c->w_n[l]) * 2);  // wf
     for (int l = 1; l < kLayers; ++l) s.push_back(size_t(c->w_n[l]) * 2);  // wd
+    // full-resolution conv outputs are stored only for the last layer; the
+    // others are pooled in the conv epilogue (the first layer's is
+    // recomputed in the backward pass, the others keep a ReLU mask)
+    const int L = kLayers - 1;
+    s.push_back(size_t(B * c->Hs[L] * c->Hs[L] * c->C[L + 1]) * 2);  // act
+    s.push_back(size_t(B * c->Hs[0] * c->Hs[0] / 4 * c->C[1]) * 2);  // dpool0
     for (int l = 0; l < kLayers; ++l) {
         const int64_t hw = int64_t(c->Hs[l]) * c->Hs[l];
-        s.push_back(size_t(B * hw * c->C[l + 1]) * 2);  // act
-        s.push_back(size_t(B * hw * c->C[l + 1]) * 2);  // dact
-        s.push_back(size_t(B * hw / 4 * c->C[l + 1]) * 2);  // pool
-        s.push_back(size_t(B * hw / 4 * c->C[l + 1]) * 2);  // dpool
+        s.push_back(l > 0 ? size_t(B * hw * c->C[l + 1]) * 2 : 0);       // dact
+        s.push_back(l < L ? size_t(B * hw / 4 * c->C[l + 1]) * 2 : 0);   // pool
+        s.push_back(l > 0 && l < L ? size_t(B * hw / 4 * c->C[l + 1]) : 0);  // mask
     }
     const int hid = c->cfg.hidden, out = c->cfg.outputs;
     s.push_back(size_t(B) * c->C[kLayers] * 4);  // gap
@@ -677,11 +789,12 @@ int lsm_cnn_bind(lsm_cnn *c, void *dptr, size_t bytes, void *hip_stream) {
     c->v = reinterpret_cast<float *>(take());
     for (int l = 1; l < kLayers; ++l) c->wf[l] = reinterpret_cast<u16 *>(take());
     for (int l = 1; l < kLayers; ++l) c->wd[l] = reinterpret_cast<u16 *>(take());
+    c->act = reinterpret_cast<u16 *>(take());
+    c->dpool0 = reinterpret_cast<u16 *>(take());
     for (int l = 0; l < kLayers; ++l) {
-        c->act[l] = reinterpret_cast<u16 *>(take());
         c->dact[l] = reinterpret_cast<u16 *>(take());
         c->pool[l] = reinterpret_cast<u16 *>(take());
-        c->dpool[l] = reinterpret_cast<u16 *>(take());
+        c->mask[l] = reinterpret_cast<uint8_t *>(take());
     }
     c->gap = reinterpret_cast<float *>(take());
     c->dgap = reinterpret_cast<float *>(take());
@@ -737,27 +850,24 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
     if (batch < 1 || batch > c->cfg.batch) return cfail(c, LSM_EINVAL, "batch out of range");
     const int B = int(batch);
     const int H0 = c->Hs[0];
-    hipLaunchKernelGGL(k_conv1_fwd, dim3(nblk(int64_t(B) * H0 * H0)), dim3(kBlk), 0, c->stream, x,
-                       c->p + c->w_off[0], c->p + c->b_off[0], c->act[0], B, H0, H0, c->C[1]);
+    hipLaunchKernelGGL(k_conv1_pool_fwd, dim3(nblk(int64_t(B) * (H0 / 2) * (H0 / 2))), dim3(kBlk), 0, c->stream,
+                       x, c->p + c->w_off[0], c->p + c->b_off[0], c->pool[0], B, H0, H0, c->C[1]);
     CHIP(c, hipGetLastError());
-    for (int l = 0; l < kLayers; ++l) {
+    for (int l = 1; l < kLayers; ++l) {
         const int H = c->Hs[l];
-        if (l > 0) {
-            const int64_t npix = int64_t(B) * H * H;
-            const dim3 grid(unsigned((npix + 64 * kConvWM - 1) / (64 * kConvWM)),
-                            unsigned((c->C[l + 1] + 16 * kConvWN - 1) / (16 * kConvWN)));
-            hipLaunchKernelGGL((k_conv_mfma<true, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->wf[l],
-                               c->p + c->b_off[l], c->act[l], B, H, H, c->C[l], c->C[l + 1]);
-            CHIP(c, hipGetLastError());
-        }
-        if (l < kLayers - 1) {
-            hipLaunchKernelGGL(k_pool2_fwd, dim3(nblk(int64_t(B) * (H / 2) * (H / 2) * c->C[l + 1])), dim3(kBlk), 0,
-                               c->stream, c->act[l], c->pool[l], B, H, H, c->C[l + 1]);
-            CHIP(c, hipGetLastError());
-        }
+        const dim3 grid = conv_grid(int64_t(B) * H * H, c->C[l + 1]);
+        if (l < kLayers - 1)
+            hipLaunchKernelGGL((k_conv_mfma<kEpiPool, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream,
+                               c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->pool[l], nullptr, c->mask[l], B, H, H,
+                               c->C[l], c->C[l + 1]);
+        else
+            hipLaunchKernelGGL((k_conv_mfma<kEpiStore, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream,
+                               c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->act, nullptr, nullptr, B, H, H,
+                               c->C[l], c->C[l + 1]);
+        CHIP(c, hipGetLastError());
     }
     const int HL = c->Hs[kLayers - 1], CL = c->C[kLayers];
-    hipLaunchKernelGGL(k_gap_fwd, dim3(nblk(int64_t(B) * CL)), dim3(kBlk), 0, c->stream, c->act[kLayers - 1], c->gap,
+    hipLaunchKernelGGL(k_gap_fwd, dim3(nblk(int64_t(B) * CL)), dim3(kBlk), 0, c->stream, c->act, c->gap,
                        B, HL * HL, CL);
     const int hid = c->cfg.hidden, out = c->cfg.outputs;
     hipLaunchKernelGGL(k_fc_fwd, dim3(nblk(int64_t(B) * hid)), dim3(kBlk), 0, c->stream, c->gap,
@@ -803,7 +913,7 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
     CHIP(c, hipGetLastError());
     const int HL = c->Hs[kLayers - 1];
     hipLaunchKernelGGL(k_gap_bwd_relu, dim3(nblk(int64_t(B) * HL * HL * CL)), dim3(kBlk), 0, c->stream, c->dgap,
-                       c->act[kLayers - 1], c->dact[kLayers - 1], B, HL * HL, CL);
+                       c->act, c->dact[kLayers - 1], B, HL * HL, CL);
     CHIP(c, hipGetLastError());
     for (int l = kLayers - 1; l >= 0; --l) {
         const int H = c->Hs[l];
@@ -813,33 +923,33 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
         if (l > 0) {
             // weight gradient: MFMA over pixel splits, then a fixed-order sum
             const dim3 grid(unsigned((cout + 63) / 64), unsigned(9 * ((cin + 63) / 64)), unsigned(sp));
+            float *bias_part = c->part + sp * nw;  // [split][co] after the weight partials
             hipLaunchKernelGGL(k_conv_wgrad_mfma, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l], c->part,
-                               B, H, H, int(cin), int(cout), int64_t(kSplitPix));
+                               bias_part, B, H, H, int(cin), int(cout), int64_t(kSplitPix));
             CHIP(c, hipGetLastError());
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
                                int(sp));
-            // bias gradient
-            hipLaunchKernelGGL(k_colsum_bf16, dim3(unsigned(sp)), dim3(kBlk), 0, c->stream, c->dact[l], c->part, npix,
-                               int(cout), int64_t(kSplitPix));
-            hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout)), dim3(kBlk), 0, c->stream, c->part, c->g + c->b_off[l],
-                               cout, int(sp));
+            hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout)), dim3(kBlk), 0, c->stream, bias_part,
+                               c->g + c->b_off[l], cout, int(sp));
             CHIP(c, hipGetLastError());
-            // input gradient: implicit GEMM with the flipped weights, then the
-            // pooling and ReLU of the layer below
-            const int64_t npin = npix;
-            const dim3 g2(unsigned((npin + 64 * kConvWM - 1) / (64 * kConvWM)),
-                          unsigned((cin + 16 * kConvWN - 1) / (16 * kConvWN)));
-            hipLaunchKernelGGL((k_conv_mfma<false, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
-                               c->dpool[l - 1], B, H, H, int(cout), int(cin));
-            CHIP(c, hipGetLastError());
-            const int Hp = c->Hs[l - 1];
-            hipLaunchKernelGGL(k_pool2_bwd_relu, dim3(nblk(int64_t(B) * Hp * Hp * cin)), dim3(kBlk), 0, c->stream,
-                               c->dpool[l - 1], c->act[l - 1], c->dact[l - 1], B, Hp, Hp, int(cin));
+            // input gradient: implicit GEMM with the flipped weights; its
+            // epilogue applies the pooling and ReLU of the layer below (the
+            // first layer's backward takes the pooled gradient itself)
+            const dim3 g2 = conv_grid(npix, int(cin));
+            if (l > 1)
+                hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
+                                   c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
+                                   int(cout), int(cin));
+            else
+                hipLaunchKernelGGL((k_conv_mfma<kEpiRaw, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
+                                   c->dact[l], c->wd[l], nullptr, c->dpool0, nullptr, nullptr, B, H, H, int(cout),
+                                   int(cin));
             CHIP(c, hipGetLastError());
         } else {
             const unsigned groups = unsigned((cout / 8 + kBlk / 64 - 1) / (kBlk / 64));
-            hipLaunchKernelGGL(k_conv1_wgrad, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
-                               c->dact[0], c->part, B, H, H, int(cout), int64_t(kSplitPix));
+            hipLaunchKernelGGL(k_conv1_bwd, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
+                               c->p + c->w_off[0], c->p + c->b_off[0], c->dpool0, c->part, B, H, H, int(cout),
+                               int64_t(kSplitPix / 4));
             // part layout [split][co][10]: taps then bias
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout * 10)), dim3(kBlk), 0, c->stream, c->part,
                                c->part + sp * cout * 10, cout * 10, int(sp));
@@ -879,10 +989,9 @@ int lsm_cnn_conv_forward(lsm_cnn *c, int layer, const void *in, void *out, int64
     if (!c->bound) return cfail(c, LSM_ESTATE, "bind first");
     const int H = c->Hs[layer];
     const int64_t npix = batch * H * H;
-    const dim3 grid(unsigned((npix + 64 * kConvWM - 1) / (64 * kConvWM)),
-                    unsigned((c->C[layer + 1] + 16 * kConvWN - 1) / (16 * kConvWN)));
-    hipLaunchKernelGGL((k_conv_mfma<true, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream, static_cast<const u16 *>(in), c->wf[layer],
-                       c->p + c->b_off[layer], static_cast<u16 *>(out), int(batch), H, H, c->C[layer], c->C[layer + 1]);
+    hipLaunchKernelGGL((k_conv_mfma<kEpiStore, kConvWM, kConvWN>), conv_grid(npix, c->C[layer + 1]), dim3(kBlk), 0,
+                       c->stream, static_cast<const u16 *>(in), c->wf[layer], c->p + c->b_off[layer],
+                       static_cast<u16 *>(out), nullptr, nullptr, int(batch), H, H, c->C[layer], c->C[layer + 1]);
     CHIP(c, hipGetLastError());
     return LSM_OK;
 }

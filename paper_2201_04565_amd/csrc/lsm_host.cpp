@@ -66,6 +66,9 @@ struct lsm_handle {
     uint8_t *d_flags = nullptr;
     void *d_mask = nullptr;
     uint32_t *d_sbase = nullptr;
+    uint32_t *d_plist = nullptr;      // packed site coordinates per particle (3D gather)
+    std::vector<uint32_t> plist;      // host copy; empty: site-grid launch
+    int c_blocks = 0;
     void *d_U[2] = {nullptr, nullptr};
     void *d_V = nullptr, *d_A = nullptr;
     double *d_f64 = nullptr, *d_partials = nullptr;
@@ -202,7 +205,10 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     p.sw_strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
     p.sw_nwork = p.sw_strips * int((h->ny + h->sw_rows - 1) / h->sw_rows);
     p.sw_nblocks = ((p.sw_nwork + 4 * 8 - 1) / (4 * 8)) * 8;
-    p.red_blocks = p.nblocks;
+    p.n_part = int32_t(h->n);
+    p.plist = h->plist.empty() ? nullptr : h->d_plist;
+    p.c_blocks = h->c_blocks;
+    p.red_blocks = p.plist ? p.c_blocks : p.nblocks;
     return p;
 }
 
@@ -214,7 +220,7 @@ hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_l
         p.red_blocks = int(h->ny) * p.sw_strips;  // one partial per (row, strip)
         return lsm::launch_sweep2d(p, h->prec, mode, h->stream, step_local);
     }
-    p.red_blocks = p.nblocks;
+    p.red_blocks = p.plist ? p.c_blocks : p.nblocks;
     return lsm::launch_step(p, h->dim, h->prec, mode, h->stream, step_local);
 }
 
@@ -222,7 +228,7 @@ hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_l
 int max_red_blocks(const lsm_handle *h) {
     const int strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
     const int sweep_partials = h->dim == 2 ? int(h->ny) * strips : 0;
-    return std::max(h->nblocks, sweep_partials);
+    return std::max(std::max(h->nblocks, sweep_partials), h->c_blocks);
 }
 
 int sync(lsm_handle *h) {
@@ -402,6 +408,20 @@ int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t n
         if (m >= (int64_t(1) << 32) - 1) return fail(h, LSM_EINVAL, "too many springs");
     }
     h->m = m;
+    // 3D lattices are mostly void in porous specimens: the gather kernel runs
+    // one thread per particle from a packed coordinate list when the
+    // dimensions fit its 10/11/11-bit fields
+    h->plist.clear();
+    h->c_blocks = 0;
+    if (h->dim == 3 && nx <= 1024 && ny <= 2048 && nz <= 2048 && h->n > 0) {
+        h->plist.resize(size_t(h->n));
+        for (int64_t c = 0; c < h->n; ++c) {
+            const int64_t g = h->site_of[size_t(c)];
+            const int64_t i = g % nx, j = (g / nx) % ny, k = g / (nx * ny);
+            h->plist[size_t(c)] = uint32_t(i) | (uint32_t(j) << 10) | (uint32_t(k) << 21);
+        }
+        h->c_blocks = int(((h->n + 255) / 256 + 7) / 8) * 8;
+    }
     h->tiles_x = int((nx + lsm::kTileX - 1) / lsm::kTileX);
     h->tiles_y = int((ny + lsm::kTileY - 1) / lsm::kTileY);
     h->ntiles = h->tiles_x * h->tiles_y * int(nz);
@@ -428,10 +448,12 @@ int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
     return LSM_OK;
 }
 
-static size_t layout(const lsm_handle *h, size_t *off /* 13 offsets */) {
+constexpr int kRegions = 14;
+
+static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
     size_t o = 0;
     const size_t ns = size_t(h->nsites);
-    size_t sizes[13] = {
+    size_t sizes[kRegions] = {
         sizeof(Ctl),                                  // 0 ctl
         sizeof(DevRecord),                            // 1 record
         sizeof(TypeRec) * lsm::kMaxTypes,             // 2 types
@@ -445,8 +467,9 @@ static size_t layout(const lsm_handle *h, size_t *off /* 13 offsets */) {
         ns * size_t(h->dim) * 8,                      // 10 f64
         size_t(max_red_blocks(h)) * lsm::kNumPartials * 8,  // 11 partials
         size_t(std::max<int64_t>(h->m, 1)) * sizeof(lsm_event),  // 12 events
+        h->plist.size() * 4,                          // 13 particle list
     };
-    for (int i = 0; i < 13; ++i) {
+    for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
         o += align256(sizes[i]);
     }
@@ -456,7 +479,7 @@ static size_t layout(const lsm_handle *h, size_t *off /* 13 offsets */) {
 int lsm_workspace_bytes(const lsm_handle *h, size_t *bytes) {
     if (!h || !bytes) return LSM_EINVAL;
     if (!h->built) return LSM_ESTATE;
-    size_t off[13];
+    size_t off[kRegions];
     *bytes = layout(h, off);
     return LSM_OK;
 }
@@ -466,7 +489,7 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     if (!h->built) return fail(h, LSM_ESTATE, "build the lattice first");
     if (h->bound) return fail(h, LSM_ESTATE, "already bound");
     if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return fail(h, LSM_EINVAL, "workspace must be 256-byte aligned");
-    size_t off[13];
+    size_t off[kRegions];
     const size_t need = layout(h, off);
     if (bytes < need) return fail(h, LSM_ENOMEM, "workspace too small");
     char *w = static_cast<char *>(dptr);
@@ -486,10 +509,13 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_f64 = reinterpret_cast<double *>(w + off[10]);
     h->d_partials = reinterpret_cast<double *>(w + off[11]);
     h->d_events = reinterpret_cast<lsm_event *>(w + off[12]);
+    h->d_plist = reinterpret_cast<uint32_t *>(w + off[13]);
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (!h->plist.empty())
+        HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->cur = 0;
     h->half = false;
@@ -1052,8 +1078,9 @@ int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
 int lsm_step_bytes(const lsm_handle *h, int64_t *bytes) {
     if (!h || !bytes) return LSM_EINVAL;
     if (!h->built) return LSM_ESTATE;
-    // per particle: displacement and velocity read and written, flag byte, break mask
-    *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb);
+    // per particle: displacement and velocity read and written, flag byte,
+    // break mask, and its packed coordinates in particle-list mode
+    *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb + (h->plist.empty() ? 0 : 4));
     return LSM_OK;
 }
 

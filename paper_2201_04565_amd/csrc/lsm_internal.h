@@ -85,7 +85,12 @@ struct StepParams {
     // columns of a strip and sw_rows rows, sweeping upward
     int32_t sw_strips, sw_rows, sw_nwork, sw_nblocks;
     int32_t sw_pf;          // rows prefetched ahead by each wavefront (1..3)
-    int32_t pad2;
+    // particle-list mode of the gather kernel (3D): one thread per particle,
+    // plist[p] = i | j << 10 | k << 21 of particle p (raster order)
+    int32_t n_part;
+    const uint32_t *plist;  // null: one thread per grid site
+    int32_t c_blocks;       // workgroups of the particle-list grid (multiple of 8)
+    int32_t pad3;
     // batch of specimens (2D sweep only)
     const SweepItem *items;  // active work items
     const int32_t *n_items;  // number of active work items (device)

@@ -335,7 +335,20 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 
     int i, j, k;
     bool active;
-    tile_coords(P, i, j, k, active);
+    if (P.plist) {
+        // one thread per particle; each XCD takes a contiguous run of
+        // workgroups (particles of neighbouring rows and planes share its L2)
+        const int b = blockIdx.x;
+        const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
+        const int64_t t = int64_t(lb) * kBlock + threadIdx.x;
+        active = t < P.n_part;
+        const uint32_t pc = active ? P.plist[t] : 0u;
+        i = int(pc & 1023u);
+        j = int((pc >> 10) & 2047u);
+        k = int(pc >> 21);
+    } else {
+        tile_coords(P, i, j, k, active);
+    }
     const int g = active ? i + P.nx * (j + P.ny * k) : 0;
     const uint8_t fp = active ? P.flags[g] : kVoid;
     active = active && fp != kVoid;
@@ -966,7 +979,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 
 template <int DIM, int PREC>
 hipError_t launch_step_t(const StepParams &p, int mode, hipStream_t s, int step_local) {
-    const dim3 grid(p.nblocks), block(kBlock);
+    const dim3 grid(p.plist ? p.c_blocks : p.nblocks), block(kBlock);
     switch (mode) {
         case kStart: hipLaunchKernelGGL((k_step<DIM, PREC, kStart>), grid, block, 0, s, p, step_local); break;
         case kMid: hipLaunchKernelGGL((k_step<DIM, PREC, kMid>), grid, block, 0, s, p, step_local); break;

@@ -41,7 +41,7 @@ class Labels:
 
 
 def label(images: np.ndarray, chunk: int = 8192, steps: int = 500, d_eps: float = 0.005,
-          device: str = "cuda:0") -> Labels:
+          device: str = "cuda:0", log=None) -> Labels:
     """Runs the batched model on every image to CURVE_POINTS increments."""
     import torch
 
@@ -57,6 +57,8 @@ def label(images: np.ndarray, chunk: int = 8192, steps: int = 500, d_eps: float 
         torch.cuda.synchronize()
         secs += time.perf_counter() - t0
         r = b.read()
+        if log is not None:
+            log(f"labelled {min(s + chunk, len(images))}/{len(images)} specimens ({secs:.1f} s)")
         cur.append(r["sigma_xx"])
         mod.append(r["modulus"])
         st.append(r["strength"])
@@ -84,11 +86,15 @@ class Surrogate:
     """K networks; mean prediction and modulus spread."""
 
     def __init__(self, k: int = 5, size: int = SIZE, batch: int = 512,
-                 outputs: int = CURVE_POINTS + 1, device: str = "cuda:0", seed: int = 0):
+                 outputs: int = CURVE_POINTS + 1, device: str = "cuda:0", seed: int = 0,
+                 modulus_weight: float = 4.0):
         import torch
 
         self.torch = torch
         self.k, self.batch, self.device = k, batch, device
+        # the modulus is one output of 65: scaling its standardised target by
+        # w weights it w^2 in the mean squared error
+        self.modulus_weight = modulus_weight
         self.nets = [cnn.Network(size=size, batch=batch, outputs=outputs, device=device)
                      for _ in range(k)]
         for i, n in enumerate(self.nets):
@@ -103,6 +109,7 @@ class Surrogate:
         torch = self.torch
         self.mu = y.mean(axis=0)
         self.sd = y.std(axis=0) + 1e-12
+        self.sd[-1] /= self.modulus_weight
         x = torch.from_numpy(np.ascontiguousarray(images)).to(self.device)
         t = torch.from_numpy(((y - self.mu) / self.sd).astype(np.float32)).to(self.device)
         n = len(images)

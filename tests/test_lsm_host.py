@@ -81,6 +81,18 @@ def test_c2_full_size_counts():
     assert g.step_bytes() == 4194304 * 50
 
 
+def test_3d_step_bytes_count_the_particle_list():
+    # 3D fp32k: u (24 B) and v (12 B) read and written, flag, 4-byte break
+    # mask, and the packed coordinates of the one-thread-per-particle launch
+    img = inputs.gaussian_random_field_3d(24, seed=3)
+    wl = inputs.WORKLOADS["c3"]
+    g = _model(img, wl, precision="fp32k")
+    assert g.n == int((img != inputs.VOID).sum()) > 0
+    assert g.step_bytes() == g.n * (2 * (24 + 12) + 1 + 4 + 4)
+    g64 = _model(img, wl, precision="fp64")
+    assert g64.step_bytes() == g64.n * (2 * (24 + 24) + 1 + 4 + 4)
+
+
 def test_table2_paper_mode_types():
     # explicit interface constants (paper's spring table), r0 = 10
     k = [[2e-5, 1.25e-4], [1.25e-4, 2e-3]]
