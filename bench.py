@@ -83,6 +83,9 @@ def batched_c4(args, torch, inputs, lsm):
     imgs = inputs.batch_specimens(args.batch_n)
     sizes = np.array([im.shape[0] for im in imgs])
     b = lsm.Batch.from_workload(wl, imgs, precision="fp32k", device="cuda:0")
+    tune = b.autotune(20)
+    print(f"[bench] batch launch: rows {b.launch[0]}, prefetch {b.launch[1]}", file=sys.stderr,
+          flush=True)
     b.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -97,7 +100,9 @@ def batched_c4(args, torch, inputs, lsm):
                particles=b.n_particles, springs=b.n_springs, wall_s=wall,
                specimens_per_hour=len(imgs) / wall * 3600.0,
                mean_increments=float(n_inc.mean()),
-               step_graph_GBs=site_steps * 50 / (ms * 1e-3) / 1e9)
+               step_graph_GBs=site_steps * 50 / (ms * 1e-3) / 1e9,
+               launch=dict(rows_per_wave=b.launch[0], prefetch=b.launch[1]),
+               autotune_us_per_step={f"{r}x{p}": round(us, 1) for r, p, us in tune})
     del b
     torch.cuda.empty_cache()
     # plain: the same kernels, one specimen at a time, on a stratified sample

@@ -284,6 +284,19 @@ int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream);
  * results do not depend on them).                                         */
 int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch);
 
+/* Picks rows_per_wave and prefetch for this batch by timing candidate
+ * launches (rows 2..16 per wavefront x prefetch 1..2, those the bound
+ * workspace holds) on the live specimens, each over steps_per_trial
+ * (2..1000) interior steps, and keeps the fastest.  Bound, before the run.
+ * The trials read the state at rest and write only the second displacement
+ * buffer (rewritten by the first increment) and the velocities (zeroed
+ * afterwards), so the run's results are unchanged.  results (cap entries,
+ * may be NULL when cap = 0) receives {LSM_KERNEL_SWEEP, rows, prefetch, 0,
+ * mean microseconds per step} per candidate; *n_results their number.
+ * Synchronises the stream.                                               */
+int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, int cap,
+                       int *n_results);
+
 /* Runs every specimen to failure (rule may be NULL for drop 0.01).  Once
  * per batch; synchronises after every increment to apply the rule.        */
 int lsm_batch_run(lsm_batch *b, double d_eps, int64_t steps_per_inc, int32_t max_inc,

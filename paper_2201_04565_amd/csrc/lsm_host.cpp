@@ -1512,6 +1512,76 @@ int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch) {
     return b->bound ? upload_items(b) : LSM_OK;
 }
 
+int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, int cap, int *n_results) {
+    if (!b) return LSM_EINVAL;
+    if (!b->bound) return bfail(b, LSM_ESTATE, "bind the batch first");
+    if (b->ran) return bfail(b, LSM_ESTATE, "tune before the run");
+    if (steps_per_trial < 2 || steps_per_trial > kGraphChunk || cap < 0 || (cap > 0 && !results))
+        return bfail(b, LSM_EINVAL, "steps_per_trial must be 2..1000");
+    struct Cand { int rows, pf; };
+    std::vector<Cand> cands;
+    for (int rows : {2, 4, 6, 8, 12, 16})
+        for (int pf : {1, 2}) {
+            std::vector<SweepItem> tmp;
+            const int keep = b->sw_rows;
+            b->sw_rows = rows;
+            for (int64_t s = 0; s < b->nspec; ++s) batch_items_for(b, s, tmp);
+            b->sw_rows = keep;
+            if (tmp.size() <= b->max_items) cands.push_back({rows, pf});
+        }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIPCHK(b, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(b, LSM_EHIP, "hipEventCreate failed");
+    }
+    double best = 1e300;
+    Cand bestc = {b->sw_rows, b->sw_pf};
+    int nres = 0, rc = LSM_OK;
+    for (const Cand &c : cands) {
+        b->sw_rows = c.rows;
+        b->sw_pf = c.pf;
+        rc = upload_items(b);
+        if (rc) break;
+        const int capacity = int(b->items.size());
+        // every trial step reads the displacements at rest and writes the
+        // other buffer: plain launches, no graph
+        StepParams p = batch_params(b, b->cur, b->cur ^ 1);
+        hipError_t le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, 1, capacity);  // warm-up
+        if (le == hipSuccess) le = hipEventRecord(e0, b->stream);
+        for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s)
+            le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, 1 + s, capacity);
+        if (le == hipSuccess) le = hipEventRecord(e1, b->stream);
+        if (le == hipSuccess) le = hipStreamSynchronize(b->stream);
+        float ms = 0.0f;
+        if (le == hipSuccess) le = hipEventElapsedTime(&ms, e0, e1);
+        if (le != hipSuccess) {
+            rc = bfail(b, LSM_EHIP, std::string("autotune trial: ") + hipGetErrorString(le));
+            break;
+        }
+        const double us = 1e3 * double(ms) / steps_per_trial;
+        if (nres < cap) results[nres] = lsm_tuning{LSM_KERNEL_SWEEP, c.rows, c.pf, 0, us};
+        ++nres;
+        if (us < best) {
+            best = us;
+            bestc = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    b->sw_rows = bestc.rows;
+    b->sw_pf = bestc.pf;
+    drop_batch_graphs(b);
+    // the trials moved the velocities (tiny residual forces of the lattice at
+    // rest): back to the zero state of a fresh batch
+    BHIPCHK(b, hipMemsetAsync(b->d_V, 0, size_t(b->nsites) * 2 * (b->prec ? 4 : 8), b->stream));
+    rc = upload_items(b);  // synchronises
+    if (rc) return rc;
+    if (n_results) *n_results = nres;
+    return LSM_OK;
+}
+
 int lsm_batch_run(lsm_batch *b, double d_eps, int64_t steps_per_inc, int32_t max_inc,
                   const lsm_fail_rule *rule) {
     if (!b) return LSM_EINVAL;

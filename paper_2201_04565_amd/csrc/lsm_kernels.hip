@@ -253,6 +253,7 @@ __device__ inline void tile_coords(const StepParams &P, int &i, int &j, int &k, 
 // current positions.
 template <int DIM, int PREC, int MODE>
 __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, double mass,
+                                      typename State<DIM, PREC>::R inv_mass,
                                       typename State<DIM, PREC>::R *uph,
                                       typename State<DIM, PREC>::R *upl,
                                       const typename State<DIM, PREC>::R *F,
@@ -275,9 +276,8 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, do
     const R gam = R(P.gamma);
     R acc[DIM];
     if constexpr (PREC == 1) {
-        const R im = R(1.0 / mass);
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * im;
+        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * inv_mass;
     } else {
         const R m = R(mass);
 #pragma unroll
@@ -328,9 +328,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 
     __shared__ TTy tt[kMaxTypes];
     __shared__ double mass_s[LSM_MAX_PHASES];
+    __shared__ R imass_s[LSM_MAX_PHASES];  // R(1 / m), once per workgroup
     __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
     for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
-    if (threadIdx.x < LSM_MAX_PHASES) mass_s[threadIdx.x] = P.mass[threadIdx.x];
+    if (threadIdx.x < LSM_MAX_PHASES) {
+        mass_s[threadIdx.x] = P.mass[threadIdx.x];
+        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    }
     __syncthreads();
 
     int i, j, k;
@@ -475,7 +479,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
                 continue;
             }
             if constexpr (PREC == 1) {
-                const float rinv = rsqrtf(r2);
+                const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
                 const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, dv[c], F[c]);
@@ -519,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
         } else {
             R w[DIM];
             if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
-            integrate_site<DIM, PREC, MODE>(P, g, fp, mass_s[pa], uph, upl, F, w, red);
+            integrate_site<DIM, PREC, MODE>(P, g, fp, mass_s[pa], imass_s[pa], uph, upl, F, w, red);
         }
     }
 
@@ -673,23 +677,20 @@ template <int PREC>
 __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok,
                                       int jj, bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
     // Loads are unconditional from an always-valid site (the specimen's
-    // first site when the row or column is outside it) and masked
-    // afterwards, so no branch joins on a pending load.
+    // first site when the row or column is outside it), so no branch joins
+    // on a pending load.  Outside the specimen only the flag is replaced
+    // (void): springs with a void end and unowned sites never read the
+    // displacement or velocity of such a lane.
     using S = State<2, PREC>;
     using R = typename S::R;
     const bool ok = col_ok && jj >= 0 && jj < it.ny;
     const int g = it.base + (ok ? i + it.nx * jj : 0);
-    R uh[2], ul[2], v[2];
-    S::load_u(P.u_in, g, P.nsites, uh, ul);
+    S::load_u(P.u_in, g, P.nsites, r.uh, r.ul);
     const int f = P.flags[g];
     const int m = reinterpret_cast<const uint8_t *>(P.mask)[g];
-    if (want_v) S::load_v(P.v, g, P.nsites, v);
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        r.uh[c] = ok ? uh[c] : R(0);
-        r.ul[c] = ok ? ul[c] : R(0);
-        r.v[c] = (ok && want_v) ? v[c] : R(0);
-    }
+    r.v[0] = R(0);
+    r.v[1] = R(0);
+    if (want_v) S::load_v(P.v, g, P.nsites, r.v);
     r.f = ok ? f : int(kVoid);
     r.m = ok ? m : 0;
 }
@@ -754,7 +755,7 @@ __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, i
             margin = (r64 - rc) / rc;
         }
         if (brk) return;
-        const float rinv = rsqrtf(r2);
+        const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
         const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
         f[0] = coef * dv[0];
         f[1] = coef * dv[1];
@@ -794,9 +795,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
     using TTy = typename TT<PREC>::type;
     __shared__ TTy tt[kMaxTypes];
     __shared__ double mass_s[LSM_MAX_PHASES];
+    __shared__ R imass_s[LSM_MAX_PHASES];  // R(1 / m), once per workgroup
     __shared__ double red_lds[MODE == kEnd ? kNumPartials : 1][kBlock / 64];
     for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
-    if (threadIdx.x < LSM_MAX_PHASES) mass_s[threadIdx.x] = P.mass[threadIdx.x];
+    if (threadIdx.x < LSM_MAX_PHASES) {
+        mass_s[threadIdx.x] = P.mass[threadIdx.x];
+        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    }
     __syncthreads();
 
     double red[MODE == kEnd ? kNumPartials : 1];
@@ -935,7 +940,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                         if (pur && !(mk & 4))
                             spring_stress64(P.types[tur], 0.5 * a64, hy64, rc.uh, rc.ul, urh, url, red);
                     }
-                    integrate_site<2, PREC, MODE>(P, g, uint8_t(rc.f), mass_s[flag_phase(rc.f)], rc.uh,
+                    integrate_site<2, PREC, MODE>(P, g, uint8_t(rc.f), mass_s[flag_phase(rc.f)],
+                                                  imass_s[flag_phase(rc.f)], rc.uh,
                                                   rc.ul, F, rc.v, red);
                 }
                 if constexpr (MODE == kEnd) {

@@ -398,7 +398,7 @@ class HostModel:
 BATCH_EXPORTS = (
     "lsm_batch_create", "lsm_batch_destroy", "lsm_batch_last_error", "lsm_batch_counts",
     "lsm_batch_workspace_bytes", "lsm_batch_bind", "lsm_batch_set_launch", "lsm_batch_run",
-    "lsm_batch_read", "lsm_batch_set_timing", "lsm_batch_read_timing",
+    "lsm_batch_read", "lsm_batch_set_timing", "lsm_batch_read_timing", "lsm_batch_autotune",
 )
 
 
@@ -420,6 +420,7 @@ def _load_batch(L):
     L.lsm_batch_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
     L.lsm_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
     L.lsm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.lsm_batch_autotune.argtypes = [vp, C.c_int, vp, C.c_int, P(C.c_int)]
     L.lsm_batch_run.argtypes = [vp, dbl, i64, i32, P(FailRule)]
     L.lsm_batch_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.lsm_batch_set_timing.argtypes = [vp, C.c_int]
@@ -492,6 +493,16 @@ class Batch:
 
     def set_launch(self, rows_per_wave=4, prefetch=1):
         self._check(self._L.lsm_batch_set_launch(self._h, int(rows_per_wave), int(prefetch)))
+
+    def autotune(self, steps_per_trial=20):
+        """Times the candidate launches on this batch before its run and keeps
+        the fastest; returns [(rows_per_wave, prefetch, us_per_step)]."""
+        buf = (Tuning * 64)()
+        n = C.c_int()
+        self._check(self._L.lsm_batch_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
+        self.launch = min(((t.rows_per_wave, t.prefetch, t.us_per_step) for t in buf[:n.value]),
+                          key=lambda r: r[2])[:2]
+        return [(t.rows_per_wave, t.prefetch, t.us_per_step) for t in buf[:n.value]]
 
     def run(self, d_eps, steps_per_inc, max_inc, drop=0.01):
         rule = FailRule(float(drop))

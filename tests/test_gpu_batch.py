@@ -80,6 +80,23 @@ def test_batch_rows_independent_and_order_free(lsm):
             assert np.array_equal(np.nan_to_num(r[key]), np.nan_to_num(out[0][key])), key
 
 
+def test_batch_autotune_keeps_results(lsm):
+    wl = inputs.WORKLOADS["c4"]
+    imgs = specimens()
+    say("batch autotune before the run leaves the results unchanged")
+    out = []
+    for tune in (False, True):
+        b = lsm.Batch.from_workload(wl, imgs, precision="fp32k")
+        if tune:
+            res = b.autotune(20)
+            assert len(res) >= 4 and all(r[2] > 0 for r in res)
+            say(f"  picked rows {b.launch[0]} prefetch {b.launch[1]} of {len(res)} candidates")
+        b.run(wl["d_eps"], 200, 25)
+        out.append(b.read())
+    for key in ("sigma_xx", "n_inc", "modulus", "strength", "n_broken"):
+        assert np.array_equal(np.nan_to_num(out[1][key]), np.nan_to_num(out[0][key])), key
+
+
 def test_batch_derived_against_oracle(lsm):
     wl = inputs.WORKLOADS["c4"]
     imgs = specimens()[:4]
