@@ -282,108 +282,143 @@ inline dim3 conv_grid(int64_t npix, int cout) {
 }
 
 // ------------------------------------------------------- weight gradient
-// dw[co, tap, ci] = sum_p dout[p, co] * in[shift(p, tap), ci], split over
-// pixel ranges: partial[split][co][tap][ci] (FP32).  Workgroup tile: 64 co x
-// 64 ci for one tap; K = 64 pixels per LDS stage.
+// dw[co, n] = sum_p dout[p, co] * in[shift(p, tap(n)), ci(n)], n = tap * Cin
+// + ci (the [Cout][9][Cin] weight layout flattened), split over pixel
+// ranges: partial[split][co][n] (FP32), summed later in a fixed order.
+// Workgroup tile: 64 co x 64 n (a tile spans two taps when Cin = 32), 64
+// pixels of reduction per LDS stage, four wavefronts of 32 x 32.  Both
+// tiles are staged in their natural [pixel][channel] order with 16-byte
+// stores and read back as MFMA operands with the transposing LDS read
+// (ds_read_b64_tr_b16): within a group of 16 lanes, lane L addressing
+// T[k0 + L / 4][m0 + 4 (L mod 4)] makes lane i receive T[k0 + k][m0 + i],
+// k = 0..3 -- four consecutive reduction elements of row m0 + i, half of
+// an MFMA fragment.  The workgroups of the first n tile also sum dout over
+// their pixels: the bias gradient.
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s lds_v4s;
+
+constexpr int kWgStride = 72;  // u16 per staged pixel row (64 + 8): 144 B, 16-byte aligned
+
+__device__ inline bf16x8 tr_frag(const u16 *tile, int k0, int m0, int lane16) {
+    const u16 *p0 = tile + (k0 + (lane16 >> 2)) * kWgStride + m0 + 4 * (lane16 & 3);
+    union {
+        v4s h[2];
+        bf16x8 v;
+    } u;
+    u.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p0));
+    u.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p0 + 4 * kWgStride));
+    return u.v;
+}
+
 __global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u16 *dout, float *partial,
                                                          float *bias_partial, int B, int H, int W, int Cin,
                                                          int Cout, int64_t pix_per_split) {
-    __shared__ u16 sd[64][64 + 8];  // [co][pixel]
-    __shared__ u16 sx[64][64 + 8];  // [ci][pixel]
-    __shared__ float sb[4][64];     // bias sums per wavefront
+    __shared__ __align__(16) u16 sd[64 * kWgStride];  // [pixel][co]
+    __shared__ __align__(16) u16 sx[64 * kWgStride];  // [pixel][n]
+    __shared__ float sb[4][64];                       // bias sums per wavefront
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int co_t = blockIdx.x * 64, ci_t = (blockIdx.y % ((Cin + 63) / 64)) * 64;
-    const int tap = blockIdx.y / ((Cin + 63) / 64);
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    const int N = 9 * Cin;
+    const int co_t = blockIdx.x * 64, n_t = blockIdx.y * 64;
     const int split = blockIdx.z;
     const int64_t npix = int64_t(B) * H * W;
     const int64_t pbeg = int64_t(split) * pix_per_split;
     const int64_t pend = pbeg + pix_per_split < npix ? pbeg + pix_per_split : npix;
     const int r16 = lane & 15, kq = lane >> 4;
-    const int wco = (wv >> 1) * 32, wci = (wv & 1) * 32;
-    // the centre-tap workgroups of the first input-channel tile also sum
-    // dout over their pixels: the bias gradient
-    const bool do_bias = tap == 4 && ci_t == 0;
-    float bsum[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) bsum[e] = 0.0f;
+    const int wco = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const bool do_bias = blockIdx.y == 0;
+    // loader: thread t stages pixels t / 8 and t / 8 + 32 of a stage,
+    // channels 8 (t mod 8) .. + 7 of both tiles; its eight n share one tap
+    const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 8;
+    const int ln = n_t + lc;
+    const bool nok = ln < N;
+    const int ltap = nok ? ln / Cin : 0;
+    const int lci = nok ? ln - ltap * Cin : 0;
+    const int ldy = ltap / 3 - 1, ldx = ltap % 3 - 1;
+    const bool cok = co_t + lc < Cout;
     f32x4 acc[2][2];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // loader: thread t covers pixel t / 4, channels (t % 4) * 16 .. + 15
-    const int lp = threadIdx.x >> 2, lc = (threadIdx.x & 3) * 16;
-    for (int64_t q0 = pbeg; q0 < pend; q0 += 64) {
-        const int64_t p = q0 + lp;
-        const bool pin = p < pend;
-        const int64_t pp = pin ? p : 0;
-        const int x = int(pp % W), y = int((pp / W) % H);
-        const int64_t n = pp / (int64_t(H) * W);
-        const int sy = y + dy, sx2 = x + dx;
-        const bool xin = pin && sy >= 0 && sy < H && sx2 >= 0 && sx2 < W;
-        const int64_t xb = xin ? ((n * H + sy) * W + sx2) * Cin : 0;
+    float bsum[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bsum[e] = 0.0f;
+    uint4 rd[2], rx[2];
+    auto gload = [&](int64_t q0) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int cc = lc + 8 * h;
-            uint4 vd = make_uint4(0, 0, 0, 0), vx = make_uint4(0, 0, 0, 0);
-            if (pin && co_t + cc < Cout) vd = *reinterpret_cast<const uint4 *>(dout + pp * Cout + co_t + cc);
-            if (xin && ci_t + cc < Cin) vx = *reinterpret_cast<const uint4 *>(in + xb + ci_t + cc);
-            const u16 *ed = reinterpret_cast<const u16 *>(&vd);
-            const u16 *ex = reinterpret_cast<const u16 *>(&vx);
+            const int64_t p = q0 + lp + 32 * h;
+            const bool pin = p < pend;
+            const int64_t pp = pin ? p : 0;
+            const int x = int(pp % W), y = int((pp / W) % H);
+            const int64_t n = pp / (int64_t(H) * W);
+            const int sy = y + ldy, sx2 = x + ldx;
+            const bool dok = pin && cok;
+            const bool xok = pin && nok && sy >= 0 && sy < H && sx2 >= 0 && sx2 < W;
+            // unconditional loads from valid addresses, masked afterwards
+            const uint4 vd = *reinterpret_cast<const uint4 *>(dout + (dok ? pp * Cout + co_t + lc : 0));
+            const uint4 vx = *reinterpret_cast<const uint4 *>(in + (xok ? ((n * H + sy) * W + sx2) * Cin + lci : 0));
+            rd[h] = dok ? vd : make_uint4(0, 0, 0, 0);
+            rx[h] = xok ? vx : make_uint4(0, 0, 0, 0);
+        }
+    };
+    if (pbeg < pend) gload(pbeg);
+    for (int64_t q0 = pbeg; q0 < pend; q0 += 64) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                sd[cc + e][lp] = ed[e];
-                sx[cc + e][lp] = ex[e];
-            }
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<uint4 *>(sd + (lp + 32 * h) * kWgStride + lc) = rd[h];
+            *reinterpret_cast<uint4 *>(sx + (lp + 32 * h) * kWgStride + lc) = rx[h];
             if (do_bias) {
+                const u16 *e8 = reinterpret_cast<const u16 *>(&rd[h]);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bsum[8 * h + e] += bf2f(ed[e]);
+                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(e8[e]);
             }
         }
         __syncthreads();
+        if (q0 + 64 < pend) gload(q0 + 64);  // next stage in flight during the MFMAs
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            Frag a[2], b[2];
+            bf16x8 a[2], b[2];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) a[r].u = *reinterpret_cast<const uint4 *>(&sd[wco + r * 16 + r16][ks * 32 + 8 * kq]);
+            for (int r = 0; r < 2; ++r) a[r] = tr_frag(sd, ks * 32 + 8 * kq, wco + r * 16, r16);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) b[c].u = *reinterpret_cast<const uint4 *>(&sx[wci + c * 16 + r16][ks * 32 + 8 * kq]);
+            for (int c = 0; c < 2; ++c) b[c] = tr_frag(sx, ks * 32 + 8 * kq, wn + c * 16, r16);
 #pragma unroll
             for (int r = 0; r < 2; ++r)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, b[c].v, acc[r][c], 0, 0, 0);
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
         }
         __syncthreads();
     }
-    // D: rows = co (4 * kq + i), column = ci (r16)
+    // D: rows = co (4 * kq + i), column = n (r16)
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            const int ci = ci_t + wci + c * 16 + r16;
-            if (ci >= Cin) continue;
+            const int n = n_t + wn + c * 16 + r16;
+            if (n >= N) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int co = co_t + wco + r * 16 + 4 * kq + i;
                 if (co >= Cout) continue;
-                partial[((int64_t(split) * Cout + co) * 9 + tap) * Cin + ci] = acc[r][c][i];
+                partial[(int64_t(split) * Cout + co) * N + n] = acc[r][c][i];
             }
-        }    if (do_bias) {  // uniform per workgroup
-        // lanes with equal lane % 4 hold the same 16 channels: butterfly
-        // over the other lane bits, then the four wavefronts in order
+        }
+    if (do_bias) {  // uniform per workgroup
+        // lanes with equal lane % 8 hold the same 8 channels: butterfly over
+        // the other lane bits, then the four wavefronts in order
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < 8; ++e) {
             float v = bsum[e];
 #pragma unroll
-            for (int o = 4; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            for (int o = 8; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
             bsum[e] = v;
         }
-        if (lane < 4) {
+        if (lane < 8) {
 #pragma unroll
-            for (int e = 0; e < 16; ++e) sb[wv][lane * 16 + e] = bsum[e];
+            for (int e = 0; e < 8; ++e) sb[wv][lane * 8 + e] = bsum[e];
         }
         __syncthreads();
         if (threadIdx.x < 64 && co_t + int(threadIdx.x) < Cout) {
@@ -922,7 +957,7 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
         const int64_t nw = c->w_n[l], cout = c->C[l + 1], cin = c->C[l];
         if (l > 0) {
             // weight gradient: MFMA over pixel splits, then a fixed-order sum
-            const dim3 grid(unsigned((cout + 63) / 64), unsigned(9 * ((cin + 63) / 64)), unsigned(sp));
+            const dim3 grid(unsigned((cout + 63) / 64), unsigned((9 * cin + 63) / 64), unsigned(sp));
             float *bias_part = c->part + sp * nw;  // [split][co] after the weight partials
             hipLaunchKernelGGL(k_conv_wgrad_mfma, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l], c->part,
                                bias_part, B, H, H, int(cin), int(cout), int64_t(kSplitPix));
