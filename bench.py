@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = ("spring-steps/s (% HBM roofline); specimens/hour batched+surrogate "
           "@≤5% error")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_step_traffic.json")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "c2_step_counters.json")
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s
+# (78.6 TFLOP/s of non-packed FP32 FMA)
+VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 WORKLOAD_NAMES = {
     "c2": "c2 brick-and-mortar 2048x2048 triangular lattice, fp32 forces with compensated fp32 "
           "displacements, 0.05% strain increments x 2000 steps",
@@ -44,17 +47,21 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, or None when absent or taken on a different kernel source."""
+def measured_counters(launch):
+    """rocprofv3 counters of the C2 step kernel (HBM bytes and VALU
+    instructions per launch) from the committed summary, or None when
+    absent, taken on a different kernel source or another launch shape."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTER_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_src_sha256") != kernel_hash():
         return None
-    return t.get("bytes_per_launch")
+    want = {k: launch[k] for k in ("variant", "rows_per_wave", "prefetch")}
+    if t.get("launch") != want:
+        return None
+    return t
 
 
 def cpu_baseline(wl, img, steps: int):
@@ -248,7 +255,9 @@ def main():
     ap.add_argument("--steps-per-inc", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--launch", default="4,1", metavar="ROWS,PREFETCH",
+    ap.add_argument("--kernel", choices=("sweep", "sweep2"), default="sweep2",
+                    help="2D step kernel: one or two interior steps per launch")
+    ap.add_argument("--launch", default="8,1", metavar="ROWS,PREFETCH",
                     help="sweep launch: rows per wavefront, prefetch depth")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch with lsm_autotune instead of --launch")
@@ -256,11 +265,13 @@ def main():
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--plain-per-size", type=int, default=2)
     ap.add_argument("--cpu-c4-inc", type=int, default=1)
-    ap.add_argument("--surrogate", action="store_true", help="also run the surrogate pipeline")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the batched-model + surrogate pipeline (on by default at reduced size)")
     ap.add_argument("--cnn-bench", action="store_true", help="also time the surrogate network kernels")
-    ap.add_argument("--sur-train", type=int, default=16384)
-    ap.add_argument("--sur-test", type=int, default=2048)
-    ap.add_argument("--sur-epochs", type=int, default=20)
+    ap.add_argument("--sur-train", type=int, default=4096,
+                    help="training specimens (the full C5 configuration: 50000)")
+    ap.add_argument("--sur-test", type=int, default=1024, help="test specimens (C5: 5000)")
+    ap.add_argument("--sur-epochs", type=int, default=10, help="epochs (C5: 20)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
@@ -287,7 +298,7 @@ def main():
         lat.autotune(100)
     else:
         rows, pf = (int(v) for v in args.launch.split(","))
-        lat.set_launch("sweep", rows)
+        lat.set_launch(args.kernel, rows)
         lat.set_prefetch(pf)
     launch = lat.launch()
     print(f"[bench] launch: {launch}", file=sys.stderr, flush=True)
@@ -316,10 +327,28 @@ def main():
     springs = lat.m
     timesteps = args.steps * spi
     value = springs * timesteps / wall
-    avg_kernel_s = kern_ms * 1e-3 / max(kern_launches, 1)
-    step_bytes = lat.step_bytes()
-    achieved = step_bytes / avg_kernel_s / 1e9
-    traffic = measured_traffic()
+    avg_step_s = kern_ms * 1e-3 / max(kern_launches, 1)  # event time per interior step
+    spl = launch["steps_per_launch"]
+    launch_s = avg_step_s * spl                            # per launch of the step kernel
+    bytes_per_launch = lat.step_bytes()
+    hbm_gbs = bytes_per_launch / launch_s / 1e9
+    counters = measured_counters(launch) if args.workload == "c2" else None
+    kname = {("c2", 2): "k_sweep2d_x2<1,1> (fp32 compensated, two interior steps per launch)",
+             ("c2", 1): "k_sweep2d<1,1> (fp32 compensated, one interior step per launch)",
+             ("c3", 1): "k_step<3,1,1> (fp32 compensated, one thread per particle)"}[(args.workload, spl)]
+    roofline = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm_gbs / HBM_PEAK_GBS,
+                "traffic": counters.get("bytes_per_launch") if counters else None,
+                "bytes_per_launch": bytes_per_launch, "steps_per_launch": spl, "kernel": kname}
+    if counters and counters.get("valu_insts_per_launch"):
+        # VALU issue rate: wavefront instructions x 64 lanes per launch time
+        alu = counters["valu_insts_per_launch"] * 64 / launch_s / 1e12
+        if alu / VALU_PEAK_T > roofline["frac"]:
+            roofline.update({"bound": "alu", "achieved": alu, "peak": VALU_PEAK_T,
+                             "unit": "T VALU lane-instructions/s", "frac": alu / VALU_PEAK_T,
+                             "hbm_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS})
+        else:
+            roofline["alu_frac"] = alu / VALU_PEAK_T
 
     out = {
         "metric": METRIC,
@@ -341,21 +370,12 @@ def main():
             "steps_per_increment": spi,
             "strain_at_end": rec["eps"],
             "broken_springs_at_end": rec["n_broken"],
-            "step_kernel_us": avg_kernel_s * 1e6,
+            "step_kernel_us": avg_step_s * 1e6,
+            "step_kernel_launch_us": launch_s * 1e6,
             "launch": launch,
-            "hbm_fraction_of_wall": step_bytes * timesteps / wall / 1e9 / HBM_PEAK_GBS,
+            "hbm_fraction_of_wall": bytes_per_launch * timesteps / spl / wall / 1e9 / HBM_PEAK_GBS,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic if args.workload == "c2" else None,
-            "bytes_per_launch": step_bytes,
-            "kernel": ("k_sweep2d<1,1> (fp32, interior step)" if args.workload == "c2"
-                       else "k_step<3,1,1> (fp32, interior step, one thread per particle)"),
-        },
+        "roofline": roofline,
     }
     if args.copy_ref:
         # plain copy kernel of known size: reads and writes copy_ref MiB once
@@ -376,7 +396,7 @@ def main():
     if args.cnn_bench:
         print("[bench] surrogate network kernels", file=sys.stderr, flush=True)
         out["cnn"] = cnn_kernels(torch)
-    if args.surrogate:
+    if not args.no_surrogate and args.workload == "c2":
         print("[bench] surrogate pipeline", file=sys.stderr, flush=True)
         out["surrogate"] = surrogate_c5(args)
     if not args.no_cpu:

@@ -57,6 +57,9 @@ extern "C" {
 #define LSM_KERNEL_AUTO 0   /* row sweep for 2D lattices, site gather for 3D */
 #define LSM_KERNEL_GATHER 1 /* one thread per site, all incident springs */
 #define LSM_KERNEL_SWEEP 2  /* 2D: wavefronts sweep rows, forward springs once */
+#define LSM_KERNEL_SWEEP2 3 /* 2D, FP32-compensated: row sweep advancing two interior
+                               steps per launch (same results as LSM_KERNEL_SWEEP, about
+                               half the memory traffic); LSM_EINVAL for FP64 lattices */
 
 /* Model and integration parameters.
  *  k[P*P], break_stretch[P*P]: row-major, symmetric spring constant and
@@ -118,11 +121,12 @@ typedef struct {
 
 /* One launch configuration of the step kernel and its measured time. */
 typedef struct {
-    int32_t variant;       /* LSM_KERNEL_GATHER or LSM_KERNEL_SWEEP */
-    int32_t rows_per_wave; /* sweep row chunk */
-    int32_t prefetch;      /* sweep rows prefetched ahead */
-    int32_t reserved;
-    double us_per_step;    /* measured (lsm_autotune), 0 otherwise */
+    int32_t variant;          /* LSM_KERNEL_* as set (AUTO: chosen per lattice) */
+    int32_t rows_per_wave;    /* sweep row chunk */
+    int32_t prefetch;         /* sweep rows prefetched ahead */
+    int32_t steps_per_launch; /* interior steps per launch: 2 for the two-step
+                                 sweep, else 1 (lsm_get_launch; 0 from tuners) */
+    double us_per_step;       /* measured (lsm_autotune), 0 otherwise */
 } lsm_tuning;
 
 typedef struct lsm_handle lsm_handle;
@@ -218,8 +222,10 @@ int lsm_load_state(lsm_handle *h, const void *buf, size_t n);
 /* Measurement hooks.  lsm_set_timing(h, 1) brackets every graph of step
  * kernels with HIP events on the bound stream; lsm_read_timing returns the
  * summed event time in ms and the number of step kernels it covered
- * (synchronises).  lsm_step_bytes gives the algorithmic bytes one step
- * kernel must move (state read + written, site flags and break masks).    */
+ * (synchronises).  lsm_step_bytes gives the algorithmic bytes one launch of
+ * the interior step kernel in use must move: state read and written once,
+ * site flags, break masks (and the particle list in 3D); one launch
+ * advances lsm_tuning.steps_per_launch steps.                             */
 int lsm_set_timing(lsm_handle *h, int enable);
 int lsm_read_timing(lsm_handle *h, double *ms, int64_t *steps);
 int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);

@@ -28,6 +28,7 @@ using lsm::TypeRec;
 namespace {
 constexpr int kGraphChunk = 1000;  // step kernels per captured graph
 constexpr int kMinSweepRows = 2;
+
 constexpr int kMaxSweepRows = 4096;
 constexpr uint32_t kStateMagic = 0x4C534D31u;
 constexpr double kHalfSqrt3 = 0.86602540378443864676;
@@ -53,7 +54,7 @@ struct lsm_handle {
     double omega = 0.0;
     int tiles_x = 0, tiles_y = 0, ntiles = 0, nblocks = 0;
     int variant = LSM_KERNEL_AUTO;  // step kernel family
-    int sw_rows = 4;                // rows per wavefront of the 2D row sweep
+    int sw_rows = 0;                // rows per wavefront of the 2D row sweep (0: default)
     int sw_pf = 1;                  // rows prefetched ahead in the sweep
     size_t ub = 0, vb = 0, mb = 0;  // bytes per site of u, v, mask
     // device
@@ -77,7 +78,11 @@ struct lsm_handle {
     bool half = false;  // velocities are half-step (between an increment and the end of a relax)
     int32_t inc = 0, step = 0;
     double eps = 0.0;
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+    // the two-step sweep reads velocities and break bits from d_V / d_mask
+    // and writes them to these; the pointers swap after each such launch
+    void *d_V_alt = nullptr, *d_mask_alt = nullptr;
+    int vm = 0;  // parity of those swaps (part of the graph key)
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
     std::vector<hipEvent_t> ev_pool;
@@ -171,6 +176,9 @@ void site_X0(const lsm_handle *h, int64_t g, double *X) {
     }
 }
 
+bool use_sweep2(const lsm_handle *h);
+int rows_of(const lsm_handle *h);
+
 StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     StepParams p{};
     p.nx = int32_t(h->nx);
@@ -200,11 +208,14 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     p.partials = h->d_partials;
     p.f64 = h->d_f64;
     p.commit = 1;
-    p.sw_rows = h->sw_rows;
+    p.sw_rows = rows_of(h);
     p.sw_pf = h->sw_pf;
     p.sw_strips = int((h->nx + lsm::kSweepCols - 1) / lsm::kSweepCols);
-    p.sw_nwork = p.sw_strips * int((h->ny + h->sw_rows - 1) / h->sw_rows);
+    p.sw_nwork = p.sw_strips * int((h->ny + p.sw_rows - 1) / p.sw_rows);
     p.sw_nblocks = ((p.sw_nwork + 4 * 8 - 1) / (4 * 8)) * 8;
+    p.sw2_strips = int((h->nx + lsm::kSweepCols2 - 1) / lsm::kSweepCols2);
+    p.sw2_nwork = p.sw2_strips * int((h->ny + p.sw_rows - 1) / p.sw_rows);
+    p.sw2_nblocks = ((p.sw2_nwork + 4 * 8 - 1) / (4 * 8)) * 8;
     p.n_part = int32_t(h->n);
     p.plist = h->plist.empty() ? nullptr : h->d_plist;
     p.c_blocks = h->c_blocks;
@@ -213,6 +224,14 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
 }
 
 bool use_sweep(const lsm_handle *h) { return h->dim == 2 && h->variant != LSM_KERNEL_GATHER; }
+// interior steps in pairs per launch: the default for 2D FP32-compensated lattices
+bool use_sweep2(const lsm_handle *h) {
+    return h->dim == 2 && h->prec &&
+           (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
+}
+// rows per wavefront: as set, else the measured best of the kernel in use
+int rows_of(const lsm_handle *h) { return h->sw_rows ? h->sw_rows : (use_sweep2(h) ? 8 : 4); }
+
 
 // Start / interior / end step with the kernel family chosen for this lattice.
 hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_local) {
@@ -222,6 +241,38 @@ hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_l
     }
     p.red_blocks = p.plist ? p.c_blocks : p.nblocks;
     return lsm::launch_step(p, h->dim, h->prec, mode, h->stream, step_local);
+}
+
+// Launches of `chunk` interior steps: pairs per launch with the two-step
+// sweep (an odd chunk ends with a single step), single steps otherwise.
+int two_step_launches(const lsm_handle *h, int chunk) { return use_sweep2(h) ? chunk / 2 : 0; }
+int mid_launches(const lsm_handle *h, int chunk) { return use_sweep2(h) ? chunk / 2 + (chunk & 1) : chunk; }
+
+// Interior steps local .. local + chunk - 1 from displacement buffer c; the
+// two-step launches read velocities / break bits from the current buffers
+// and write the other ones, swapping them for the next launch.
+hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
+    hipError_t le = hipSuccess;
+    void *vc = h->d_V, *va = h->d_V_alt, *mc = h->d_mask, *ma = h->d_mask_alt;
+    int s = 0;
+    while (s < chunk && le == hipSuccess) {
+        StepParams p = make_params(h, c, c ^ 1);
+        p.v = vc;
+        p.mask = mc;
+        p.v_out = va;
+        p.mask_out = ma;
+        if (use_sweep2(h) && s + 1 < chunk) {
+            le = lsm::launch_sweep2d_x2(p, h->prec, h->stream, local + s);
+            std::swap(vc, va);
+            std::swap(mc, ma);
+            s += 2;
+        } else {
+            le = launch_phase(h, p, lsm::kMid, local + s);
+            s += 1;
+        }
+        c ^= 1;
+    }
+    return le;
 }
 
 // Largest number of workgroups any end-of-relax kernel may use.
@@ -250,19 +301,13 @@ hipEvent_t pool_event(lsm_handle *h) {
 // Runs `chunk` interior steps starting at local step index `local`.
 int run_mid_chunk(lsm_handle *h, int chunk, int local) {
     hipGraphExec_t exec = nullptr;
-    const auto key = std::make_tuple(chunk, h->cur, local);
+    const auto key = std::make_tuple(chunk, h->cur, h->vm, local);
     auto it = h->graphs.find(key);
     if (it != h->graphs.end()) {
         exec = it->second;
     } else if (h->stream != nullptr) {
         HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        int c = h->cur;
-        hipError_t le = hipSuccess;
-        for (int s = 0; s < chunk && le == hipSuccess; ++s) {
-            StepParams p = make_params(h, c, c ^ 1);
-            le = launch_phase(h, p, lsm::kMid, local + s);
-            c ^= 1;
-        }
+        const hipError_t le = launch_mid_steps(h, chunk, local, h->cur);
         hipGraph_t graph = nullptr;
         hipError_t ce = hipStreamEndCapture(h->stream, &graph);
         if (le != hipSuccess) {
@@ -285,19 +330,19 @@ int run_mid_chunk(lsm_handle *h, int chunk, int local) {
     if (exec) {
         HIPCHK(h, hipGraphLaunch(exec, h->stream));
     } else {  // null stream: no capture, launch directly
-        int c = h->cur;
-        for (int s = 0; s < chunk; ++s) {
-            StepParams p = make_params(h, c, c ^ 1);
-            HIPCHK(h, launch_phase(h, p, lsm::kMid, local + s));
-            c ^= 1;
-        }
+        HIPCHK(h, launch_mid_steps(h, chunk, local, h->cur));
     }
     if (h->timing) {
         HIPCHK(h, hipEventRecord(e1, h->stream));
         h->tev.emplace_back(e0, e1);
         h->timed_steps += chunk;
     }
-    h->cur ^= (chunk & 1);
+    h->cur ^= mid_launches(h, chunk) & 1;
+    if (two_step_launches(h, chunk) & 1) {
+        std::swap(h->d_V, h->d_V_alt);
+        std::swap(h->d_mask, h->d_mask_alt);
+        h->vm ^= 1;
+    }
     return LSM_OK;
 }
 
@@ -414,6 +459,8 @@ int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t n
     h->plist.clear();
     h->c_blocks = 0;
     if (h->dim == 3 && nx <= 1024 && ny <= 2048 && nz <= 2048 && h->n > 0) {
+        // raster order (the particle order): tile-major orders of 16x4x4,
+        // 8x8x4, 32x4x2, 8x4x8 and 64x2x2 sites measured 2-40 % slower
         h->plist.resize(size_t(h->n));
         for (int64_t c = 0; c < h->n; ++c) {
             const int64_t g = h->site_of[size_t(c)];
@@ -448,7 +495,7 @@ int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
     return LSM_OK;
 }
 
-constexpr int kRegions = 14;
+constexpr int kRegions = 16;
 
 static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
     size_t o = 0;
@@ -468,6 +515,8 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         size_t(max_red_blocks(h)) * lsm::kNumPartials * 8,  // 11 partials
         size_t(std::max<int64_t>(h->m, 1)) * sizeof(lsm_event),  // 12 events
         h->plist.size() * 4,                          // 13 particle list
+        h->dim == 2 ? ns * h->vb : 0,                 // 14 second velocity buffer (two-step sweep)
+        h->dim == 2 ? ns * h->mb : 0,                 // 15 second break-bit buffer
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -510,6 +559,9 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_partials = reinterpret_cast<double *>(w + off[11]);
     h->d_events = reinterpret_cast<lsm_event *>(w + off[12]);
     h->d_plist = reinterpret_cast<uint32_t *>(w + off[13]);
+    h->d_V_alt = w + off[14];
+    h->d_mask_alt = w + off[15];
+    h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
@@ -975,9 +1027,13 @@ int lsm_set_prefetch(lsm_handle *h, int rows_ahead) {
 
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     if (!h) return LSM_EINVAL;
-    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP)
+    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP &&
+        variant != LSM_KERNEL_SWEEP2)
         return fail(h, LSM_EINVAL, "unknown kernel variant");
-    if (variant == LSM_KERNEL_SWEEP && h->dim != 2) return fail(h, LSM_EINVAL, "row sweep is 2D only");
+    if ((variant == LSM_KERNEL_SWEEP || variant == LSM_KERNEL_SWEEP2) && h->dim != 2)
+        return fail(h, LSM_EINVAL, "row sweep is 2D only");
+    if (variant == LSM_KERNEL_SWEEP2 && !h->prec)
+        return fail(h, LSM_EINVAL, "the two-step sweep runs FP32-compensated lattices only");
     if (rows_per_wave != 0 && (rows_per_wave < kMinSweepRows || rows_per_wave > kMaxSweepRows))
         return fail(h, LSM_EINVAL, "rows_per_wave out of range");
     if (h->half) return fail(h, LSM_ESTATE, "change the launch only between relaxations");
@@ -1071,16 +1127,18 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
 
 int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
     if (!h || !out) return LSM_EINVAL;
-    *out = lsm_tuning{h->variant, h->sw_rows, h->sw_pf, 0, 0.0};
+    *out = lsm_tuning{h->variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
     return LSM_OK;
 }
 
 int lsm_step_bytes(const lsm_handle *h, int64_t *bytes) {
     if (!h || !bytes) return LSM_EINVAL;
     if (!h->built) return LSM_ESTATE;
-    // per particle: displacement and velocity read and written, flag byte,
-    // break mask, and its packed coordinates in particle-list mode
-    *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb + (h->plist.empty() ? 0 : 4));
+    // per particle and launch: displacement and velocity read and written,
+    // flag byte, break mask read (and rewritten by the two-step sweep), and
+    // the packed coordinates in particle-list mode
+    *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb + (use_sweep2(h) ? h->mb : 0) +
+                            (h->plist.empty() ? 0 : 4));
     return LSM_OK;
 }
 

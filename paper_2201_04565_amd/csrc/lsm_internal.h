@@ -15,6 +15,7 @@ constexpr int kMaxTypes = 2 * LSM_MAX_PHASES * LSM_MAX_PHASES;  // (geometry, ph
 constexpr uint8_t kVoid = 0xFF;
 constexpr int kNumPartials = 24;  // virial[9], kinetic[9], pe, ke, nonfinite, 3 spare
 constexpr int kSweepCols = 62;    // owned columns per wavefront in the 2D row sweep
+constexpr int kSweepCols2 = 60;   // owned columns per wavefront of the two-step sweep
 
 // Site flag byte: bits 0-3 phase, bits 4-5 grip (1 left column, 2 right column).
 __host__ __device__ inline int flag_phase(uint8_t f) { return f & 0x0F; }
@@ -90,7 +91,11 @@ struct StepParams {
     int32_t n_part;
     const uint32_t *plist;  // null: one thread per grid site
     int32_t c_blocks;       // workgroups of the particle-list grid (multiple of 8)
-    int32_t pad3;
+    // two-step sweep: 60-column strips; velocities and break bits are read
+    // from v / mask and written to v_out / mask_out
+    int32_t sw2_strips, sw2_nwork, sw2_nblocks;
+    void *v_out;
+    void *mask_out;
     // batch of specimens (2D sweep only)
     const SweepItem *items;  // active work items
     const int32_t *n_items;  // number of active work items (device)
@@ -105,6 +110,9 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
 // 2D row-sweep variant of the start/mid/end steps (same semantics as launch_step).
 hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t stream,
                           int step_local);
+// Two interior steps (step_local and step_local + 1) in one launch of the
+// 2D row sweep; reads u_in, writes u_out.
+hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t stream, int step_local);
 hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
 // Batch versions: the grid covers `capacity` work items; items beyond
 // *p.n_items exit at once.

@@ -246,6 +246,36 @@ __device__ inline void tile_coords(const StepParams &P, int &i, int &j, int &k, 
     ok = ok && i < P.nx && j < P.ny;
 }
 
+// Acceleration (F - gamma v) / m of a free particle (v: the half-step velocity).
+template <int DIM, int PREC>
+__device__ inline void site_acc(const typename State<DIM, PREC>::R *F, const typename State<DIM, PREC>::R *w,
+                                double mass, typename State<DIM, PREC>::R inv_mass,
+                                typename State<DIM, PREC>::R gam, typename State<DIM, PREC>::R *acc) {
+    using R = typename State<DIM, PREC>::R;
+    if constexpr (PREC == 1) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * inv_mass;
+    } else {
+        const R m = R(mass);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) / m;
+    }
+}
+
+// Interior step: close the half kick, open the next one, drift.
+template <int DIM, int PREC>
+__device__ inline void mid_kick_drift(typename State<DIM, PREC>::R *uph, typename State<DIM, PREC>::R *upl,
+                                      typename State<DIM, PREC>::R *w, const typename State<DIM, PREC>::R *acc,
+                                      typename State<DIM, PREC>::R h, typename State<DIM, PREC>::R dt) {
+    using R = typename State<DIM, PREC>::R;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const R vfull = w[c] + h * acc[c];
+        w[c] = vfull + h * acc[c];
+        comp_add(uph[c], upl[c], dt * w[c]);
+    }
+}
+
 // Velocity Verlet in the half-step form (Eq. 3-5) with viscous damping
 // evaluated with the half-step velocity, for one free particle; grips stay
 // clamped.  On entry w is the particle's stored velocity (full step at the
@@ -275,14 +305,7 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, do
     const R dt = R(P.dt);
     const R gam = R(P.gamma);
     R acc[DIM];
-    if constexpr (PREC == 1) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) * inv_mass;
-    } else {
-        const R m = R(mass);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) acc[c] = (F[c] - gam * w[c]) / m;
-    }
+    site_acc<DIM, PREC>(F, w, mass, inv_mass, gam, acc);
     if constexpr (MODE == kStart) {
         // w holds the full-step velocity at the increment
 #pragma unroll
@@ -293,12 +316,7 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, do
         S::store_u(P.u_out, g, P.nsites, uph, upl);
         S::store_v(P.v, g, P.nsites, w);
     } else if constexpr (MODE == kMid) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            const R vfull = w[c] + h * acc[c];
-            w[c] = vfull + h * acc[c];
-            comp_add(uph[c], upl[c], dt * w[c]);
-        }
+        mid_kick_drift<DIM, PREC>(uph, upl, w, acc, h, dt);
         S::store_u(P.u_out, g, P.nsites, uph, upl);
         S::store_v(P.v, g, P.nsites, w);
     } else if constexpr (MODE == kEnd) {
@@ -788,6 +806,106 @@ __device__ inline void spring_stress64(const TypeRec &T, double ex64, double ey6
     red[18] += 0.5 * T.k64 * (r - T.r0_64) * (r - T.r0_64);
 }
 
+// The three forward springs of a swept row (east, upper-left, upper-right),
+// evaluated per lane from the row (rc) and the row above (ru); neighbour
+// sites come from adjacent lanes through DPP moves, so every lane of the
+// wavefront must call this.
+template <class R>
+struct RowSprings {
+    R eh[2], el[2], ulh[2], ull[2], urh[2], url[2];  // neighbour displacements (stress)
+    R fe[2], ful[2], fur[2];                         // forces on this site
+    int pe, pul, pur, be, bul, bur, te, tul, tur;    // present, broken now, type index
+    double me, mul, mur;                             // break margins
+    int nb;                                          // bits 0..2: broken at this evaluation
+    int fb;                                          // bits 0..2: broken now or before
+};
+
+template <int PREC, class TTy>
+__device__ inline void row_springs(const TTy *tt, const TypeRec *types,
+                                   const SweepRow<typename State<2, PREC>::R> &rc,
+                                   const SweepRow<typename State<2, PREC>::R> &ru, int par,
+                                   RowSprings<typename State<2, PREC>::R> &o, double a64) {
+    using R = typename State<2, PREC>::R;
+    const R a = R(a64), hy = R(kHalfSqrt3 * a64);
+    const double hy64 = kHalfSqrt3 * a64;
+    const R half_a = R(0.5) * a;
+    int ef, ulf, urf;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+        o.eh[cc] = lane_next(rc.uh[cc]);
+        o.el[cc] = PREC ? lane_next(rc.ul[cc]) : R(0);
+    }
+    ef = lane_next(rc.f);
+    if (par == 0) {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            o.ulh[cc] = lane_prev(ru.uh[cc]);
+            o.ull[cc] = PREC ? lane_prev(ru.ul[cc]) : R(0);
+            o.urh[cc] = ru.uh[cc];
+            o.url[cc] = ru.ul[cc];
+        }
+        ulf = lane_prev(ru.f);
+        urf = ru.f;
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            o.ulh[cc] = ru.uh[cc];
+            o.ull[cc] = ru.ul[cc];
+            o.urh[cc] = lane_next(ru.uh[cc]);
+            o.url[cc] = PREC ? lane_next(ru.ul[cc]) : R(0);
+        }
+        ulf = ru.f;
+        urf = lane_next(ru.f);
+    }
+    fwd_spring<PREC>(tt, types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, o.eh, o.el, ef, o.fe, o.pe,
+                     o.be, o.me, o.te);
+    fwd_spring<PREC>(tt, types, rc.f, rc.m, 1, -half_a, hy, -0.5 * a64, hy64, rc.uh, rc.ul, o.ulh, o.ull, ulf,
+                     o.ful, o.pul, o.bul, o.mul, o.tul);
+    fwd_spring<PREC>(tt, types, rc.f, rc.m, 2, half_a, hy, 0.5 * a64, hy64, rc.uh, rc.ul, o.urh, o.url, urf,
+                     o.fur, o.pur, o.bur, o.mur, o.tur);
+    o.nb = o.be | (o.bul << 1) | (o.bur << 2);
+    o.fb = o.nb | (rc.m & 7);
+}
+
+// Total force on the lane's site: its forward springs, minus the forward
+// forces of its west neighbour (adjacent lane) and of its two lower
+// neighbours (carried from the row below: pUL, pUR, and pbrk = their
+// upper-left / upper-right "broken now or before" bits), in a fixed order;
+// and its break mask after this evaluation.  The backward bits come from
+// the neighbours' broken-now-or-before bits, so they do not depend on
+// whether the owner of a neighbouring site has already stored its new bits
+// when this lane reads them.  DPP moves: every lane must call this.
+template <class R>
+__device__ inline void row_force(const RowSprings<R> &o, const R *pUL, const R *pUR, int pbrk, int par, int m,
+                                 R *F, int &newmask) {
+    R gW[2], gDR[2], gDL[2];
+    int bW, bDR, bDL;
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) gW[cc] = lane_prev(o.fe[cc]);
+    bW = lane_prev(o.fb) & 1;
+    if (par == 0) {
+        // lower-right neighbour is this lane, lower-left the previous lane
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            gDR[cc] = pUL[cc];
+            gDL[cc] = lane_prev(pUR[cc]);
+        }
+        bDR = pbrk & 1;
+        bDL = (lane_prev(pbrk) >> 1) & 1;
+    } else {
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            gDR[cc] = lane_next(pUL[cc]);
+            gDL[cc] = pUR[cc];
+        }
+        bDR = lane_next(pbrk) & 1;
+        bDL = (pbrk >> 1) & 1;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) F[cc] = ((((o.fe[cc] + o.ful[cc]) + o.fur[cc]) - gW[cc]) - gDR[cc]) - gDL[cc];
+    newmask = m | o.nb | (bW << 3) | (bDR << 4) | (bDL << 5);
+}
+
 template <int PREC, int MODE, int PF, int BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
     using S = State<2, PREC>;
@@ -821,9 +939,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const int j0 = it.j0;
         const int j1 = it.j1;
         const int jstart = j0 > 0 ? j0 - 1 : 0;
-        const R a = R(P.a), hy = R(kHalfSqrt3 * P.a);
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
-        const R half_a = R(0.5) * a;
 
         R pUL[2] = {R(0), R(0)}, pUR[2] = {R(0), R(0)};
         int pbrk = 0;
@@ -833,77 +949,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         auto row_step = [&](int j, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
             load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
             const int par = j & 1;
-            // neighbour sites: east (this row, next lane), upper-left / upper-right (row above)
-            R eh[2], el[2], ulh[2], ull[2], urh[2], url[2];
-            int ef, ulf, urf;
-#pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-                eh[cc] = lane_next(rc.uh[cc]);
-                el[cc] = PREC ? lane_next(rc.ul[cc]) : R(0);
-            }
-            ef = lane_next(rc.f);
-            if (par == 0) {
-#pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    ulh[cc] = lane_prev(ru.uh[cc]);
-                    ull[cc] = PREC ? lane_prev(ru.ul[cc]) : R(0);
-                    urh[cc] = ru.uh[cc];
-                    url[cc] = ru.ul[cc];
-                }
-                ulf = lane_prev(ru.f);
-                urf = ru.f;
-            } else {
-#pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    ulh[cc] = ru.uh[cc];
-                    ull[cc] = ru.ul[cc];
-                    urh[cc] = lane_next(ru.uh[cc]);
-                    url[cc] = PREC ? lane_next(ru.ul[cc]) : R(0);
-                }
-                ulf = ru.f;
-                urf = lane_next(ru.f);
-            }
-            R fe[2], ful[2], fur[2];
-            int pe, pul, pur, be, bul, bur, te, tul, tur;
-            double me, mul, mur;
-            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, eh, el, ef,
-                             fe, pe, be, me, te);
-            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 1, -half_a, hy, -0.5 * a64, hy64, rc.uh, rc.ul,
-                             ulh, ull, ulf, ful, pul, bul, mul, tul);
-            fwd_spring<PREC>(tt, P.types, rc.f, rc.m, 2, half_a, hy, 0.5 * a64, hy64, rc.uh, rc.ul,
-                             urh, url, urf, fur, pur, bur, mur, tur);
-            const int nb = be | (bul << 1) | (bur << 2);
+            RowSprings<R> o;
+            row_springs<PREC>(tt, P.types, rc, ru, par, o, P.a);
+            const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
+            const R *fe = o.fe, *ful = o.ful, *fur = o.fur;
+            const int pe = o.pe, pul = o.pul, pur = o.pur, be = o.be, bul = o.bul, bur = o.bur;
+            const int te = o.te, tul = o.tul, tur = o.tur;
+            const double me = o.me, mul = o.mul, mur = o.mur;
+            const int nb = o.nb;
             if (j >= j0) {
-                R gW[2], gDR[2], gDL[2];
-                int bW, bDR, bDL;
-#pragma unroll
-                for (int cc = 0; cc < 2; ++cc) gW[cc] = lane_prev(fe[cc]);
-                bW = lane_prev(nb) & 1;
-                if (par == 0) {
-                    // lower-right neighbour is this lane, lower-left the previous lane
-#pragma unroll
-                    for (int cc = 0; cc < 2; ++cc) {
-                        gDR[cc] = pUL[cc];
-                        gDL[cc] = lane_prev(pUR[cc]);
-                    }
-                    bDR = pbrk & 1;
-                    bDL = (lane_prev(pbrk) >> 1) & 1;
-                } else {
-#pragma unroll
-                    for (int cc = 0; cc < 2; ++cc) {
-                        gDR[cc] = lane_next(pUL[cc]);
-                        gDL[cc] = pUR[cc];
-                    }
-                    bDR = lane_next(pbrk) & 1;
-                    bDL = (pbrk >> 1) & 1;
-                }
+                R F[2];
+                int newmask;
+                row_force<R>(o, pUL, pUR, pbrk, par, rc.m, F, newmask);
                 if (own_lane && rc.f != kVoid) {
                     const int g = it.base + i + it.nx * j;
-                    R F[2];
-#pragma unroll
-                    for (int cc = 0; cc < 2; ++cc)
-                        F[cc] = ((((fe[cc] + ful[cc]) + fur[cc]) - gW[cc]) - gDR[cc]) - gDL[cc];
-                    const int newmask = rc.m | nb | (bW << 3) | (bDR << 4) | (bDL << 5);
                     if (newmask != rc.m) {
                         reinterpret_cast<uint8_t *>(P.mask)[g] = uint8_t(newmask);
                         if constexpr (BATCH) {
@@ -961,7 +1020,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                 pUL[cc] = ful[cc];
                 pUR[cc] = fur[cc];
             }
-            pbrk = (nb >> 1) & 3;
+            pbrk = (o.fb >> 1) & 3;
         };
 
         // K rotating row buffers: row j lives in B[(j - jstart) % K]; the
@@ -981,6 +1040,170 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         }
     }
     (void)red_lds;
+}
+
+// Two interior time steps per launch: temporal blocking of the row sweep.
+// Stage A advances the rows read from memory by one step and keeps each
+// row's new state (displacement, velocity, break bits) in registers; stage
+// B, one row behind, advances that state by a second step and writes it.
+// Stage A is valid on lanes 1..62 and stage B on lanes 2..61, so a wavefront
+// owns 60 columns (kSweepCols2) and rows j0..j1-1; stage A also advances
+// rows j0-1 and j1 and evaluates the forward springs of row j0-2, whose
+// forces act on row j0-1.  Velocities and break bits are read from P.v /
+// P.mask and written to P.v_out / P.mask_out: neighbouring wavefronts read
+// the sites a wavefront owns (as their halo rows and columns) during the
+// same launch, so nothing they read may be updated in place.  Every site
+// goes through exactly the operations of two single-step launches (shared
+// helpers, same order), so the state is bitwise the same; memory is read
+// and written once per two steps.  FP32-compensated lattices only.
+template <int PREC>
+__device__ inline void log_breaks(const StepParams &P, int g, const RowSprings<typename State<2, PREC>::R> &o,
+                                  int step) {
+    const int brks[3] = {o.be, o.bul, o.bur};
+    const double mgs[3] = {o.me, o.mul, o.mur};
+    const int pres[3] = {o.pe, o.pul, o.pur};
+    int rank = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (brks[d]) {
+            const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+            if (idx < P.ev_cap) {
+                lsm_event ev;
+                ev.increment = P.ctl->inc;
+                ev.step = P.ctl->step_base + step;
+                ev.spring_id = int64_t(P.sbase[g]) + rank;
+                ev.margin = mgs[d];
+                P.events[idx] = ev;
+            }
+        }
+        rank += pres[d];
+    }
+}
+
+template <int PREC, int PF>
+__global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_local) {
+    using S = State<2, PREC>;
+    using R = typename S::R;
+    using TTy = typename TT<PREC>::type;
+    __shared__ TTy tt[kMaxTypes];
+    __shared__ double mass_s[LSM_MAX_PHASES];
+    __shared__ R imass_s[LSM_MAX_PHASES];
+    for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    if (threadIdx.x < LSM_MAX_PHASES) {
+        mass_s[threadIdx.x] = P.mass[threadIdx.x];
+        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    }
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    const int per = P.sw2_nblocks >> 3;
+    const int Lb = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
+    const int w = Lb * (kBlock / 64) + wv;
+    if (w >= P.sw2_nwork) return;  // whole wavefronts; no barrier follows
+    SweepItem it;
+    it.base = 0;
+    it.nx = P.nx;
+    it.ny = P.ny;
+    it.i0 = (w % P.sw2_strips) * kSweepCols2 - 2;
+    it.j0 = (w / P.sw2_strips) * P.sw_rows;
+    it.j1 = min(it.j0 + P.sw_rows, P.ny);
+    const int i = it.i0 + lane;
+    const bool col_ok = i >= 0 && i < it.nx;
+    const bool own = col_ok && lane >= 2 && lane <= kSweepCols2 + 1;
+    const int j0 = it.j0, j1 = it.j1;
+    const int ja = j0 >= 2 ? j0 - 2 : 0;
+    const R h = R(0.5 * P.dt), dt = R(P.dt), gam = R(P.gamma);
+
+    R aUL[2] = {R(0), R(0)}, aUR[2] = {R(0), R(0)};  // stage A: forces carried from the row below
+    R bUL[2] = {R(0), R(0)}, bUR[2] = {R(0), R(0)};  // stage B
+    int abrk = 0, bbrk = 0;
+    SweepRow<R> Aprev;  // stage-A state of the previous row
+#pragma unroll
+    for (int c = 0; c < 2; ++c) Aprev.uh[c] = Aprev.ul[c] = Aprev.v[c] = R(0);
+    Aprev.f = kVoid;
+    Aprev.m = 0;
+
+    auto row_step = [&](int a, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
+        const int jn = a + PF + 1;
+        load_sweep_row<PREC>(P, it, i, col_ok, jn <= j1 + 1 ? jn : -1, jn >= j0 - 1, rn);
+        // ---- stage A: row a, step s
+        RowSprings<R> oa;
+        row_springs<PREC>(tt, P.types, rc, ru, a & 1, oa, P.a);
+        SweepRow<R> Acur = rc;
+        if (a >= j0 - 1) {
+            R F[2];
+            int nm;
+            row_force<R>(oa, aUL, aUR, abrk, a & 1, rc.m, F, nm);
+            Acur.m = nm;
+            if (rc.f != kVoid && flag_grip(rc.f) == 0) {
+                const int ph = flag_phase(rc.f);
+                R acc[2];
+                site_acc<2, PREC>(F, Acur.v, mass_s[ph], imass_s[ph], gam, acc);
+                mid_kick_drift<2, PREC>(Acur.uh, Acur.ul, Acur.v, acc, h, dt);
+            }
+            if (own && a >= j0 && a < j1 && rc.f != kVoid && oa.nb)
+                log_breaks<PREC>(P, i + it.nx * a, oa, step_local);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            aUL[c] = oa.ful[c];
+            aUR[c] = oa.fur[c];
+        }
+        abrk = (oa.fb >> 1) & 3;
+        // ---- stage B: row a - 1, step s + 1, from the stage-A states
+        const int b = a - 1;
+        if (b >= j0 - 1) {
+            RowSprings<R> ob;
+            row_springs<PREC>(tt, P.types, Aprev, Acur, b & 1, ob, P.a);
+            if (b >= j0) {
+                R F[2];
+                int nm;
+                row_force<R>(ob, bUL, bUR, bbrk, b & 1, Aprev.m, F, nm);
+                if (own && Aprev.f != kVoid) {
+                    const int g = i + it.nx * b;
+                    reinterpret_cast<uint8_t *>(P.mask_out)[g] = uint8_t(nm);
+                    if (ob.nb) log_breaks<PREC>(P, g, ob, step_local + 1);
+                    R uh[2], ul[2], v[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        uh[c] = Aprev.uh[c];
+                        ul[c] = Aprev.ul[c];
+                        v[c] = Aprev.v[c];
+                    }
+                    if (flag_grip(Aprev.f) == 0) {
+                        const int ph = flag_phase(Aprev.f);
+                        R acc[2];
+                        site_acc<2, PREC>(F, v, mass_s[ph], imass_s[ph], gam, acc);
+                        mid_kick_drift<2, PREC>(uh, ul, v, acc, h, dt);
+                    }
+                    S::store_v(P.v_out, g, P.nsites, v);
+                    S::store_u(P.u_out, g, P.nsites, uh, ul);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                bUL[c] = ob.ful[c];
+                bUR[c] = ob.fur[c];
+            }
+            bbrk = (ob.fb >> 1) & 3;
+        }
+        Aprev = Acur;
+    };
+
+    constexpr int K = PF + 2;
+    SweepRow<R> B[K];
+#pragma unroll
+    for (int t = 0; t <= PF; ++t) {
+        const int jj = ja + t;
+        load_sweep_row<PREC>(P, it, i, col_ok, jj <= j1 + 1 ? jj : -1, jj >= j0 - 1, B[t]);
+    }
+    for (int a = ja; a <= j1; a += K) {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+            if (a + t <= j1) row_step(a + t, B[t], B[(t + 1) % K], B[(t + PF + 1) % K]);
+        }
+    }
 }
 
 template <int DIM, int PREC>
@@ -1131,6 +1354,14 @@ hipError_t launch_finalize_batch(const StepParams &p, int dim, hipStream_t s, De
                                  const SpecDesc *specs, int nspec, int nsteps) {
     if (nspec <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_finalize_batch, dim3(nspec), dim3(kBlock), 0, s, p, recs, specs, nsteps, dim);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t s, int step_local) {
+    const dim3 grid(p.sw2_nblocks), block(kBlock);
+    if (!prec) return hipErrorInvalidValue;  // FP32-compensated lattices only
+    if (p.sw_pf >= 2) hipLaunchKernelGGL((k_sweep2d_x2<1, 2>), grid, block, 0, s, p, step_local);
+    else hipLaunchKernelGGL((k_sweep2d_x2<1, 1>), grid, block, 0, s, p, step_local);
     return hipGetLastError();
 }
 

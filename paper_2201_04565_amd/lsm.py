@@ -20,7 +20,7 @@ LSM_OK, LSM_EINVAL, LSM_ENOMEM, LSM_EHIP, LSM_EUNSTABLE, LSM_ESTATE = 0, -1, -2,
 TRI2D, SC3D = 0, 1
 FP64, FP32_KAHAN = 0, 1
 PRED_AFFINE, PRED_GRIPS_ONLY = 0, 1
-KERNEL_AUTO, KERNEL_GATHER, KERNEL_SWEEP = 0, 1, 2
+KERNEL_AUTO, KERNEL_GATHER, KERNEL_SWEEP, KERNEL_SWEEP2 = 0, 1, 2, 3
 MAX_PHASES = 8
 
 EXPORTS = (
@@ -50,7 +50,7 @@ class Record(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("variant", C.c_int32), ("rows_per_wave", C.c_int32), ("prefetch", C.c_int32),
-                ("reserved", C.c_int32), ("us_per_step", C.c_double)]
+                ("steps_per_launch", C.c_int32), ("us_per_step", C.c_double)]
 
 
 class Event(C.Structure):
@@ -318,7 +318,8 @@ class Lattice:
         return b.value
 
     def set_launch(self, variant="auto", rows_per_wave=0):
-        v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP}[variant]
+        v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
+             "sweep2": KERNEL_SWEEP2}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def set_prefetch(self, rows_ahead):
@@ -330,15 +331,17 @@ class Lattice:
         buf = (Tuning * 64)()
         n = C.c_int()
         self._check(self._L.lsm_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
-        names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep"}
+        names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2"}
         return [(names.get(t.variant, "auto"), t.rows_per_wave, t.prefetch, t.us_per_step)
                 for t in buf[:n.value]]
 
     def launch(self):
         t = Tuning()
         self._check(self._L.lsm_get_launch(self._h, C.byref(t)))
-        names = {KERNEL_AUTO: "auto", KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep"}
-        return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch)
+        names = {KERNEL_AUTO: "auto", KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep",
+                 KERNEL_SWEEP2: "sweep2"}
+        return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch,
+                    steps_per_launch=t.steps_per_launch)
 
     def synchronize(self):
         self.stream.synchronize()
@@ -388,6 +391,12 @@ class HostModel:
         nb = C.c_size_t()
         self._check(self._L.lsm_workspace_bytes(self._h, C.byref(nb)))
         return nb.value
+
+    def set_launch(self, variant="auto", rows_per_wave=0):
+        """Kernel variant whose bytes step_bytes reports (no device call)."""
+        v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
+             "sweep2": KERNEL_SWEEP2}[variant]
+        self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def step_bytes(self) -> int:
         b = C.c_int64()

@@ -77,7 +77,11 @@ def test_c2_full_size_counts():
     # closed form (W-1) H + (2W-1)(H-1) at 2048^2
     g = _model(inputs.c2_image(), inputs.WORKLOADS["c2"])
     assert (g.n, g.m) == (4194304, 12574721)
-    # algorithmic bytes per step: 24 B state read + written, flag, mask per site
+    # algorithmic bytes per launch of the default two-step sweep (two steps):
+    # 24 B state read + written, flag, break byte read + written per site
+    assert g.step_bytes() == 4194304 * 51
+    # the single-step sweep rewrites a break byte only when it changes
+    g.set_launch("sweep")
     assert g.step_bytes() == 4194304 * 50
 
 
