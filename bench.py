@@ -91,8 +91,8 @@ def batched_c4(args, torch, inputs, lsm):
     sizes = np.array([im.shape[0] for im in imgs])
     b = lsm.Batch.from_workload(wl, imgs, precision="fp32k", device="cuda:0")
     tune = b.autotune(20)
-    print(f"[bench] batch launch: rows {b.launch[0]}, prefetch {b.launch[1]}", file=sys.stderr,
-          flush=True)
+    launch = b.launch()
+    print(f"[bench] batch launch: {launch}", file=sys.stderr, flush=True)
     b.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -108,8 +108,8 @@ def batched_c4(args, torch, inputs, lsm):
                specimens_per_hour=len(imgs) / wall * 3600.0,
                mean_increments=float(n_inc.mean()),
                step_graph_GBs=site_steps * 50 / (ms * 1e-3) / 1e9,
-               launch=dict(rows_per_wave=b.launch[0], prefetch=b.launch[1]),
-               autotune_us_per_step={f"{r}x{p}": round(us, 1) for r, p, us in tune})
+               launch=launch,
+               autotune_us_per_step={f"{v} {r}x{p}": round(us, 1) for v, r, p, us in tune})
     del b
     torch.cuda.empty_cache()
     # plain: the same kernels, one specimen at a time, on a stratified sample

@@ -286,20 +286,26 @@ int lsm_batch_counts(const lsm_batch *b, int64_t *n_particles, int64_t *n_spring
 int lsm_batch_workspace_bytes(const lsm_batch *b, size_t *bytes);
 int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream);
 
-/* Row chunk and prefetch depth of the batched sweep (before the run;
- * results do not depend on them).                                         */
-int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch);
+/* Kernel, row chunk and prefetch depth of the batched sweep (before the
+ * run; results do not depend on them).  variant: LSM_KERNEL_SWEEP (one
+ * step per launch), LSM_KERNEL_SWEEP2 (two interior steps per launch,
+ * FP32-compensated batches only) or LSM_KERNEL_AUTO (SWEEP2 where it
+ * applies, the default).  After binding, a row chunk whose work items
+ * exceed the bound workspace is LSM_EINVAL.                               */
+int lsm_batch_set_launch(lsm_batch *b, int variant, int rows_per_wave, int prefetch);
+int lsm_batch_get_launch(const lsm_batch *b, lsm_tuning *out);
 
-/* Picks rows_per_wave and prefetch for this batch by timing candidate
- * launches (rows 2..16 per wavefront x prefetch 1..2, those the bound
- * workspace holds) on the live specimens, each over steps_per_trial
- * (2..1000) interior steps, and keeps the fastest.  Bound, before the run.
- * The trials read the state at rest and write only the second displacement
- * buffer (rewritten by the first increment) and the velocities (zeroed
- * afterwards), so the run's results are unchanged.  results (cap entries,
- * may be NULL when cap = 0) receives {LSM_KERNEL_SWEEP, rows, prefetch, 0,
- * mean microseconds per step} per candidate; *n_results their number.
- * Synchronises the stream.                                               */
+/* Picks the kernel (two-step sweep for FP32-compensated batches, and the
+ * one-step sweep), rows_per_wave and prefetch for this batch by timing
+ * candidate launches (rows 2..16 per wavefront x prefetch 1..2, those the
+ * bound workspace holds) on the live specimens, each over about
+ * steps_per_trial (2..1000) interior steps, and keeps the fastest.  Bound,
+ * before the run.  The trials read the state at rest and write only the
+ * second displacement, velocity and break-bit buffers (rewritten before
+ * they are read) and the velocities (zeroed afterwards), so the run's
+ * results are unchanged.  results (cap entries, may be NULL when cap = 0)
+ * receives {variant, rows, prefetch, 0, mean microseconds per step} per
+ * candidate; *n_results their number.  Synchronises the stream.         */
 int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, int cap,
                        int *n_results);
 

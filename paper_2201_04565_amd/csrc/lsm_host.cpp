@@ -504,8 +504,10 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         sizeof(Ctl),                                  // 0 ctl
         sizeof(DevRecord),                            // 1 record
         sizeof(TypeRec) * lsm::kMaxTypes,             // 2 types
-        ns,                                           // 3 flags
-        ns * h->mb,                                   // 4 mask
+        // flags and break bits end with one sentinel site (void, no broken
+        // spring) that the 2D sweep reads for lanes outside the lattice
+        ns + 1,                                       // 3 flags
+        (ns + 1) * h->mb,                             // 4 mask
         ns * 4,                                       // 5 sbase
         ns * h->ub,                                   // 6 U0
         ns * h->ub,                                   // 7 U1
@@ -516,7 +518,7 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         size_t(std::max<int64_t>(h->m, 1)) * sizeof(lsm_event),  // 12 events
         h->plist.size() * 4,                          // 13 particle list
         h->dim == 2 ? ns * h->vb : 0,                 // 14 second velocity buffer (two-step sweep)
-        h->dim == 2 ? ns * h->mb : 0,                 // 15 second break-bit buffer
+        h->dim == 2 ? (ns + 1) * h->mb : 0,           // 15 second break-bit buffer
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -565,6 +567,7 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->d_flags + h->nsites, lsm::kVoid, 1, h->stream));  // sentinel site
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->plist.empty())
         HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -1186,12 +1189,23 @@ struct lsm_batch {
     SpecDesc *d_specs = nullptr;
     uint32_t *d_spec_broken = nullptr;
     size_t max_items = 0;
+    // two-step sweep of the interior steps (FP32-compensated batches):
+    // 60-column work items, and velocities / break bits double-buffered
+    bool x2 = false;
+    std::vector<SweepItem> items2;
+    SweepItem *d_items2 = nullptr;
+    int32_t *d_nitems2 = nullptr;
+    size_t max_items2 = 0;
+    int capacity2 = 0;
+    void *d_V_alt = nullptr;
+    uint8_t *d_mask_alt = nullptr;
+    int vm = 0;
     int cur = 0;
     int32_t inc = 0;
     double eps = 0.0;
     bool ran = false;
     int capacity = 0;  // work items the captured graphs were sized for
-    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> tev;
     std::vector<hipEvent_t> ev_pool;
@@ -1241,14 +1255,56 @@ void batch_items_for(const lsm_batch *b, int64_t s, std::vector<SweepItem> &out)
         }
 }
 
+void batch_items2_for(const lsm_batch *b, int64_t s, std::vector<SweepItem> &out);
+
+// Work items of every specimen for the current row chunk: the largest
+// tables seen so far size the workspace.
+void size_items(lsm_batch *b) {
+    std::vector<SweepItem> t1, t2;
+    for (int64_t s = 0; s < b->nspec; ++s) {
+        batch_items_for(b, s, t1);
+        batch_items2_for(b, s, t2);
+    }
+    b->max_items = std::max(b->max_items, t1.size());
+    b->max_items2 = std::max(b->max_items2, t2.size());
+}
+
+// Work items of specimen s for the two-step sweep: 60-column strips.
+void batch_items2_for(const lsm_batch *b, int64_t s, std::vector<SweepItem> &out) {
+    const int32_t nx = b->nx[s], ny = b->ny[s];
+    const int32_t strips = int32_t((nx + lsm::kSweepCols2 - 1) / lsm::kSweepCols2);
+    for (int32_t j0 = 0; j0 < ny; j0 += b->sw_rows)
+        for (int32_t st = 0; st < strips; ++st) {
+            SweepItem it{};
+            it.base = int32_t(b->base[s]);
+            it.nx = nx;
+            it.ny = ny;
+            it.i0 = st * lsm::kSweepCols2 - 2;
+            it.j0 = j0;
+            it.j1 = std::min(j0 + b->sw_rows, ny);
+            it.strip = st;
+            it.strips = strips;
+            it.pbase = b->specs[s].pbase;
+            it.spec = int32_t(s);
+            out.push_back(it);
+        }
+}
+
 int upload_items(lsm_batch *b) {
     b->items.clear();
+    b->items2.clear();
     for (int64_t s = 0; s < b->nspec; ++s)
-        if (b->active[s]) batch_items_for(b, s, b->items);
-    const int32_t n = int32_t(b->items.size());
-    if (n) BHIPCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), size_t(n) * sizeof(SweepItem),
-                                     hipMemcpyHostToDevice, b->stream));
-    BHIPCHK(b, hipMemcpyAsync(b->d_nitems, &n, sizeof(n), hipMemcpyHostToDevice, b->stream));
+        if (b->active[s]) {
+            batch_items_for(b, s, b->items);
+            if (b->x2) batch_items2_for(b, s, b->items2);
+        }
+    const int32_t n[2] = {int32_t(b->items.size()), int32_t(b->items2.size())};
+    if (n[0]) BHIPCHK(b, hipMemcpyAsync(b->d_items, b->items.data(), size_t(n[0]) * sizeof(SweepItem),
+                                        hipMemcpyHostToDevice, b->stream));
+    if (n[1]) BHIPCHK(b, hipMemcpyAsync(b->d_items2, b->items2.data(), size_t(n[1]) * sizeof(SweepItem),
+                                        hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_nitems, &n[0], sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->d_nitems2, &n[1], sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));  // n lives on this stack frame
     return LSM_OK;
 }
@@ -1275,6 +1331,10 @@ StepParams batch_params(const lsm_batch *b, int in_buf, int out_buf) {
     p.sw_pf = b->sw_pf;
     p.items = b->d_items;
     p.n_items = b->d_nitems;
+    p.items2 = b->d_items2;
+    p.n_items2 = b->d_nitems2;
+    p.v_out = b->d_V_alt;
+    p.mask_out = b->d_mask_alt;
     p.spec_broken = b->d_spec_broken;
     return p;
 }
@@ -1284,21 +1344,44 @@ void drop_batch_graphs(lsm_batch *b) {
     b->graphs.clear();
 }
 
+// Interior steps local .. local + chunk - 1: pairs per launch with the
+// two-step sweep (reading the current velocity / break-bit buffers and
+// writing the other ones, swapping them per launch), single steps otherwise.
+hipError_t batch_mid_steps(const lsm_batch *b, int chunk, int local) {
+    hipError_t le = hipSuccess;
+    int c = b->cur;
+    void *vc = b->d_V, *va = b->d_V_alt;
+    uint8_t *mc = b->d_mask, *ma = b->d_mask_alt;
+    int s = 0;
+    while (s < chunk && le == hipSuccess) {
+        StepParams p = batch_params(b, c, c ^ 1);
+        p.v = vc;
+        p.mask = mc;
+        p.v_out = va;
+        p.mask_out = ma;
+        if (b->x2 && s + 1 < chunk) {
+            le = lsm::launch_sweep2d_x2_batch(p, b->prec, b->stream, local + s, b->capacity2);
+            std::swap(vc, va);
+            std::swap(mc, ma);
+            s += 2;
+        } else {
+            le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, local + s, b->capacity);
+            s += 1;
+        }
+        c ^= 1;
+    }
+    return le;
+}
+
 int batch_mid_chunk(lsm_batch *b, int chunk, int local) {
-    const auto key = std::make_tuple(chunk, b->cur, local, b->capacity);
+    const auto key = std::make_tuple(chunk, b->cur, b->vm, local, b->capacity, b->capacity2);
     hipGraphExec_t exec = nullptr;
     auto itg = b->graphs.find(key);
     if (itg != b->graphs.end()) {
         exec = itg->second;
     } else {
         BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        int c = b->cur;
-        hipError_t le = hipSuccess;
-        for (int s = 0; s < chunk && le == hipSuccess; ++s) {
-            StepParams p = batch_params(b, c, c ^ 1);
-            le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, local + s, b->capacity);
-            c ^= 1;
-        }
+        const hipError_t le = batch_mid_steps(b, chunk, local);
         hipGraph_t graph = nullptr;
         hipError_t ce = hipStreamEndCapture(b->stream, &graph);
         if (le != hipSuccess || ce != hipSuccess) {
@@ -1336,7 +1419,13 @@ int batch_mid_chunk(lsm_batch *b, int chunk, int local) {
             if (b->active[s]) sites += double(b->npart[s]);
         b->timed_site_steps += sites * chunk;
     }
-    b->cur ^= (chunk & 1);
+    const int x2_launches = b->x2 ? chunk / 2 : 0;
+    b->cur ^= (chunk - x2_launches) & 1;  // one buffer swap per launch
+    if (x2_launches & 1) {
+        std::swap(b->d_V, b->d_V_alt);
+        std::swap(b->d_mask, b->d_mask_alt);
+        b->vm ^= 1;
+    }
     return LSM_OK;
 }
 
@@ -1457,9 +1546,8 @@ int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *img
     b->ntot = ntot;
     b->mtot = mtot;
     b->active.assign(size_t(n), 1);
-    std::vector<SweepItem> tmp;
-    for (int64_t s = 0; s < n; ++s) batch_items_for(b, s, tmp);
-    b->max_items = tmp.size();
+    b->x2 = b->prec != 0;  // the two-step sweep runs FP32-compensated batches
+    size_items(b);
     *out = b;
     return LSM_OK;
 }
@@ -1485,15 +1573,17 @@ int lsm_batch_counts(const lsm_batch *b, int64_t *n_particles, int64_t *n_spring
     return LSM_OK;
 }
 
+constexpr int kBatchRegions = 17;
+
 static size_t batch_layout(const lsm_batch *b, size_t *off) {
     const size_t ns = size_t(b->nsites);
     const size_t rb = b->prec ? 4 : 8;
-    const size_t sizes[13] = {
+    const size_t sizes[kBatchRegions] = {
         sizeof(Ctl),
         sizeof(DevRecord) * size_t(b->nspec),
         sizeof(TypeRec) * lsm::kMaxTypes,
-        ns,                                   // flags
-        ns,                                   // mask
+        ns + 1,                               // flags (+ a void sentinel site)
+        ns + 1,                               // mask (+ the sentinel's zero bits)
         ns * 16,                              // U0
         ns * 16,                              // U1
         ns * 2 * rb,                          // V
@@ -1502,9 +1592,13 @@ static size_t batch_layout(const lsm_batch *b, size_t *off) {
         std::max<size_t>(b->max_items, 1) * sizeof(SweepItem),
         sizeof(int32_t),
         size_t(b->nspec) * (sizeof(SpecDesc) + sizeof(uint32_t)),
+        b->prec ? std::max<size_t>(b->max_items2, 1) * sizeof(SweepItem) : 0,  // two-step items
+        sizeof(int32_t),                                                         // their number
+        b->prec ? ns * 2 * rb : 0,                                               // second V
+        b->prec ? ns + 1 : 0,                                                    // second mask
     };
     size_t o = 0;
-    for (int i = 0; i < 13; ++i) {
+    for (int i = 0; i < kBatchRegions; ++i) {
         off[i] = o;
         o += align256(sizes[i]);
     }
@@ -1513,7 +1607,7 @@ static size_t batch_layout(const lsm_batch *b, size_t *off) {
 
 int lsm_batch_workspace_bytes(const lsm_batch *b, size_t *bytes) {
     if (!b || !bytes) return LSM_EINVAL;
-    size_t off[13];
+    size_t off[kBatchRegions];
     *bytes = batch_layout(b, off);
     return LSM_OK;
 }
@@ -1522,7 +1616,7 @@ int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream) {
     if (!b || !dptr) return LSM_EINVAL;
     if (b->bound) return bfail(b, LSM_ESTATE, "already bound");
     if (reinterpret_cast<uintptr_t>(dptr) % 256 != 0) return bfail(b, LSM_EINVAL, "workspace must be 256-byte aligned");
-    size_t off[13];
+    size_t off[kBatchRegions];
     const size_t need = batch_layout(b, off);
     if (bytes < need) return bfail(b, LSM_ENOMEM, "workspace too small");
     char *w = static_cast<char *>(dptr);
@@ -1541,9 +1635,15 @@ int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream) {
     b->d_nitems = reinterpret_cast<int32_t *>(w + off[11]);
     b->d_specs = reinterpret_cast<SpecDesc *>(w + off[12]);
     b->d_spec_broken = reinterpret_cast<uint32_t *>(w + off[12] + size_t(b->nspec) * sizeof(SpecDesc));
+    b->d_items2 = reinterpret_cast<SweepItem *>(w + off[13]);
+    b->d_nitems2 = reinterpret_cast<int32_t *>(w + off[14]);
+    b->d_V_alt = w + off[15];
+    b->d_mask_alt = reinterpret_cast<uint8_t *>(w + off[16]);
+    b->vm = 0;
     BHIPCHK(b, hipMemsetAsync(w, 0, need, b->stream));
     BHIPCHK(b, hipMemcpyAsync(b->d_types, b->types, sizeof(b->types), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipMemcpyAsync(b->d_flags, b->flags.data(), b->flags.size(), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemsetAsync(b->d_flags + b->nsites, lsm::kVoid, 1, b->stream));  // sentinel site
     BHIPCHK(b, hipMemcpyAsync(b->d_specs, b->specs.data(), b->specs.size() * sizeof(SpecDesc),
                               hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));
@@ -1551,23 +1651,42 @@ int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream) {
     return upload_items(b);
 }
 
-int lsm_batch_set_launch(lsm_batch *b, int rows_per_wave, int prefetch) {
+// Row chunk rows fits the bound workspace (both item tables).
+static bool batch_rows_fit(lsm_batch *b, int rows) {
+    const int keep = b->sw_rows;
+    b->sw_rows = rows;
+    std::vector<SweepItem> t1, t2;
+    for (int64_t s = 0; s < b->nspec; ++s) {
+        batch_items_for(b, s, t1);
+        if (b->prec) batch_items2_for(b, s, t2);
+    }
+    b->sw_rows = keep;
+    return t1.size() <= b->max_items && t2.size() <= b->max_items2;
+}
+
+int lsm_batch_set_launch(lsm_batch *b, int variant, int rows_per_wave, int prefetch) {
     if (!b) return LSM_EINVAL;
     if (b->ran) return bfail(b, LSM_ESTATE, "set the launch before running");
     if (rows_per_wave < kMinSweepRows || rows_per_wave > kMaxSweepRows || prefetch < 1 || prefetch > 3)
         return bfail(b, LSM_EINVAL, "launch out of range");
+    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_SWEEP && variant != LSM_KERNEL_SWEEP2)
+        return bfail(b, LSM_EINVAL, "batches run the row sweep (LSM_KERNEL_SWEEP or LSM_KERNEL_SWEEP2)");
+    if (variant == LSM_KERNEL_SWEEP2 && !b->prec)
+        return bfail(b, LSM_EINVAL, "the two-step sweep runs FP32-compensated batches only");
+    if (b->bound && !batch_rows_fit(b, rows_per_wave))
+        return bfail(b, LSM_EINVAL, "rows_per_wave too small for the bound workspace");
+    b->x2 = variant == LSM_KERNEL_SWEEP ? false : b->prec != 0;
     b->sw_rows = rows_per_wave;
     b->sw_pf = prefetch;
     drop_batch_graphs(b);
-    std::vector<SweepItem> tmp;
-    for (int64_t s = 0; s < b->nspec; ++s) batch_items_for(b, s, tmp);
-    if (tmp.size() > b->max_items) {
-        // more items than the workspace was sized for: only shapes with at
-        // most as many items are accepted after binding
-        if (b->bound) return bfail(b, LSM_EINVAL, "rows_per_wave too small for the bound workspace");
-        b->max_items = tmp.size();
-    }
+    if (!b->bound) size_items(b);  // more items than before: a larger workspace
     return b->bound ? upload_items(b) : LSM_OK;
+}
+
+int lsm_batch_get_launch(const lsm_batch *b, lsm_tuning *out) {
+    if (!b || !out) return LSM_EINVAL;
+    *out = lsm_tuning{b->x2 ? LSM_KERNEL_SWEEP2 : LSM_KERNEL_SWEEP, b->sw_rows, b->sw_pf, b->x2 ? 2 : 1, 0.0};
+    return LSM_OK;
 }
 
 int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, int cap, int *n_results) {
@@ -1576,17 +1695,14 @@ int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, i
     if (b->ran) return bfail(b, LSM_ESTATE, "tune before the run");
     if (steps_per_trial < 2 || steps_per_trial > kGraphChunk || cap < 0 || (cap > 0 && !results))
         return bfail(b, LSM_EINVAL, "steps_per_trial must be 2..1000");
-    struct Cand { int rows, pf; };
+    struct Cand { bool x2; int rows, pf; };
     std::vector<Cand> cands;
-    for (int rows : {2, 4, 6, 8, 12, 16})
-        for (int pf : {1, 2}) {
-            std::vector<SweepItem> tmp;
-            const int keep = b->sw_rows;
-            b->sw_rows = rows;
-            for (int64_t s = 0; s < b->nspec; ++s) batch_items_for(b, s, tmp);
-            b->sw_rows = keep;
-            if (tmp.size() <= b->max_items) cands.push_back({rows, pf});
-        }
+    for (bool x2 : {true, false}) {
+        if (x2 && !b->prec) continue;
+        for (int rows : {2, 4, 6, 8, 12, 16})
+            for (int pf : {1, 2})
+                if (batch_rows_fit(b, rows)) cands.push_back({x2, rows, pf});
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BHIPCHK(b, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
@@ -1594,21 +1710,28 @@ int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, i
         return bfail(b, LSM_EHIP, "hipEventCreate failed");
     }
     double best = 1e300;
-    Cand bestc = {b->sw_rows, b->sw_pf};
+    Cand bestc = {b->x2, b->sw_rows, b->sw_pf};
     int nres = 0, rc = LSM_OK;
     for (const Cand &c : cands) {
+        b->x2 = c.x2;
         b->sw_rows = c.rows;
         b->sw_pf = c.pf;
         rc = upload_items(b);
         if (rc) break;
-        const int capacity = int(b->items.size());
-        // every trial step reads the displacements at rest and writes the
-        // other buffer: plain launches, no graph
+        const int capacity = int(b->items.size()), capacity2 = int(b->items2.size());
+        // every trial launch reads the state at rest (displacements, and for
+        // the two-step sweep velocities and break bits) and writes only the
+        // other buffers: plain launches, no graph
         StepParams p = batch_params(b, b->cur, b->cur ^ 1);
-        hipError_t le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, 1, capacity);  // warm-up
+        auto trial = [&](int step) {
+            return c.x2 ? lsm::launch_sweep2d_x2_batch(p, b->prec, b->stream, step, capacity2)
+                        : lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, step, capacity);
+        };
+        const int per = c.x2 ? 2 : 1;
+        const int launches = std::max(1, steps_per_trial / per);
+        hipError_t le = trial(1);  // warm-up
         if (le == hipSuccess) le = hipEventRecord(e0, b->stream);
-        for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s)
-            le = lsm::launch_sweep2d_batch(p, b->prec, lsm::kMid, b->stream, 1 + s, capacity);
+        for (int s = 0; s < launches && le == hipSuccess; ++s) le = trial(1 + per * s);
         if (le == hipSuccess) le = hipEventRecord(e1, b->stream);
         if (le == hipSuccess) le = hipStreamSynchronize(b->stream);
         float ms = 0.0f;
@@ -1617,8 +1740,9 @@ int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, i
             rc = bfail(b, LSM_EHIP, std::string("autotune trial: ") + hipGetErrorString(le));
             break;
         }
-        const double us = 1e3 * double(ms) / steps_per_trial;
-        if (nres < cap) results[nres] = lsm_tuning{LSM_KERNEL_SWEEP, c.rows, c.pf, 0, us};
+        const double us = 1e3 * double(ms) / (launches * per);
+        if (nres < cap)
+            results[nres] = lsm_tuning{c.x2 ? LSM_KERNEL_SWEEP2 : LSM_KERNEL_SWEEP, c.rows, c.pf, 0, us};
         ++nres;
         if (us < best) {
             best = us;
@@ -1628,12 +1752,15 @@ int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, i
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    b->x2 = bestc.x2;
     b->sw_rows = bestc.rows;
     b->sw_pf = bestc.pf;
     drop_batch_graphs(b);
     // the trials moved the velocities (tiny residual forces of the lattice at
     // rest): back to the zero state of a fresh batch
-    BHIPCHK(b, hipMemsetAsync(b->d_V, 0, size_t(b->nsites) * 2 * (b->prec ? 4 : 8), b->stream));
+    const size_t vbytes = size_t(b->nsites) * 2 * (b->prec ? 4 : 8);
+    BHIPCHK(b, hipMemsetAsync(b->d_V, 0, vbytes, b->stream));
+    if (b->prec) BHIPCHK(b, hipMemsetAsync(b->d_V_alt, 0, vbytes, b->stream));
     rc = upload_items(b);  // synchronises
     if (rc) return rc;
     if (n_results) *n_results = nres;
@@ -1662,12 +1789,14 @@ int lsm_batch_run(lsm_batch *b, double d_eps, int64_t steps_per_inc, int32_t max
     int rc = upload_items(b);
     if (rc) return rc;
     b->capacity = int(b->items.size());
+    b->capacity2 = int(b->items2.size());
     for (int32_t it = 1; it <= max_inc && !b->items.empty(); ++it) {
         const double eps_new = b->eps + d_eps;
         const int nitems = int(b->items.size());
         if (nitems * 2 < b->capacity) {  // shrink the launch when half the work has retired
             drop_batch_graphs(b);
             b->capacity = nitems;
+            b->capacity2 = int(b->items2.size());
         }
         StepParams p = batch_params(b, b->cur, b->cur ^ 1);
         BHIPCHK(b, lsm::launch_increment_batch(p, b->prec, b->stream, eps_new, d_eps, it,

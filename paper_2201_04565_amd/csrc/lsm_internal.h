@@ -96,6 +96,8 @@ struct StepParams {
     int32_t sw2_strips, sw2_nwork, sw2_nblocks;
     void *v_out;
     void *mask_out;
+    const SweepItem *items2;   // batch work items of the two-step sweep (60-column strips)
+    const int32_t *n_items2;   // their number (device)
     // batch of specimens (2D sweep only)
     const SweepItem *items;  // active work items
     const int32_t *n_items;  // number of active work items (device)
@@ -113,6 +115,9 @@ hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t s
 // Two interior steps (step_local and step_local + 1) in one launch of the
 // 2D row sweep; reads u_in, writes u_out.
 hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t stream, int step_local);
+// Batch version over capacity2 two-step work items (items beyond *p.n_items2 exit at once).
+hipError_t launch_sweep2d_x2_batch(const StepParams &p, int prec, hipStream_t stream, int step_local,
+                                   int capacity2);
 hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
 // Batch versions: the grid covers `capacity` work items; items beyond
 // *p.n_items exit at once.

@@ -21,6 +21,8 @@
 // narrow band of rc^2 are re-tested in FP64 from the compensated state.
 #include <math.h>
 
+#include <type_traits>
+
 #include "lsm_internal.h"
 
 namespace lsm {
@@ -181,8 +183,12 @@ template <int PREC>
 struct TT;
 template <>
 struct TT<1> {
-    using type = float4;  // k, k r0, rc^2, r0
-    __device__ static type make(const TypeRec &t) { return make_float4(t.k32, t.kr0_32, t.rc2_32, t.r0_32); }
+    // k, k r0, r^2 above which the break test is redone in FP64 (just
+    // below rc^2), r0
+    using type = float4;
+    __device__ static type make(const TypeRec &t) {
+        return make_float4(t.k32, t.kr0_32, t.rc2_32 - kBand2 * t.rc2_32, t.r0_32);
+    }
 };
 struct D4 {
     double x, y, z, w;
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
             bool have64 = false;
             if constexpr (PREC == 1) {
                 // FP32 test; inside the band (or above rc) the FP64 test decides
-                if (r2 > T.z - kBand2 * T.z) {
+                if (r2 > T.z) {
                     double s2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
@@ -669,9 +675,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, DevRecord *re
 // has a fixed order per site, so results do not depend on the launch shape.
 
 // wave_shl:1 -> lane l reads lane l + 1; wave_shr:1 -> lane l reads lane l - 1
-// (the edge lane keeps its own value; edge lanes are never owned).
-__device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xF, 0xF, false); }
-__device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xF, 0xF, false); }
+// (the edge lane reads zero; edge lanes are never owned).
+__device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
+__device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
+// Site flags: the edge lane reads a void site, so its springs across the
+// wavefront edge are absent (zero positions there would otherwise send them
+// down the FP64 break test on every row).
+__device__ inline int flag_next(int f) { return __builtin_amdgcn_update_dpp(int(kVoid), f, 0x130, 0xF, 0xF, false); }
+__device__ inline int flag_prev(int f) { return __builtin_amdgcn_update_dpp(int(kVoid), f, 0x138, 0xF, 0xF, false); }
 __device__ inline float lane_next(float x) { return __int_as_float(lane_next(__float_as_int(x))); }
 __device__ inline float lane_prev(float x) { return __int_as_float(lane_prev(__float_as_int(x))); }
 __device__ inline double lane_next(double x) {
@@ -685,6 +696,16 @@ __device__ inline double lane_prev(double x) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
+// Calls f(std::integral_constant<int, t>) for t = T .. N - 1 in order, so
+// each unrolled row can use t in template arguments.
+template <int T, int N, class F>
+__device__ __attribute__((always_inline)) inline void unroll_rows(F &&f) {
+    if constexpr (T < N) {
+        f(std::integral_constant<int, T>{});
+        unroll_rows<T + 1, N>(f);
+    }
+}
+
 template <class R>
 struct SweepRow {
     R uh[2], ul[2], v[2];
@@ -694,23 +715,23 @@ struct SweepRow {
 template <int PREC>
 __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok,
                                       int jj, bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
-    // Loads are unconditional from an always-valid site (the specimen's
-    // first site when the row or column is outside it), so no branch joins
-    // on a pending load.  Outside the specimen only the flag is replaced
-    // (void): springs with a void end and unowned sites never read the
-    // displacement or velocity of such a lane.
+    // Loads are unconditional from always-valid addresses, so no branch
+    // joins on a pending load and no select waits for one.  Outside the
+    // specimen a lane reads its flag and break bits from the sentinel site
+    // after the last one (void, no bits) and its displacement and velocity
+    // from the specimen's first site: springs with a void end and unowned
+    // sites never use them.
     using S = State<2, PREC>;
     using R = typename S::R;
     const bool ok = col_ok && jj >= 0 && jj < it.ny;
     const int g = it.base + (ok ? i + it.nx * jj : 0);
+    const int gf = ok ? g : int(P.nsites);
     S::load_u(P.u_in, g, P.nsites, r.uh, r.ul);
-    const int f = P.flags[g];
-    const int m = reinterpret_cast<const uint8_t *>(P.mask)[g];
+    r.f = P.flags[gf];
+    r.m = reinterpret_cast<const uint8_t *>(P.mask)[gf];
     r.v[0] = R(0);
     r.v[1] = R(0);
     if (want_v) S::load_v(P.v, g, P.nsites, r.v);
-    r.f = ok ? f : int(kVoid);
-    r.m = ok ? m : 0;
 }
 
 // Work item of wavefront w: computed for a single lattice, read from the
@@ -740,7 +761,10 @@ __device__ inline bool sweep_item(const StepParams &P, int w, SweepItem &it) {
 
 // One forward spring of site p towards q (lattice vector (ex, ey)).  Returns
 // the force on p in f (zero if absent or broken), present = both ends are
-// particles, brk = broken at this evaluation.
+// particles, brk = broken at this evaluation, margin = (r - rc) / rc when
+// brk (left unset otherwise), ti = type index (meaningful when present).
+// The FP32 form runs the same instructions on every lane and masks absent
+// and broken springs at the end; only the FP64 test near rc branches.
 template <int PREC, class TTy>
 __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, int mask, int d,
                                   typename State<2, PREC>::R ex, typename State<2, PREC>::R ey,
@@ -751,20 +775,20 @@ __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, i
                                   typename State<2, PREC>::R *f, int &present, int &brk,
                                   double &margin, int &ti) {
     using R = typename State<2, PREC>::R;
-    f[0] = R(0);
-    f[1] = R(0);
     present = (fp != kVoid) && (fq != kVoid);
     brk = 0;
-    margin = 0.0;
-    ti = present ? flag_phase(fp) * LSM_MAX_PHASES + flag_phase(fq) : 0;
-    if (!present || (mask & (1 << d))) return;
-    R dv[2];
-    dv[0] = ex + ((qh[0] - ph[0]) + (ql[0] - pl[0]));
-    dv[1] = ey + ((qh[1] - ph[1]) + (ql[1] - pl[1]));
-    const R r2 = dv[0] * dv[0] + dv[1] * dv[1];
-    const TTy T = tt[ti];
     if constexpr (PREC == 1) {
-        if (r2 > T.z - kBand2 * T.z) {
+        // phases are below LSM_MAX_PHASES = 8, so masking keeps void lanes in
+        // the table
+        ti = (fp & 7) * LSM_MAX_PHASES + (fq & 7);
+        const bool act = present && !(mask & (1 << d));
+        R dv[2];
+        dv[0] = ex + ((qh[0] - ph[0]) + (ql[0] - pl[0]));
+        dv[1] = (qh[1] - ph[1]) + (ql[1] - pl[1]);
+        if (d != 0) dv[1] = ey + dv[1];  // the east spring has ey = 0
+        const R r2 = dv[0] * dv[0] + dv[1] * dv[1];
+        const TTy T = tt[ti];
+        if (act && r2 > T.z) {
             const double dx = ex64 + ((double(qh[0]) - double(ph[0])) + (double(ql[0]) - double(pl[0])));
             const double dy = ey64 + ((double(qh[1]) - double(ph[1])) + (double(ql[1]) - double(pl[1])));
             const double r64 = sqrt(dx * dx + dy * dy);
@@ -772,12 +796,23 @@ __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, i
             brk = r64 > rc;
             margin = (r64 - rc) / rc;
         }
-        if (brk) return;
-        const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
+        // r2 is a normal number on every active spring; other lanes are
+        // masked below whatever rsq returns for them
+        const float rinv = __builtin_amdgcn_rsqf(r2);
         const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
-        f[0] = coef * dv[0];
-        f[1] = coef * dv[1];
+        const bool ok = act && !brk;
+        f[0] = ok ? coef * dv[0] : R(0);
+        f[1] = ok ? coef * dv[1] : R(0);
     } else {
+        f[0] = R(0);
+        f[1] = R(0);
+        ti = present ? flag_phase(fp) * LSM_MAX_PHASES + flag_phase(fq) : 0;
+        if (!present || (mask & (1 << d))) return;
+        R dv[2];
+        dv[0] = ex + ((qh[0] - ph[0]) + (ql[0] - pl[0]));
+        dv[1] = ey + ((qh[1] - ph[1]) + (ql[1] - pl[1]));
+        const R r2 = dv[0] * dv[0] + dv[1] * dv[1];
+        const TTy T = tt[ti];
         const double r = sqrt(r2);
         brk = r > T.z;
         if (brk) {
@@ -820,10 +855,10 @@ struct RowSprings {
     int fb;                                          // bits 0..2: broken now or before
 };
 
-template <int PREC, class TTy>
+template <int PREC, int PAR, class TTy>
 __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
                                    const SweepRow<typename State<2, PREC>::R> &rc,
-                                   const SweepRow<typename State<2, PREC>::R> &ru, int par,
+                                   const SweepRow<typename State<2, PREC>::R> &ru,
                                    RowSprings<typename State<2, PREC>::R> &o, double a64) {
     using R = typename State<2, PREC>::R;
     const R a = R(a64), hy = R(kHalfSqrt3 * a64);
@@ -835,8 +870,8 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
         o.eh[cc] = lane_next(rc.uh[cc]);
         o.el[cc] = PREC ? lane_next(rc.ul[cc]) : R(0);
     }
-    ef = lane_next(rc.f);
-    if (par == 0) {
+    ef = flag_next(rc.f);
+    if constexpr (PAR == 0) {
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             o.ulh[cc] = lane_prev(ru.uh[cc]);
@@ -844,7 +879,7 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
             o.urh[cc] = ru.uh[cc];
             o.url[cc] = ru.ul[cc];
         }
-        ulf = lane_prev(ru.f);
+        ulf = flag_prev(ru.f);
         urf = ru.f;
     } else {
 #pragma unroll
@@ -855,7 +890,7 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
             o.url[cc] = PREC ? lane_next(ru.ul[cc]) : R(0);
         }
         ulf = ru.f;
-        urf = lane_next(ru.f);
+        urf = flag_next(ru.f);
     }
     fwd_spring<PREC>(tt, types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, o.eh, o.el, ef, o.fe, o.pe,
                      o.be, o.me, o.te);
@@ -875,15 +910,15 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
 // the neighbours' broken-now-or-before bits, so they do not depend on
 // whether the owner of a neighbouring site has already stored its new bits
 // when this lane reads them.  DPP moves: every lane must call this.
-template <class R>
-__device__ inline void row_force(const RowSprings<R> &o, const R *pUL, const R *pUR, int pbrk, int par, int m,
+template <int PAR, class R>
+__device__ inline void row_force(const RowSprings<R> &o, const R *pUL, const R *pUR, int pbrk, int m,
                                  R *F, int &newmask) {
     R gW[2], gDR[2], gDL[2];
     int bW, bDR, bDL;
 #pragma unroll
     for (int cc = 0; cc < 2; ++cc) gW[cc] = lane_prev(o.fe[cc]);
     bW = lane_prev(o.fb) & 1;
-    if (par == 0) {
+    if constexpr (PAR == 0) {
         // lower-right neighbour is this lane, lower-left the previous lane
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
@@ -939,6 +974,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const int j0 = it.j0;
         const int j1 = it.j1;
         const int jstart = j0 > 0 ? j0 - 1 : 0;
+        const int js = jstart & ~1;  // even: the parity of each unrolled row is a constant
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
 
         R pUL[2] = {R(0), R(0)}, pUR[2] = {R(0), R(0)};
@@ -946,11 +982,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         // Row j is computed from rc (row j) and ru (row j + 1) while rn
         // receives row j + 2; the three buffers rotate roles so that no
         // register copy forces an early wait on the prefetched row.
-        auto row_step = [&](int j, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
+        auto row_step = [&](auto parc, int j, SweepRow<R> &rc, SweepRow<R> &ru,
+                            SweepRow<R> &rn) __attribute__((always_inline)) {
+            constexpr int PAR = decltype(parc)::value;
             load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
-            const int par = j & 1;
             RowSprings<R> o;
-            row_springs<PREC>(tt, P.types, rc, ru, par, o, P.a);
+            row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a);
             const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
             const R *fe = o.fe, *ful = o.ful, *fur = o.fur;
             const int pe = o.pe, pul = o.pul, pur = o.pur, be = o.be, bul = o.bul, bur = o.bur;
@@ -960,7 +997,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
             if (j >= j0) {
                 R F[2];
                 int newmask;
-                row_force<R>(o, pUL, pUR, pbrk, par, rc.m, F, newmask);
+                row_force<PAR>(o, pUL, pUR, pbrk, rc.m, F, newmask);
                 if (own_lane && rc.f != kVoid) {
                     const int g = it.base + i + it.nx * j;
                     if (newmask != rc.m) {
@@ -1023,20 +1060,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
             pbrk = (o.fb >> 1) & 3;
         };
 
-        // K rotating row buffers: row j lives in B[(j - jstart) % K]; the
-        // step for row j prefetches row j + PF + 1.
-        constexpr int K = PF + 2;
+        // K (even) rotating row buffers: row j lives in B[(j - js) % K]; the
+        // step for row j prefetches row j + PF + 1.  A row below jstart
+        // (js = jstart - 1) is loaded as void: it has no springs and no work.
+        constexpr int K = (PF + 3) & ~1;
         SweepRow<R> B[K];
 #pragma unroll
         for (int t = 0; t <= PF; ++t) {
-            const int jj = jstart + t;
-            load_sweep_row<PREC>(P, it, i, col_ok, jj <= j1 ? jj : -1, jj >= j0, B[t]);
+            const int jj = js + t;
+            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, jj >= j0, B[t]);
         }
-        for (int j = jstart; j < j1; j += K) {
-#pragma unroll
-            for (int t = 0; t < K; ++t) {
-                if (j + t < j1) row_step(j + t, B[t], B[(t + 1) % K], B[(t + PF + 1) % K]);
-            }
+        for (int j = js; j < j1; j += K) {
+            unroll_rows<0, K>([&](auto tc) __attribute__((always_inline)) {
+                constexpr int t = decltype(tc)::value;
+                if (j + t < j1)
+                    row_step(std::integral_constant<int, t & 1>{}, j + t, B[t], B[(t + 1) % K],
+                             B[(t + PF + 1) % K]);
+            });
         }
     }
     (void)red_lds;
@@ -1080,7 +1120,7 @@ __device__ inline void log_breaks(const StepParams &P, int g, const RowSprings<t
     }
 }
 
-template <int PREC, int PF>
+template <int PREC, int PF, int BATCH>
 __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_local) {
     using S = State<2, PREC>;
     using R = typename S::R;
@@ -1100,50 +1140,60 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
     const int per = P.sw2_nblocks >> 3;
     const int Lb = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
     const int w = Lb * (kBlock / 64) + wv;
-    if (w >= P.sw2_nwork) return;  // whole wavefronts; no barrier follows
     SweepItem it;
-    it.base = 0;
-    it.nx = P.nx;
-    it.ny = P.ny;
-    it.i0 = (w % P.sw2_strips) * kSweepCols2 - 2;
-    it.j0 = (w / P.sw2_strips) * P.sw_rows;
-    it.j1 = min(it.j0 + P.sw_rows, P.ny);
+    if constexpr (BATCH) {
+        if (w >= *P.n_items2) return;  // whole wavefronts; no barrier follows
+        it = P.items2[w];
+    } else {
+        if (w >= P.sw2_nwork) return;
+        it.base = 0;
+        it.nx = P.nx;
+        it.ny = P.ny;
+        it.i0 = (w % P.sw2_strips) * kSweepCols2 - 2;
+        it.j0 = (w / P.sw2_strips) * P.sw_rows;
+        it.j1 = min(it.j0 + P.sw_rows, P.ny);
+    }
     const int i = it.i0 + lane;
     const bool col_ok = i >= 0 && i < it.nx;
     const bool own = col_ok && lane >= 2 && lane <= kSweepCols2 + 1;
     const int j0 = it.j0, j1 = it.j1;
     const int ja = j0 >= 2 ? j0 - 2 : 0;
+    const int a0 = ja & ~1;  // even: the parity of each unrolled row is a constant
     const R h = R(0.5 * P.dt), dt = R(P.dt), gam = R(P.gamma);
 
     R aUL[2] = {R(0), R(0)}, aUR[2] = {R(0), R(0)};  // stage A: forces carried from the row below
     R bUL[2] = {R(0), R(0)}, bUR[2] = {R(0), R(0)};  // stage B
     int abrk = 0, bbrk = 0;
-    SweepRow<R> Aprev;  // stage-A state of the previous row
-#pragma unroll
-    for (int c = 0; c < 2; ++c) Aprev.uh[c] = Aprev.ul[c] = Aprev.v[c] = R(0);
-    Aprev.f = kVoid;
-    Aprev.m = 0;
 
-    auto row_step = [&](int a, SweepRow<R> &rc, SweepRow<R> &ru, SweepRow<R> &rn) {
+    // Row a: stage A at step s on rc (row a, advanced in place, so rc then
+    // holds the stage-A state), ru = row a + 1, rn receives row a + PF + 1;
+    // stage B at step s + 1 on row a - 1 from Aprev (its stage-A state).
+    auto row_step = [&](auto parc, int a, SweepRow<R> &rc, const SweepRow<R> &ru, SweepRow<R> &rn,
+                        const SweepRow<R> &Aprev) __attribute__((always_inline)) {
+        constexpr int PAR = decltype(parc)::value;  // a & 1
         const int jn = a + PF + 1;
         load_sweep_row<PREC>(P, it, i, col_ok, jn <= j1 + 1 ? jn : -1, jn >= j0 - 1, rn);
         // ---- stage A: row a, step s
         RowSprings<R> oa;
-        row_springs<PREC>(tt, P.types, rc, ru, a & 1, oa, P.a);
-        SweepRow<R> Acur = rc;
+        row_springs<PREC, PAR>(tt, P.types, rc, ru, oa, P.a);
+        SweepRow<R> &Acur = rc;
         if (a >= j0 - 1) {
             R F[2];
             int nm;
-            row_force<R>(oa, aUL, aUR, abrk, a & 1, rc.m, F, nm);
+            row_force<PAR>(oa, aUL, aUR, abrk, rc.m, F, nm);
             Acur.m = nm;
-            if (rc.f != kVoid && flag_grip(rc.f) == 0) {
-                const int ph = flag_phase(rc.f);
+            if (Acur.f != kVoid && flag_grip(Acur.f) == 0) {
+                const int ph = flag_phase(Acur.f);
                 R acc[2];
                 site_acc<2, PREC>(F, Acur.v, mass_s[ph], imass_s[ph], gam, acc);
                 mid_kick_drift<2, PREC>(Acur.uh, Acur.ul, Acur.v, acc, h, dt);
             }
-            if (own && a >= j0 && a < j1 && rc.f != kVoid && oa.nb)
-                log_breaks<PREC>(P, i + it.nx * a, oa, step_local);
+            if (own && a >= j0 && a < j1 && Acur.f != kVoid && oa.nb) {
+                if constexpr (BATCH)  // batches keep a per-specimen count instead of a log
+                    atomicAdd(&P.spec_broken[it.spec], uint32_t(oa.be + oa.bul + oa.bur));
+                else
+                    log_breaks<PREC>(P, i + it.nx * a, oa, step_local);
+            }
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -1155,15 +1205,20 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
         const int b = a - 1;
         if (b >= j0 - 1) {
             RowSprings<R> ob;
-            row_springs<PREC>(tt, P.types, Aprev, Acur, b & 1, ob, P.a);
+            row_springs<PREC, PAR ^ 1>(tt, P.types, Aprev, Acur, ob, P.a);
             if (b >= j0) {
                 R F[2];
                 int nm;
-                row_force<R>(ob, bUL, bUR, bbrk, b & 1, Aprev.m, F, nm);
+                row_force<PAR ^ 1>(ob, bUL, bUR, bbrk, Aprev.m, F, nm);
                 if (own && Aprev.f != kVoid) {
-                    const int g = i + it.nx * b;
+                    const int g = it.base + i + it.nx * b;
                     reinterpret_cast<uint8_t *>(P.mask_out)[g] = uint8_t(nm);
-                    if (ob.nb) log_breaks<PREC>(P, g, ob, step_local + 1);
+                    if (ob.nb) {
+                        if constexpr (BATCH)
+                            atomicAdd(&P.spec_broken[it.spec], uint32_t(ob.be + ob.bul + ob.bur));
+                        else
+                            log_breaks<PREC>(P, g, ob, step_local + 1);
+                    }
                     R uh[2], ul[2], v[2];
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
@@ -1188,21 +1243,32 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
             }
             bbrk = (ob.fb >> 1) & 3;
         }
-        Aprev = Acur;
     };
 
-    constexpr int K = PF + 2;
+    // K (even) rotating row buffers: row a lives in B[(a - a0) % K]; the
+    // step for row a prefetches row a + PF + 1 into B[(a - a0 + PF + 1) % K],
+    // which with K >= PF + 3 is neither row a - 1 (stage B still reads it)
+    // nor row a + 1.  A row below ja (a0 = ja - 1) is loaded as void: no
+    // springs, and stage B skips the row below it.  B[K - 1] starts as a
+    // void row: the stage-A state of row a0 - 1 seen by the first stage B.
+    constexpr int K = (PF + 4) & ~1;
     SweepRow<R> B[K];
 #pragma unroll
     for (int t = 0; t <= PF; ++t) {
-        const int jj = ja + t;
-        load_sweep_row<PREC>(P, it, i, col_ok, jj <= j1 + 1 ? jj : -1, jj >= j0 - 1, B[t]);
+        const int jj = a0 + t;
+        load_sweep_row<PREC>(P, it, i, col_ok, jj >= ja && jj <= j1 + 1 ? jj : -1, jj >= j0 - 1, B[t]);
     }
-    for (int a = ja; a <= j1; a += K) {
 #pragma unroll
-        for (int t = 0; t < K; ++t) {
-            if (a + t <= j1) row_step(a + t, B[t], B[(t + 1) % K], B[(t + PF + 1) % K]);
-        }
+    for (int c = 0; c < 2; ++c) B[K - 1].uh[c] = B[K - 1].ul[c] = B[K - 1].v[c] = R(0);
+    B[K - 1].f = kVoid;
+    B[K - 1].m = 0;
+    for (int a = a0; a <= j1; a += K) {
+        unroll_rows<0, K>([&](auto tc) __attribute__((always_inline)) {
+            constexpr int t = decltype(tc)::value;
+            if (a + t <= j1)
+                row_step(std::integral_constant<int, t & 1>{}, a + t, B[t], B[(t + 1) % K], B[(t + PF + 1) % K],
+                         B[(t + K - 1) % K]);
+        });
     }
 }
 
@@ -1342,6 +1408,16 @@ hipError_t launch_sweep2d_batch(const StepParams &p, int prec, int mode, hipStre
                 : launch_sweep_t<0, 1>(q, mode, s, step_local, q.sw_nblocks);
 }
 
+hipError_t launch_sweep2d_x2_batch(const StepParams &p, int prec, hipStream_t s, int step_local, int capacity2) {
+    if (!prec) return hipErrorInvalidValue;  // FP32-compensated batches only
+    StepParams q = p;
+    q.sw2_nblocks = batch_blocks(capacity2);
+    const dim3 grid(q.sw2_nblocks), block(kBlock);
+    if (q.sw_pf >= 2) hipLaunchKernelGGL((k_sweep2d_x2<1, 2, 1>), grid, block, 0, s, q, step_local);
+    else hipLaunchKernelGGL((k_sweep2d_x2<1, 1, 1>), grid, block, 0, s, q, step_local);
+    return hipGetLastError();
+}
+
 hipError_t launch_increment_batch(const StepParams &p, int prec, hipStream_t s, double eps_new,
                                   double d_eps, int inc, int affine, int capacity) {
     const dim3 grid(unsigned((capacity + kBlock / 64 - 1) / (kBlock / 64))), block(kBlock);
@@ -1360,8 +1436,8 @@ hipError_t launch_finalize_batch(const StepParams &p, int dim, hipStream_t s, De
 hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t s, int step_local) {
     const dim3 grid(p.sw2_nblocks), block(kBlock);
     if (!prec) return hipErrorInvalidValue;  // FP32-compensated lattices only
-    if (p.sw_pf >= 2) hipLaunchKernelGGL((k_sweep2d_x2<1, 2>), grid, block, 0, s, p, step_local);
-    else hipLaunchKernelGGL((k_sweep2d_x2<1, 1>), grid, block, 0, s, p, step_local);
+    if (p.sw_pf >= 2) hipLaunchKernelGGL((k_sweep2d_x2<1, 2, 0>), grid, block, 0, s, p, step_local);
+    else hipLaunchKernelGGL((k_sweep2d_x2<1, 1, 0>), grid, block, 0, s, p, step_local);
     return hipGetLastError();
 }
 

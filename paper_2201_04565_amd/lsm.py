@@ -408,6 +408,7 @@ BATCH_EXPORTS = (
     "lsm_batch_create", "lsm_batch_destroy", "lsm_batch_last_error", "lsm_batch_counts",
     "lsm_batch_workspace_bytes", "lsm_batch_bind", "lsm_batch_set_launch", "lsm_batch_run",
     "lsm_batch_read", "lsm_batch_set_timing", "lsm_batch_read_timing", "lsm_batch_autotune",
+    "lsm_batch_get_launch",
 )
 
 
@@ -428,7 +429,8 @@ def _load_batch(L):
     L.lsm_batch_counts.argtypes = [vp, P(i64), P(i64)]
     L.lsm_batch_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
     L.lsm_batch_bind.argtypes = [vp, vp, C.c_size_t, vp]
-    L.lsm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int]
+    L.lsm_batch_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+    L.lsm_batch_get_launch.argtypes = [vp, C.POINTER(Tuning)]
     L.lsm_batch_autotune.argtypes = [vp, C.c_int, vp, C.c_int, P(C.c_int)]
     L.lsm_batch_run.argtypes = [vp, dbl, i64, i32, P(FailRule)]
     L.lsm_batch_read.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -500,18 +502,25 @@ class Batch:
         except Exception:
             pass
 
-    def set_launch(self, rows_per_wave=4, prefetch=1):
-        self._check(self._L.lsm_batch_set_launch(self._h, int(rows_per_wave), int(prefetch)))
+    def set_launch(self, rows_per_wave=4, prefetch=1, variant="auto"):
+        v = {"auto": KERNEL_AUTO, "sweep": KERNEL_SWEEP, "sweep2": KERNEL_SWEEP2}[variant]
+        self._check(self._L.lsm_batch_set_launch(self._h, v, int(rows_per_wave), int(prefetch)))
+
+    def launch(self):
+        t = Tuning()
+        self._check(self._L.lsm_batch_get_launch(self._h, C.byref(t)))
+        names = {KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2"}
+        return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch,
+                    steps_per_launch=t.steps_per_launch)
 
     def autotune(self, steps_per_trial=20):
         """Times the candidate launches on this batch before its run and keeps
-        the fastest; returns [(rows_per_wave, prefetch, us_per_step)]."""
+        the fastest; returns [(variant, rows_per_wave, prefetch, us_per_step)]."""
         buf = (Tuning * 64)()
         n = C.c_int()
         self._check(self._L.lsm_batch_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
-        self.launch = min(((t.rows_per_wave, t.prefetch, t.us_per_step) for t in buf[:n.value]),
-                          key=lambda r: r[2])[:2]
-        return [(t.rows_per_wave, t.prefetch, t.us_per_step) for t in buf[:n.value]]
+        names = {KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2"}
+        return [(names[t.variant], t.rows_per_wave, t.prefetch, t.us_per_step) for t in buf[:n.value]]
 
     def run(self, d_eps, steps_per_inc, max_inc, drop=0.01):
         rule = FailRule(float(drop))

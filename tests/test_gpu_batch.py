@@ -65,10 +65,13 @@ def test_batch_rows_independent_and_order_free(lsm):
     imgs = specimens()
     say("batch launch-shape independence and specimen order")
     out = []
-    for rows, order in ((4, None), (13, None), (4, [5, 3, 1, 0, 2, 4])):
+    cases = ((4, None, "sweep"), (13, None, "sweep"), (4, [5, 3, 1, 0, 2, 4], "sweep"),
+             (4, None, "sweep2"), (7, None, "sweep2"), (16, [5, 3, 1, 0, 2, 4], "sweep2"))
+    for rows, order, variant in cases:
         use = imgs if order is None else [imgs[i] for i in order]
         b = lsm.Batch.from_workload(wl, use, precision="fp32k")
-        b.set_launch(rows, 1)
+        b.set_launch(rows, 1, variant)
+        assert b.launch()["steps_per_launch"] == (2 if variant == "sweep2" else 1)
         b.run(wl["d_eps"], 200, 25)
         r = b.read()
         if order is not None:
@@ -89,8 +92,9 @@ def test_batch_autotune_keeps_results(lsm):
         b = lsm.Batch.from_workload(wl, imgs, precision="fp32k")
         if tune:
             res = b.autotune(20)
-            assert len(res) >= 4 and all(r[2] > 0 for r in res)
-            say(f"  picked rows {b.launch[0]} prefetch {b.launch[1]} of {len(res)} candidates")
+            assert len(res) >= 4 and all(r[3] > 0 for r in res)
+            assert {r[0] for r in res} == {"sweep", "sweep2"}
+            say(f"  picked {b.launch()} of {len(res)} candidates")
         b.run(wl["d_eps"], 200, 25)
         out.append(b.read())
     for key in ("sigma_xx", "n_inc", "modulus", "strength", "n_broken"):
