@@ -257,8 +257,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--kernel", choices=("sweep", "sweep2"), default="sweep2",
                     help="2D step kernel: one or two interior steps per launch")
-    ap.add_argument("--launch", default="8,1", metavar="ROWS,PREFETCH",
-                    help="sweep launch: rows per wavefront, prefetch depth")
+    ap.add_argument("--launch", default="0,1", metavar="ROWS,PREFETCH",
+                    help="sweep launch: rows per wavefront (0: the library's occupancy-model "
+                         "default), prefetch depth")
     ap.add_argument("--autotune", action="store_true",
                     help="pick the launch with lsm_autotune instead of --launch")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched C4 measurement")

@@ -232,8 +232,11 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);
 
 /* Launch shape of the step kernel (used by the autotuner).  variant is one
  * of LSM_KERNEL_*; rows_per_wave (2..4096, 0 = keep) sets the row chunk of
- * the 2D sweep.  Results are bitwise independent of rows_per_wave.  Only
- * between relaxations (LSM_ESTATE otherwise); drops cached graphs.        */
+ * the 2D sweep.  Until a row chunk is set, the sweep picks one per kernel
+ * and prefetch depth from the bound device's compute units and the
+ * kernel's occupancy (wavefronts of nearly equal work filling whole rounds
+ * of resident slots).  Results are bitwise independent of rows_per_wave.
+ * Only between relaxations (LSM_ESTATE otherwise); drops cached graphs.  */
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave);
 
 /* Rows the 2D sweep prefetches ahead of the row it computes (1..3).
@@ -297,7 +300,7 @@ int lsm_batch_get_launch(const lsm_batch *b, lsm_tuning *out);
 
 /* Picks the kernel (two-step sweep for FP32-compensated batches, and the
  * one-step sweep), rows_per_wave and prefetch for this batch by timing
- * candidate launches (rows 2..16 per wavefront x prefetch 1..2, those the
+ * candidate launches (rows 4..32 per wavefront x prefetch 1..2, those the
  * bound workspace holds) on the live specimens, each over about
  * steps_per_trial (2..1000) interior steps, and keeps the fastest.  Bound,
  * before the run.  The trials read the state at rest and write only the

@@ -56,6 +56,8 @@ struct lsm_handle {
     int variant = LSM_KERNEL_AUTO;  // step kernel family
     int sw_rows = 0;                // rows per wavefront of the 2D row sweep (0: default)
     int sw_pf = 1;                  // rows prefetched ahead in the sweep
+    int cus = 0;                    // compute units of the bound device
+    mutable int auto_rows[2][4]{};  // default row chunk per (two-step, prefetch), 0 until known
     size_t ub = 0, vb = 0, mb = 0;  // bytes per site of u, v, mask
     // device
     hipStream_t stream = nullptr;
@@ -229,8 +231,40 @@ bool use_sweep2(const lsm_handle *h) {
     return h->dim == 2 && h->prec &&
            (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
 }
-// rows per wavefront: as set, else the measured best of the kernel in use
-int rows_of(const lsm_handle *h) { return h->sw_rows ? h->sw_rows : (use_sweep2(h) ? 8 : 4); }
+// Default rows per wavefront of the 2D sweep.  The sweep's wavefronts all
+// carry about the same work, (R + 1) row evaluations for the one-step
+// kernel and (2 R + 3) for the two-step kernel at R rows, and run in
+// ceil(W / slots) rounds when W of them compete for the device's resident
+// wavefront slots: pick R in 4..32 with the least rounds x work per
+// wavefront (ties: fewer rows, more parallel work).
+int model_rows(const lsm_handle *h) {
+    const int two = use_sweep2(h) ? 1 : 0;
+    const int pf = std::min(std::max(h->sw_pf, 1), 3);
+    int &cached = h->auto_rows[two][pf];
+    if (cached) return cached;
+    const int fallback = two ? 8 : 4;
+    if (h->cus <= 0) return fallback;
+    const int64_t slots = int64_t(h->cus) * lsm::sweep_waves_per_cu(two, h->prec, pf);
+    if (slots <= 0) return fallback;
+    const int64_t cols = two ? lsm::kSweepCols2 : lsm::kSweepCols;
+    const int64_t strips = (h->nx + cols - 1) / cols;
+    int64_t best_cost = INT64_MAX;
+    int best = fallback;
+    for (int r = 4; r <= 32; ++r) {
+        const int64_t waves = strips * ((h->ny + r - 1) / r);
+        const int64_t rounds = (waves + slots - 1) / slots;
+        const int64_t cost = rounds * (two ? 2 * r + 3 : r + 1);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = r;
+        }
+    }
+    cached = best;
+    return best;
+}
+
+// rows per wavefront: as set, else the occupancy model's choice
+int rows_of(const lsm_handle *h) { return h->sw_rows ? h->sw_rows : model_rows(h); }
 
 
 // Start / interior / end step with the kernel family chosen for this lattice.
@@ -565,6 +599,12 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_mask_alt = w + off[15];
     h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            h->cus = 0;  // the default row chunk falls back to a fixed one
+    }
     HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemsetAsync(h->d_flags + h->nsites, lsm::kVoid, 1, h->stream));  // sentinel site
@@ -1699,7 +1739,7 @@ int lsm_batch_autotune(lsm_batch *b, int steps_per_trial, lsm_tuning *results, i
     std::vector<Cand> cands;
     for (bool x2 : {true, false}) {
         if (x2 && !b->prec) continue;
-        for (int rows : {2, 4, 6, 8, 12, 16})
+        for (int rows : {4, 6, 8, 12, 16, 20, 24, 32})
             for (int pf : {1, 2})
                 if (batch_rows_fit(b, rows)) cands.push_back({x2, rows, pf});
     }

@@ -115,6 +115,9 @@ hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t s
 // Two interior steps (step_local and step_local + 1) in one launch of the
 // 2D row sweep; reads u_in, writes u_out.
 hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t stream, int step_local);
+// Wavefronts of the interior-step row sweep (two-step or one-step kernel)
+// resident per CU; 0 if the runtime cannot tell.
+int sweep_waves_per_cu(int two_step, int prec, int pf);
 // Batch version over capacity2 two-step work items (items beyond *p.n_items2 exit at once).
 hipError_t launch_sweep2d_x2_batch(const StepParams &p, int prec, hipStream_t stream, int step_local,
                                    int capacity2);

@@ -1433,6 +1433,20 @@ hipError_t launch_finalize_batch(const StepParams &p, int dim, hipStream_t s, De
     return hipGetLastError();
 }
 
+int sweep_waves_per_cu(int two_step, int prec, int pf) {
+    // resident workgroups of the interior-step kernel per CU, in wavefronts
+    int blocks = 0;
+    hipError_t e;
+    if (two_step)
+        e = pf >= 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep2d_x2<1, 2, 0>, kBlock, 0)
+                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep2d_x2<1, 1, 0>, kBlock, 0);
+    else if (prec)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep2d<1, kMid, 1, 0>, kBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_sweep2d<0, kMid, 1, 0>, kBlock, 0);
+    return e == hipSuccess ? blocks * (kBlock / 64) : 0;
+}
+
 hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t s, int step_local) {
     const dim3 grid(p.sw2_nblocks), block(kBlock);
     if (!prec) return hipErrorInvalidValue;  // FP32-compensated lattices only
