@@ -232,7 +232,9 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);
 
 /* Launch shape of the step kernel (used by the autotuner).  variant is one
  * of LSM_KERNEL_*; rows_per_wave (2..4096, 0 = keep) sets the row chunk of
- * the 2D sweep.  Until a row chunk is set, the sweep picks one per kernel
+ * the 2D sweep (lattices of fewer than 2^28 sites; larger 2D lattices
+ * run the gather kernel, and asking for a sweep there is LSM_EINVAL).
+ * Until a row chunk is set, the sweep picks one per kernel
  * and prefetch depth from the bound device's compute units and the
  * kernel's occupancy (wavefronts of nearly equal work filling whole rounds
  * of resident slots).  Results are bitwise independent of rows_per_wave.
@@ -280,7 +282,8 @@ typedef struct {
 } lsm_fail_rule;
 
 /* imgs[s]: host image of specimen s (x fastest); dims[3 s .. 3 s + 2] =
- * (nx, ny, 1).  2D triangular lattices only (LSM_EINVAL otherwise).      */
+ * (nx, ny, 1).  2D triangular lattices only, fewer than 2^28 sites in all
+ * (LSM_EINVAL otherwise).                                                */
 int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *imgs,
                      const int64_t *dims, lsm_batch **out);
 void lsm_batch_destroy(lsm_batch *b);

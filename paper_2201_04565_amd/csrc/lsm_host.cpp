@@ -225,11 +225,12 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     return p;
 }
 
-bool use_sweep(const lsm_handle *h) { return h->dim == 2 && h->variant != LSM_KERNEL_GATHER; }
+bool use_sweep(const lsm_handle *h) {
+    return h->dim == 2 && h->variant != LSM_KERNEL_GATHER && h->nsites <= lsm::kSweepMaxSites;
+}
 // interior steps in pairs per launch: the default for 2D FP32-compensated lattices
 bool use_sweep2(const lsm_handle *h) {
-    return h->dim == 2 && h->prec &&
-           (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
+    return use_sweep(h) && h->prec && (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
 }
 // Default rows per wavefront of the 2D sweep.  The sweep's wavefronts all
 // carry about the same work, (R + 1) row evaluations for the one-step
@@ -1077,6 +1078,8 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
         return fail(h, LSM_EINVAL, "row sweep is 2D only");
     if (variant == LSM_KERNEL_SWEEP2 && !h->prec)
         return fail(h, LSM_EINVAL, "the two-step sweep runs FP32-compensated lattices only");
+    if ((variant == LSM_KERNEL_SWEEP || variant == LSM_KERNEL_SWEEP2) && h->built && h->nsites > lsm::kSweepMaxSites)
+        return fail(h, LSM_EINVAL, "the row sweep runs lattices of fewer than 2^28 sites");
     if (rows_per_wave != 0 && (rows_per_wave < kMinSweepRows || rows_per_wave > kMaxSweepRows))
         return fail(h, LSM_EINVAL, "rows_per_wave out of range");
     if (h->half) return fail(h, LSM_ESTATE, "change the launch only between relaxations");
@@ -1530,8 +1533,8 @@ int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *img
         b->ny[s] = int32_t(sy);
         b->base[s] = off;
         off += sx * sy;
-        if (off >= (int64_t(1) << 31) - 1) {
-            delete b;
+        if (sx > lsm::kSweepMaxSites || sy > lsm::kSweepMaxSites || off > lsm::kSweepMaxSites) {
+            delete b;  // the row sweep's 32-bit offsets
             return LSM_EINVAL;
         }
         b->specs[s].pbase = int32_t(pb);

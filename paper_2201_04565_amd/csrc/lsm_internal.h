@@ -16,6 +16,10 @@ constexpr uint8_t kVoid = 0xFF;
 constexpr int kNumPartials = 24;  // virial[9], kinetic[9], pe, ke, nonfinite, 3 spare
 constexpr int kSweepCols = 62;    // owned columns per wavefront in the 2D row sweep
 constexpr int kSweepCols2 = 60;   // owned columns per wavefront of the two-step sweep
+// The row sweeps address 16-byte site records with 32-bit byte offsets:
+// lattices and batches they run hold fewer sites than this (one more, the
+// sentinel site, follows the last).
+constexpr int64_t kSweepMaxSites = (int64_t(1) << 28) - 1;
 
 // Site flag byte: bits 0-3 phase, bits 4-5 grip (1 left column, 2 right column).
 __host__ __device__ inline int flag_phase(uint8_t f) { return f & 0x0F; }

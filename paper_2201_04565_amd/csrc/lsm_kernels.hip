@@ -287,8 +287,38 @@ __device__ inline void mid_kick_drift(typename State<DIM, PREC>::R *uph, typenam
 // clamped.  On entry w is the particle's stored velocity (full step at the
 // start of an increment, half step otherwise); F is the spring force at the
 // current positions.
-template <int DIM, int PREC, int MODE>
-__device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, double mass,
+// Where a site's new state goes: by site index (gather kernel) ...
+template <int DIM, int PREC>
+struct SiteStore {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    int g;
+    int64_t ns;
+    __device__ void u(void *U, const R *hi, const R *lo) const { S::store_u(U, g, ns, hi, lo); }
+    __device__ void v(void *V, const R *w) const { S::store_v(V, g, ns, w); }
+};
+
+// ... or, in the 2D sweeps, by 32-bit byte offsets from the array base
+// (the sweeps run lattices and batches of fewer than 2^28 sites, so a
+// 16-byte record's offset fits), which the accesses take as base + offset.
+template <int PREC>
+struct RowStore {
+    using R = typename State<2, PREC>::R;
+    using V2 = typename std::conditional<PREC == 1, float2, double2>::type;
+    uint32_t g;  // site index
+    __device__ void u(void *U, const R *hi, const R *lo) const {
+        char *b = static_cast<char *>(U) + g * 16u;
+        if constexpr (PREC == 1) *reinterpret_cast<float4 *>(b) = make_float4(hi[0], hi[1], lo[0], lo[1]);
+        else *reinterpret_cast<double2 *>(b) = make_double2(hi[0], hi[1]);
+    }
+    __device__ void v(void *V, const R *w) const {
+        char *b = static_cast<char *>(V) + g * uint32_t(sizeof(V2));
+        *reinterpret_cast<V2 *>(b) = V2{w[0], w[1]};
+    }
+};
+
+template <int DIM, int PREC, int MODE, class ST>
+__device__ inline void integrate_site(const StepParams &P, const ST &st, uint8_t fp, double mass,
                                       typename State<DIM, PREC>::R inv_mass,
                                       typename State<DIM, PREC>::R *uph,
                                       typename State<DIM, PREC>::R *upl,
@@ -298,12 +328,12 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, do
     using R = typename S::R;
     if (flag_grip(fp) != 0) {
         // clamped: displacement carried over, velocity stays zero
-        if constexpr (MODE != kEnd) S::store_u(P.u_out, g, P.nsites, uph, upl);
+        if constexpr (MODE != kEnd) st.u(P.u_out, uph, upl);
         if constexpr (MODE == kEnd) {
             R z[DIM];
 #pragma unroll
             for (int c = 0; c < DIM; ++c) z[c] = R(0);
-            S::store_v(P.acc, g, P.nsites, z);
+            st.v(P.acc, z);
         }
         return;
     }
@@ -319,18 +349,18 @@ __device__ inline void integrate_site(const StepParams &P, int g, uint8_t fp, do
             w[c] = w[c] + h * acc[c];
             comp_add(uph[c], upl[c], dt * w[c]);
         }
-        S::store_u(P.u_out, g, P.nsites, uph, upl);
-        S::store_v(P.v, g, P.nsites, w);
+        st.u(P.u_out, uph, upl);
+        st.v(P.v, w);
     } else if constexpr (MODE == kMid) {
         mid_kick_drift<DIM, PREC>(uph, upl, w, acc, h, dt);
-        S::store_u(P.u_out, g, P.nsites, uph, upl);
-        S::store_v(P.v, g, P.nsites, w);
+        st.u(P.u_out, uph, upl);
+        st.v(P.v, w);
     } else if constexpr (MODE == kEnd) {
         // close the step on the full-step velocity
 #pragma unroll
         for (int c = 0; c < DIM; ++c) w[c] = w[c] + h * acc[c];
-        S::store_v(P.v, g, P.nsites, w);
-        S::store_v(P.acc, g, P.nsites, acc);
+        st.v(P.v, w);
+        st.v(P.acc, acc);
         const double mm = mass;
 #pragma unroll
         for (int aa = 0; aa < DIM; ++aa) {
@@ -547,7 +577,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
         } else {
             R w[DIM];
             if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
-            integrate_site<DIM, PREC, MODE>(P, g, fp, mass_s[pa], imass_s[pa], uph, upl, F, w, red);
+            integrate_site<DIM, PREC, MODE>(P, SiteStore<DIM, PREC>{g, P.nsites}, fp, mass_s[pa], imass_s[pa],
+                                            uph, upl, F, w, red);
         }
     }
 
@@ -713,25 +744,41 @@ struct SweepRow {
 };
 
 template <int PREC>
-__device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok,
-                                      int jj, bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
+__device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok, int jj,
+                                      bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
     // Loads are unconditional from always-valid addresses, so no branch
-    // joins on a pending load and no select waits for one.  Outside the
+    // joins on a pending load and no select waits for one.  Off the
     // specimen a lane reads its flag and break bits from the sentinel site
     // after the last one (void, no bits) and its displacement and velocity
     // from the specimen's first site: springs with a void end and unowned
-    // sites never use them.
-    using S = State<2, PREC>;
-    using R = typename S::R;
+    // sites never use them.  Offsets are 32-bit: the sweeps run lattices
+    // and batches of fewer than 2^28 sites.
+    using R = typename State<2, PREC>::R;
     const bool ok = col_ok && jj >= 0 && jj < it.ny;
-    const int g = it.base + (ok ? i + it.nx * jj : 0);
-    const int gf = ok ? g : int(P.nsites);
-    S::load_u(P.u_in, g, P.nsites, r.uh, r.ul);
+    const uint32_t g = uint32_t(it.base) + (ok ? uint32_t(i + it.nx * jj) : 0u);
+    const uint32_t gf = ok ? g : uint32_t(P.nsites);
+    const char *ub = static_cast<const char *>(P.u_in) + g * 16u;
+    if constexpr (PREC == 1) {
+        const float4 t = *reinterpret_cast<const float4 *>(ub);
+        r.uh[0] = t.x; r.uh[1] = t.y; r.ul[0] = t.z; r.ul[1] = t.w;
+    } else {
+        const double2 t = *reinterpret_cast<const double2 *>(ub);
+        r.uh[0] = t.x; r.uh[1] = t.y; r.ul[0] = 0.0; r.ul[1] = 0.0;
+    }
     r.f = P.flags[gf];
     r.m = reinterpret_cast<const uint8_t *>(P.mask)[gf];
     r.v[0] = R(0);
     r.v[1] = R(0);
-    if (want_v) S::load_v(P.v, g, P.nsites, r.v);
+    if (want_v) {
+        const char *vb = static_cast<const char *>(P.v) + g * uint32_t(2 * sizeof(R));
+        if constexpr (PREC == 1) {
+            const float2 t = *reinterpret_cast<const float2 *>(vb);
+            r.v[0] = t.x; r.v[1] = t.y;
+        } else {
+            const double2 t = *reinterpret_cast<const double2 *>(vb);
+            r.v[0] = t.x; r.v[1] = t.y;
+        }
+    }
 }
 
 // Work item of wavefront w: computed for a single lattice, read from the
@@ -999,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                 int newmask;
                 row_force<PAR>(o, pUL, pUR, pbrk, rc.m, F, newmask);
                 if (own_lane && rc.f != kVoid) {
-                    const int g = it.base + i + it.nx * j;
+                    const uint32_t g = uint32_t(it.base + i + it.nx * j);
                     if (newmask != rc.m) {
                         reinterpret_cast<uint8_t *>(P.mask)[g] = uint8_t(newmask);
                         if constexpr (BATCH) {
@@ -1036,7 +1083,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
                         if (pur && !(mk & 4))
                             spring_stress64(P.types[tur], 0.5 * a64, hy64, rc.uh, rc.ul, urh, url, red);
                     }
-                    integrate_site<2, PREC, MODE>(P, g, uint8_t(rc.f), mass_s[flag_phase(rc.f)],
+                    integrate_site<2, PREC, MODE>(P, RowStore<PREC>{g}, uint8_t(rc.f),
+                                                  mass_s[flag_phase(rc.f)],
                                                   imass_s[flag_phase(rc.f)], rc.uh,
                                                   rc.ul, F, rc.v, red);
                 }
@@ -1211,7 +1259,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
                 int nm;
                 row_force<PAR ^ 1>(ob, bUL, bUR, bbrk, Aprev.m, F, nm);
                 if (own && Aprev.f != kVoid) {
-                    const int g = it.base + i + it.nx * b;
+                    const uint32_t g = uint32_t(it.base + i + it.nx * b);
                     reinterpret_cast<uint8_t *>(P.mask_out)[g] = uint8_t(nm);
                     if (ob.nb) {
                         if constexpr (BATCH)
@@ -1232,8 +1280,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
                         site_acc<2, PREC>(F, v, mass_s[ph], imass_s[ph], gam, acc);
                         mid_kick_drift<2, PREC>(uh, ul, v, acc, h, dt);
                     }
-                    S::store_v(P.v_out, g, P.nsites, v);
-                    S::store_u(P.u_out, g, P.nsites, uh, ul);
+                    const RowStore<PREC> st{g};
+                    st.v(P.v_out, v);
+                    st.u(P.u_out, uh, ul);
                 }
             }
 #pragma unroll

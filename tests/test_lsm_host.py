@@ -140,6 +140,20 @@ def test_empty_and_degenerate_images():
     assert (g.n, g.m) == (7, 6)
 
 
+def test_batch_rejects_more_sites_than_the_sweep_addresses():
+    # the row sweeps use 32-bit byte offsets into 16-byte site records: a
+    # batch holds fewer than 2^28 sites (sizes are checked before any image
+    # is read, so tiny buffers stand in for the images here)
+    L = lsm._load_batch(lsm.load_library())
+    cfg = lsm.make_config(lattice=lsm.TRI2D, k=[[1.0]], s=[[0.1]], mass=[1.0])
+    img = np.zeros(16, np.uint8)
+    ptrs = (C.c_void_p * 2)(img.ctypes.data, img.ctypes.data)
+    h = C.c_void_p()
+    dims = np.array([[16384, 8192, 1], [16384, 8192, 1]], dtype=np.int64)
+    assert L.lsm_batch_create(C.byref(cfg), 2, ptrs, dims.ctypes.data_as(C.c_void_p),
+                              C.byref(h)) == lsm.LSM_EINVAL
+
+
 def test_unbound_calls_report_state_errors():
     L = lsm.load_library()
     g = lsm.HostModel(np.zeros((4, 4), np.uint8), k=[[1.0]], s=[[0.1]], mass=[1.0])
