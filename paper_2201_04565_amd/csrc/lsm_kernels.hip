@@ -209,6 +209,14 @@ __device__ inline void comp_add(float &hi, float &lo, float delta) {
     hi = t;
 }
 __device__ inline void comp_add(double &hi, double &, double delta) { hi = hi + delta; }
+// the same with delta = a b, the product rounded once with the low part
+__device__ inline void comp_add_fma(float &hi, float &lo, float a, float b) {
+    const float y = fmaf(a, b, lo);
+    const float t = hi + y;
+    const float bp = t - hi;
+    lo = (hi - (t - bp)) + (y - bp);
+    hi = t;
+}
 
 __device__ inline double wave_sum(double x) {
 #pragma unroll
@@ -268,7 +276,9 @@ __device__ inline void site_acc(const typename State<DIM, PREC>::R *F, const typ
     }
 }
 
-// Interior step: close the half kick, open the next one, drift.
+// Interior step: close the half kick, open the next one, drift.  In FP32
+// the two half kicks are one kick by dt (h + h = dt exactly) and the drift
+// product is fused into the compensated sum.
 template <int DIM, int PREC>
 __device__ inline void mid_kick_drift(typename State<DIM, PREC>::R *uph, typename State<DIM, PREC>::R *upl,
                                       typename State<DIM, PREC>::R *w, const typename State<DIM, PREC>::R *acc,
@@ -276,9 +286,14 @@ __device__ inline void mid_kick_drift(typename State<DIM, PREC>::R *uph, typenam
     using R = typename State<DIM, PREC>::R;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        const R vfull = w[c] + h * acc[c];
-        w[c] = vfull + h * acc[c];
-        comp_add(uph[c], upl[c], dt * w[c]);
+        if constexpr (PREC == 1) {
+            w[c] = fmaf(dt, acc[c], w[c]);
+            comp_add_fma(uph[c], upl[c], dt, w[c]);
+        } else {
+            const R vfull = w[c] + h * acc[c];
+            w[c] = vfull + h * acc[c];
+            comp_add(uph[c], upl[c], dt * w[c]);
+        }
     }
 }
 
@@ -611,7 +626,7 @@ __global__ __launch_bounds__(256) void k_increment(StepParams P, double eps_new,
     R hi[DIM], lo[DIM];
     S::load_u(P.u_in, int(g), P.nsites, hi, lo);
     if (flag_grip(f)) {
-        const double ux = eps_new * c;
+        const double ux = eps_new * c + 0.0;  // +0, not -0, on the origin column under compression
         hi[0] = R(ux);
         lo[0] = R(ux - double(hi[0]));
 #pragma unroll
@@ -1174,12 +1189,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
     using R = typename S::R;
     using TTy = typename TT<PREC>::type;
     __shared__ TTy tt[kMaxTypes];
-    __shared__ double mass_s[LSM_MAX_PHASES];
-    __shared__ R imass_s[LSM_MAX_PHASES];
+    // 1 / m by the low six flag bits (phase, grip), zero for grips and void
+    // sites: every lane runs the update, which then leaves a grip's state
+    // exactly as it was (zero velocity, zero drift into a normalised
+    // compensated pair)
+    __shared__ R imass_f[64];
     for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
-    if (threadIdx.x < LSM_MAX_PHASES) {
-        mass_s[threadIdx.x] = P.mass[threadIdx.x];
-        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    if (threadIdx.x < 64) {
+        const int ph = threadIdx.x & 15, grip = (threadIdx.x >> 4) & 3;
+        imass_f[threadIdx.x] = (grip == 0 && ph < LSM_MAX_PHASES) ? R(1.0 / P.mass[ph]) : R(0);
     }
     __syncthreads();
 
@@ -1230,12 +1248,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
             int nm;
             row_force<PAR>(oa, aUL, aUR, abrk, rc.m, F, nm);
             Acur.m = nm;
-            if (Acur.f != kVoid && flag_grip(Acur.f) == 0) {
-                const int ph = flag_phase(Acur.f);
-                R acc[2];
-                site_acc<2, PREC>(F, Acur.v, mass_s[ph], imass_s[ph], gam, acc);
-                mid_kick_drift<2, PREC>(Acur.uh, Acur.ul, Acur.v, acc, h, dt);
-            }
+            R acc[2];
+            site_acc<2, PREC>(F, Acur.v, 0.0, imass_f[Acur.f & 63], gam, acc);
+            mid_kick_drift<2, PREC>(Acur.uh, Acur.ul, Acur.v, acc, h, dt);
             if (own && a >= j0 && a < j1 && Acur.f != kVoid && oa.nb) {
                 if constexpr (BATCH)  // batches keep a per-specimen count instead of a log
                     atomicAdd(&P.spec_broken[it.spec], uint32_t(oa.be + oa.bul + oa.bur));
@@ -1274,12 +1289,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
                         ul[c] = Aprev.ul[c];
                         v[c] = Aprev.v[c];
                     }
-                    if (flag_grip(Aprev.f) == 0) {
-                        const int ph = flag_phase(Aprev.f);
-                        R acc[2];
-                        site_acc<2, PREC>(F, v, mass_s[ph], imass_s[ph], gam, acc);
-                        mid_kick_drift<2, PREC>(uh, ul, v, acc, h, dt);
-                    }
+                    R acc[2];
+                    site_acc<2, PREC>(F, v, 0.0, imass_f[Aprev.f & 63], gam, acc);
+                    mid_kick_drift<2, PREC>(uh, ul, v, acc, h, dt);
                     const RowStore<PREC> st{g};
                     st.v(P.v_out, v);
                     st.u(P.u_out, uh, ul);
@@ -1379,7 +1391,7 @@ __global__ __launch_bounds__(kBlock) void k_increment_batch(StepParams P, double
         R hi[2], lo[2];
         S::load_u(P.u_in, g, P.nsites, hi, lo);
         if (flag_grip(f)) {
-            const double ux = eps_new * c;
+            const double ux = eps_new * c + 0.0;  // +0, not -0, on the origin column under compression
             hi[0] = R(ux);
             lo[0] = R(ux - double(hi[0]));
             hi[1] = R(0);
