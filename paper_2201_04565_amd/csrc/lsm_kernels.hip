@@ -760,7 +760,7 @@ struct SweepRow {
 
 template <int PREC>
 __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok, int jj,
-                                      bool want_v, SweepRow<typename State<2, PREC>::R> &r) {
+                                      SweepRow<typename State<2, PREC>::R> &r) {
     // Loads are unconditional from always-valid addresses, so no branch
     // joins on a pending load and no select waits for one.  Off the
     // specimen a lane reads its flag and break bits from the sentinel site
@@ -782,17 +782,15 @@ __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, 
     }
     r.f = P.flags[gf];
     r.m = reinterpret_cast<const uint8_t *>(P.mask)[gf];
-    r.v[0] = R(0);
-    r.v[1] = R(0);
-    if (want_v) {
-        const char *vb = static_cast<const char *>(P.v) + g * uint32_t(2 * sizeof(R));
-        if constexpr (PREC == 1) {
-            const float2 t = *reinterpret_cast<const float2 *>(vb);
-            r.v[0] = t.x; r.v[1] = t.y;
-        } else {
-            const double2 t = *reinterpret_cast<const double2 *>(vb);
-            r.v[0] = t.x; r.v[1] = t.y;
-        }
+    // the velocity too, also on the halo row below the chunk that is never
+    // advanced: one more load there costs less than the branch around it
+    const char *vb = static_cast<const char *>(P.v) + g * uint32_t(2 * sizeof(R));
+    if constexpr (PREC == 1) {
+        const float2 t = *reinterpret_cast<const float2 *>(vb);
+        r.v[0] = t.x; r.v[1] = t.y;
+    } else {
+        const double2 t = *reinterpret_cast<const double2 *>(vb);
+        r.v[0] = t.x; r.v[1] = t.y;
     }
 }
 
@@ -1047,7 +1045,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         auto row_step = [&](auto parc, int j, SweepRow<R> &rc, SweepRow<R> &ru,
                             SweepRow<R> &rn) __attribute__((always_inline)) {
             constexpr int PAR = decltype(parc)::value;
-            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, true, rn);
+            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn);
             RowSprings<R> o;
             row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a);
             const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
@@ -1131,7 +1129,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
         for (int t = 0; t <= PF; ++t) {
             const int jj = js + t;
-            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, jj >= j0, B[t]);
+            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, B[t]);
         }
         for (int j = js; j < j1; j += K) {
             unroll_rows<0, K>([&](auto tc) __attribute__((always_inline)) {
@@ -1238,7 +1236,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
                         const SweepRow<R> &Aprev) __attribute__((always_inline)) {
         constexpr int PAR = decltype(parc)::value;  // a & 1
         const int jn = a + PF + 1;
-        load_sweep_row<PREC>(P, it, i, col_ok, jn <= j1 + 1 ? jn : -1, jn >= j0 - 1, rn);
+        load_sweep_row<PREC>(P, it, i, col_ok, jn <= j1 + 1 ? jn : -1, rn);
         // ---- stage A: row a, step s
         RowSprings<R> oa;
         row_springs<PREC, PAR>(tt, P.types, rc, ru, oa, P.a);
@@ -1317,7 +1315,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d_x2(StepParams P, int step_lo
 #pragma unroll
     for (int t = 0; t <= PF; ++t) {
         const int jj = a0 + t;
-        load_sweep_row<PREC>(P, it, i, col_ok, jj >= ja && jj <= j1 + 1 ? jj : -1, jj >= j0 - 1, B[t]);
+        load_sweep_row<PREC>(P, it, i, col_ok, jj >= ja && jj <= j1 + 1 ? jj : -1, B[t]);
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) B[K - 1].uh[c] = B[K - 1].ul[c] = B[K - 1].v[c] = R(0);
