@@ -107,7 +107,10 @@ def batched_c4(args, torch, inputs, lsm):
                particles=b.n_particles, springs=b.n_springs, wall_s=wall,
                specimens_per_hour=len(imgs) / wall * 3600.0,
                mean_increments=float(n_inc.mean()),
-               step_graph_GBs=site_steps * 50 / (ms * 1e-3) / 1e9,
+               # algorithmic bytes per particle-step: 50 for the one-step kernel,
+               # 51 per two steps for the two-step kernel
+               step_graph_GBs=site_steps * (25.5 if launch["steps_per_launch"] == 2 else 50)
+               / (ms * 1e-3) / 1e9,
                launch=launch,
                autotune_us_per_step={f"{v} {r}x{p}": round(us, 1) for v, r, p, us in tune})
     del b
@@ -334,8 +337,8 @@ def main():
     bytes_per_launch = lat.step_bytes()
     hbm_gbs = bytes_per_launch / launch_s / 1e9
     counters = measured_counters(launch) if args.workload == "c2" else None
-    kname = {("c2", 2): "k_sweep2d_x2<1,1> (fp32 compensated, two interior steps per launch)",
-             ("c2", 1): "k_sweep2d<1,1> (fp32 compensated, one interior step per launch)",
+    kname = {("c2", 2): "k_sweep2d_x2<1,1,0> (fp32 compensated, two interior steps per launch)",
+             ("c2", 1): "k_sweep2d<1,1,1,0> (fp32 compensated, one interior step per launch)",
              ("c3", 1): "k_step<3,1,1> (fp32 compensated, one thread per particle)"}[(args.workload, spl)]
     roofline = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_gbs / HBM_PEAK_GBS,
