@@ -258,8 +258,9 @@ def main():
     ap.add_argument("--steps-per-inc", type=int, default=None)
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel", choices=("sweep", "sweep2"), default="sweep2",
-                    help="2D step kernel: one or two interior steps per launch")
+    ap.add_argument("--kernel", choices=("auto", "sweep", "sweep2", "gather"), default="auto",
+                    help="2D step kernel: auto (the two-step sweep), sweep (one step per launch), "
+                         "sweep2 (two steps), gather (one thread per site)")
     ap.add_argument("--launch", default="0,1", metavar="ROWS,PREFETCH",
                     help="sweep launch: rows per wavefront (0: the library's occupancy-model "
                          "default), prefetch depth")
@@ -297,7 +298,7 @@ def main():
     print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
           flush=True)
     if args.workload == "c3":
-        pass  # 3D: one thread per particle (the sweep is 2D only)
+        pass  # 3D: the gather kernel, one thread per particle
     elif args.autotune:
         lat.autotune(100)
     else:
@@ -337,9 +338,11 @@ def main():
     bytes_per_launch = lat.step_bytes()
     hbm_gbs = bytes_per_launch / launch_s / 1e9
     counters = measured_counters(launch) if args.workload == "c2" else None
-    kname = {("c2", 2): "k_sweep2d_x2<1,1,0> (fp32 compensated, two interior steps per launch)",
-             ("c2", 1): "k_sweep2d<1,1,1,0> (fp32 compensated, one interior step per launch)",
-             ("c3", 1): "k_step<3,1,1> (fp32 compensated, one thread per particle)"}[(args.workload, spl)]
+    if args.workload == "c3":
+        kname = "k_step<3,1,1> (fp32 compensated, one thread per particle)"
+    else:
+        kname = {2: "k_sweep2d_x2<1,1,0> (fp32 compensated, two interior steps per launch)",
+                 1: "k_sweep2d<1,1,1,0> (fp32 compensated, one interior step per launch)"}[spl]
     roofline = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_gbs / HBM_PEAK_GBS,
                 "traffic": counters.get("bytes_per_launch") if counters else None,
