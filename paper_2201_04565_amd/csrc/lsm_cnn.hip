@@ -274,6 +274,117 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
         }
 }
 
+// Forward convolution + ReLU + 2x2 average pooling with the input patch
+// staged in LDS.  A workgroup computes an 8 x 16 pixel tile of one image and
+// 64 output channels: the (8 + 2) x (16 + 2) x CIN input patch (zeros off
+// the image) is loaded into LDS once and serves all nine taps, so each
+// input value is fetched once per tile instead of once per tap.  The four
+// wavefronts split the tile into 2 x 2 blocks of 64 pixels (4 tile rows x
+// 16 columns) x 32 channels: four 16-row MFMA tiles (each four 2x2 quads,
+// the row order of the pooling epilogue above) by two 16-column ones.  The
+// reduction runs in the same K steps and order as k_conv_mfma, so both
+// kernels produce the same bits; weights come from global memory (L1/L2
+// resident), one step ahead.
+constexpr int kPatchH = 10, kPatchW = 18;
+
+template <int CIN>
+__global__ __launch_bounds__(kBlk) void k_conv_pool_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                                                       uint8_t *mask_out, int B, int H, int W, int Cout) {
+    constexpr int PS = CIN + 8;  // u16 per staged pixel (16 bytes of padding against bank conflicts)
+    constexpr int KPT = CIN / 32;
+    constexpr int NK = 9 * KPT;
+    __shared__ __attribute__((aligned(16))) u16 patch[kPatchH * kPatchW * PS];
+    const int tiles_x = W / 16, tiles_y = H / 8;
+    const int tile = blockIdx.x;
+    const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y;
+    const int n = tile / (tiles_x * tiles_y);
+    const int y0 = ty * 8, x0 = tx * 16;
+    const int c0 = blockIdx.y * 64;
+    // stage the input patch (16-byte chunks)
+    for (int idx = threadIdx.x; idx < kPatchH * kPatchW * (CIN / 8); idx += kBlk) {
+        const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
+        const int gy = y0 + pix / kPatchW - 1, gx = x0 + pix % kPatchW - 1;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *reinterpret_cast<const uint4 *>(in + ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8);
+        *reinterpret_cast<uint4 *>(patch + pix * PS + 8 * c8) = v;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int wm = wv & 1, wn = wv >> 1;
+    const int r16 = lane & 15, kq = lane >> 4;
+    // patch pixel (before the tap shift) of this lane's row in each M tile:
+    // row 16 r + r16 is quad 4 r + r16 / 4, position r16 mod 4
+    int abase[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ql = 4 * r + (r16 >> 2), sub = r16 & 3;
+        const int y = 4 * wm + 2 * (ql >> 3) + (sub >> 1), x = 2 * (ql & 7) + (sub & 1);
+        abase[r] = ((y + 1) * kPatchW + (x + 1)) * PS + 8 * kq;
+    }
+    const u16 *wrow[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) wrow[c] = wt + int64_t(c0 + 32 * wn + 16 * c + r16) * (9 * CIN) + 8 * kq;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    Frag bcur[2], bnext[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) bcur[c].u = *reinterpret_cast<const uint4 *>(wrow[c]);
+    __syncthreads();
+#pragma unroll 2
+    for (int kk = 0; kk < NK; ++kk) {
+        if (kk + 1 < NK) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) bnext[c].u = *reinterpret_cast<const uint4 *>(wrow[c] + (kk + 1) * 32);
+        }
+        const int tap = kk / KPT, ci0 = (kk - tap * KPT) * 32;
+        const int shift = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * PS + ci0;
+        Frag a[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r].u = *reinterpret_cast<const uint4 *>(patch + abase[r] + shift);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bcur[c].v, acc[r][c], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) bcur[c] = bnext[c];
+    }
+    // pooling epilogue: this lane holds quad 4 r + kq of M tile r, channel
+    // column r16 of N tile c
+    const int Wq = W / 2, Hq = H / 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int ql = 4 * r + kq;
+        const int qy = y0 / 2 + 2 * wm + (ql >> 3), qx = x0 / 2 + (ql & 7);
+        const int64_t q = (int64_t(n) * Hq + qy) * Wq + qx;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int co = c0 + 32 * wn + 16 * c + r16;
+            const float bv = bias[co];
+            float s4 = 0.0f;
+            unsigned m = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float a = bf2f(f2bf(fmaxf(acc[r][c][i] + bv, 0.0f)));
+                s4 += a;
+                m |= (a > 0.0f ? 1u : 0u) << i;
+            }
+            out[q * Cout + co] = f2bf(0.25f * s4);
+            mask_out[q * Cout + co] = uint8_t(m);
+        }
+    }
+}
+
+// Staged-patch kernel for a pooled layer: input channels 32, 64 or 128,
+// 8 x 16 tiles and 64-channel blocks that divide the layer exactly.
+inline bool conv_pool_lds_fits(int H, int W, int Cin, int Cout) {
+    return (Cin == 32 || Cin == 64 || Cin == 128) && H % 8 == 0 && W % 16 == 0 && Cout % 64 == 0;
+}
+
 constexpr int kConvWM = 4, kConvWN = 4;  // 64 pixels x 64 channels per wavefront
 
 // four wavefronts of WM * 16 pixels per workgroup along x, WN * 16 channels along y
@@ -891,7 +1002,20 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
     for (int l = 1; l < kLayers; ++l) {
         const int H = c->Hs[l];
         const dim3 grid = conv_grid(int64_t(B) * H * H, c->C[l + 1]);
-        if (l < kLayers - 1)
+        if (l < kLayers - 1 && conv_pool_lds_fits(H, H, c->C[l], c->C[l + 1])) {
+            const dim3 g(unsigned(B * (H / 8) * (H / 16)), unsigned(c->C[l + 1] / 64));
+            const u16 *in = c->pool[l - 1];
+            const float *bias = c->p + c->b_off[l];
+            if (c->C[l] == 32)
+                hipLaunchKernelGGL(k_conv_pool_lds<32>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
+                                   c->mask[l], B, H, H, c->C[l + 1]);
+            else if (c->C[l] == 64)
+                hipLaunchKernelGGL(k_conv_pool_lds<64>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
+                                   c->mask[l], B, H, H, c->C[l + 1]);
+            else
+                hipLaunchKernelGGL(k_conv_pool_lds<128>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
+                                   c->mask[l], B, H, H, c->C[l + 1]);
+        } else if (l < kLayers - 1)
             hipLaunchKernelGGL((k_conv_mfma<kEpiPool, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream,
                                c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->pool[l], nullptr, c->mask[l], B, H, H,
                                c->C[l], c->C[l + 1]);
