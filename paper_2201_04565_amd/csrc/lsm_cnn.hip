@@ -274,36 +274,36 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
         }
 }
 
-// Forward convolution + ReLU + 2x2 average pooling with the input patch
-// staged in LDS.  A workgroup computes an 8 x 16 pixel tile of one image and
-// 64 output channels: the (8 + 2) x (16 + 2) x CIN input patch (zeros off
-// the image) is loaded into LDS once and serves all nine taps, so each
-// input value is fetched once per tile instead of once per tap.  The four
-// wavefronts split the tile into 2 x 2 blocks of 64 pixels (4 tile rows x
-// 16 columns) x 32 channels: four 16-row MFMA tiles (each four 2x2 quads,
-// the row order of the pooling epilogue above) by two 16-column ones.  The
-// reduction runs in the same K steps and order as k_conv_mfma, so both
-// kernels produce the same bits; weights come from global memory (L1/L2
-// resident), one step ahead.
-constexpr int kPatchH = 10, kPatchW = 18;
-
-template <int CIN>
-__global__ __launch_bounds__(kBlk) void k_conv_pool_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
-                                                       uint8_t *mask_out, int B, int H, int W, int Cout) {
+// Forward convolution (ReLU, then 2x2 average pooling or a plain store)
+// with the input patch staged in LDS.  A workgroup computes an 8 x TW pixel
+// tile of one image (TW = 16 or 8) and 64 output channels: the (8 + 2) x
+// (TW + 2) x CIN input patch (zeros off the image) is loaded into LDS once
+// and serves all nine taps, so each input value is fetched once per tile
+// instead of once per tap.  With TW = 16 the four wavefronts split the tile
+// into 2 x 2 blocks of 64 pixels (4 tile rows) x 32 channels; with TW = 8
+// each takes all 64 pixels and 16 channels.  A wavefront's pixels form four
+// 16-row MFMA tiles of four 2x2 quads each (the row order of the pooling
+// epilogue above).  The reduction runs in the same K steps and order as
+// k_conv_mfma, so both kernels produce the same bits; weights come from
+// global memory (L1/L2 resident), one step ahead.
+template <int CIN, int TW, int EPI>
+__global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                                                  uint8_t *mask_out, int B, int H, int W, int Cout) {
+    constexpr int PH = 10, PW = TW + 2;
     constexpr int PS = CIN + 8;  // u16 per staged pixel (16 bytes of padding against bank conflicts)
     constexpr int KPT = CIN / 32;
     constexpr int NK = 9 * KPT;
-    __shared__ __attribute__((aligned(16))) u16 patch[kPatchH * kPatchW * PS];
-    const int tiles_x = W / 16, tiles_y = H / 8;
+    constexpr int NT = TW == 16 ? 2 : 1;  // 16-column MFMA tiles per wavefront
+    constexpr int QW = TW / 2;            // quads per tile row pair
+    __shared__ __attribute__((aligned(16))) u16 patch[PH * PW * PS];
+    const int tiles_x = W / TW, tiles_y = H / 8;
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y;
     const int n = tile / (tiles_x * tiles_y);
-    const int y0 = ty * 8, x0 = tx * 16;
-    const int c0 = blockIdx.y * 64;
-    // stage the input patch (16-byte chunks)
-    for (int idx = threadIdx.x; idx < kPatchH * kPatchW * (CIN / 8); idx += kBlk) {
+    const int y0 = ty * 8, x0 = tx * TW;
+    for (int idx = threadIdx.x; idx < PH * PW * (CIN / 8); idx += kBlk) {
         const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
-        const int gy = y0 + pix / kPatchW - 1, gx = x0 + pix % kPatchW - 1;
+        const int gy = y0 + pix / PW - 1, gx = x0 + pix % PW - 1;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (gy >= 0 && gy < H && gx >= 0 && gx < W)
             v = *reinterpret_cast<const uint4 *>(in + ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8);
@@ -311,7 +311,8 @@ __global__ __launch_bounds__(kBlk) void k_conv_pool_lds(const u16 *in, const u16
     }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int wm = wv & 1, wn = wv >> 1;
+    const int wm = TW == 16 ? (wv & 1) : 0;
+    const int cw = blockIdx.y * 64 + (TW == 16 ? 32 * (wv >> 1) : 16 * wv);  // first channel of the wavefront
     const int r16 = lane & 15, kq = lane >> 4;
     // patch pixel (before the tap shift) of this lane's row in each M tile:
     // row 16 r + r16 is quad 4 r + r16 / 4, position r16 mod 4
@@ -319,70 +320,94 @@ __global__ __launch_bounds__(kBlk) void k_conv_pool_lds(const u16 *in, const u16
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ql = 4 * r + (r16 >> 2), sub = r16 & 3;
-        const int y = 4 * wm + 2 * (ql >> 3) + (sub >> 1), x = 2 * (ql & 7) + (sub & 1);
-        abase[r] = ((y + 1) * kPatchW + (x + 1)) * PS + 8 * kq;
+        const int y = 4 * wm + 2 * (ql / QW) + (sub >> 1), x = 2 * (ql % QW) + (sub & 1);
+        abase[r] = ((y + 1) * PW + (x + 1)) * PS + 8 * kq;
     }
-    const u16 *wrow[2];
+    const u16 *wrow[NT];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) wrow[c] = wt + int64_t(c0 + 32 * wn + 16 * c + r16) * (9 * CIN) + 8 * kq;
-    f32x4 acc[4][2];
+    for (int c = 0; c < NT; ++c) wrow[c] = wt + int64_t(cw + 16 * c + r16) * (9 * CIN) + 8 * kq;
+    f32x4 acc[4][NT];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    Frag bcur[2], bnext[2];
+        for (int c = 0; c < NT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    Frag bcur[NT], bnext[NT];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) bcur[c].u = *reinterpret_cast<const uint4 *>(wrow[c]);
+    for (int c = 0; c < NT; ++c) bcur[c].u = *reinterpret_cast<const uint4 *>(wrow[c]);
     __syncthreads();
 #pragma unroll 2
     for (int kk = 0; kk < NK; ++kk) {
         if (kk + 1 < NK) {
 #pragma unroll
-            for (int c = 0; c < 2; ++c) bnext[c].u = *reinterpret_cast<const uint4 *>(wrow[c] + (kk + 1) * 32);
+            for (int c = 0; c < NT; ++c) bnext[c].u = *reinterpret_cast<const uint4 *>(wrow[c] + (kk + 1) * 32);
         }
         const int tap = kk / KPT, ci0 = (kk - tap * KPT) * 32;
-        const int shift = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * PS + ci0;
+        const int shift = ((tap / 3 - 1) * PW + (tap % 3 - 1)) * PS + ci0;
         Frag a[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r].u = *reinterpret_cast<const uint4 *>(patch + abase[r] + shift);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
+            for (int c = 0; c < NT; ++c)
                 acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bcur[c].v, acc[r][c], 0, 0, 0);
 #pragma unroll
-        for (int c = 0; c < 2; ++c) bcur[c] = bnext[c];
+        for (int c = 0; c < NT; ++c) bcur[c] = bnext[c];
     }
-    // pooling epilogue: this lane holds quad 4 r + kq of M tile r, channel
-    // column r16 of N tile c
-    const int Wq = W / 2, Hq = H / 2;
+    // epilogue: this lane holds quad 4 r + kq of M tile r, channel column
+    // r16 of N tile c
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int ql = 4 * r + kq;
-        const int qy = y0 / 2 + 2 * wm + (ql >> 3), qx = x0 / 2 + (ql & 7);
-        const int64_t q = (int64_t(n) * Hq + qy) * Wq + qx;
+        const int qy = y0 / 2 + 2 * wm + ql / QW, qx = x0 / 2 + ql % QW;  // pooled coordinates
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int co = c0 + 32 * wn + 16 * c + r16;
+        for (int c = 0; c < NT; ++c) {
+            const int co = cw + 16 * c + r16;
             const float bv = bias[co];
-            float s4 = 0.0f;
-            unsigned m = 0;
+            if constexpr (EPI == kEpiPool) {
+                const int64_t q = (int64_t(n) * (H / 2) + qy) * (W / 2) + qx;
+                float s4 = 0.0f;
+                unsigned m = 0;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float a = bf2f(f2bf(fmaxf(acc[r][c][i] + bv, 0.0f)));
-                s4 += a;
-                m |= (a > 0.0f ? 1u : 0u) << i;
+                for (int i = 0; i < 4; ++i) {
+                    const float a = bf2f(f2bf(fmaxf(acc[r][c][i] + bv, 0.0f)));
+                    s4 += a;
+                    m |= (a > 0.0f ? 1u : 0u) << i;
+                }
+                out[q * Cout + co] = f2bf(0.25f * s4);
+                mask_out[q * Cout + co] = uint8_t(m);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int y = 2 * qy + (i >> 1), x = 2 * qx + (i & 1);
+                    out[((int64_t(n) * H + y) * W + x) * Cout + co] = f2bf(fmaxf(acc[r][c][i] + bv, 0.0f));
+                }
             }
-            out[q * Cout + co] = f2bf(0.25f * s4);
-            mask_out[q * Cout + co] = uint8_t(m);
         }
     }
 }
 
-// Staged-patch kernel for a pooled layer: input channels 32, 64 or 128,
-// 8 x 16 tiles and 64-channel blocks that divide the layer exactly.
-inline bool conv_pool_lds_fits(int H, int W, int Cin, int Cout) {
-    return (Cin == 32 || Cin == 64 || Cin == 128) && H % 8 == 0 && W % 16 == 0 && Cout % 64 == 0;
+// The staged-patch kernel takes layers with 32, 64 or 128 input channels
+// whose 8 x TW tiles and 64-channel blocks divide the layer exactly.
+inline int conv_lds_tw(int H, int W, int Cin, int Cout) {
+    if (!(Cin == 32 || Cin == 64 || Cin == 128) || H % 8 != 0 || Cout % 64 != 0) return 0;
+    return W % 16 == 0 ? 16 : (W % 8 == 0 ? 8 : 0);
+}
+
+template <int EPI, int TW>
+void launch_conv_lds_tw(hipStream_t st, const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask,
+                        int B, int H, int Cin, int Cout) {
+    const dim3 g(unsigned(B * (H / 8) * (H / TW)), unsigned(Cout / 64));
+    if (Cin == 32) hipLaunchKernelGGL((k_conv_lds<32, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+    else if (Cin == 64) hipLaunchKernelGGL((k_conv_lds<64, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+    else hipLaunchKernelGGL((k_conv_lds<128, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+}
+
+template <int EPI>
+void launch_conv_lds(hipStream_t st, int tw, const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                     uint8_t *mask, int B, int H, int Cin, int Cout) {
+    if (tw == 16) launch_conv_lds_tw<EPI, 16>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
+    else launch_conv_lds_tw<EPI, 8>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
 }
 
 constexpr int kConvWM = 4, kConvWN = 4;  // 64 pixels x 64 channels per wavefront
@@ -638,17 +663,54 @@ __global__ __launch_bounds__(kBlk) void k_gap_bwd_relu(const float *dg, const u1
 }
 
 // ---------------------------------------------------------- dense layers
-// y[n, o] = act(b[o] + sum_i w[o, i] x[n, i])
+// y[n, o] = act(b[o] + sum_i w[o, i] x[n, i]), summed in the order i = 0,
+// 1, ...  A workgroup computes 32 samples x 64 outputs (eight outputs per
+// thread), staging 64-wide slices of x and w in LDS with coalesced row
+// loads (rows padded by one float against bank conflicts).
+constexpr int kFcN = 32, kFcO = 64, kFcI = 64;
+
 __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w, const float *b, float *y, int B,
                                                 int In, int Out, int relu) {
-    const int64_t t = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (t >= int64_t(B) * Out) return;
-    const int o = int(t % Out);
-    const int64_t n = t / Out;
-    float s = b[o];
-    for (int i = 0; i < In; ++i) s = fmaf(w[int64_t(o) * In + i], x[n * In + i], s);
-    y[t] = relu ? fmaxf(s, 0.0f) : s;
+    __shared__ float xs[kFcN][kFcI + 1];
+    __shared__ float ws[kFcO][kFcI + 1];
+    const int n0 = blockIdx.y * kFcN, o0 = blockIdx.x * kFcO;
+    const int nl = threadIdx.x >> 3, og = threadIdx.x & 7;  // sample, group of outputs og + 8 j
+    float s[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int o = o0 + og + 8 * j;
+        s[j] = o < Out ? b[o] : 0.0f;
+    }
+    for (int i0 = 0; i0 < In; i0 += kFcI) {
+        for (int e = threadIdx.x; e < kFcN * kFcI; e += kBlk) {
+            const int r = e / kFcI, c = e % kFcI;
+            const int n = n0 + r, i = i0 + c;
+            xs[r][c] = (n < B && i < In) ? x[int64_t(n) * In + i] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < kFcO * kFcI; e += kBlk) {
+            const int r = e / kFcI, c = e % kFcI;
+            const int o = o0 + r, i = i0 + c;
+            ws[r][c] = (o < Out && i < In) ? w[int64_t(o) * In + i] : 0.0f;
+        }
+        __syncthreads();
+        const int ni = min(kFcI, In - i0);
+        for (int c = 0; c < ni; ++c) {
+            const float xv = xs[nl][c];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s[j] = fmaf(ws[og + 8 * j][c], xv, s[j]);
+        }
+        __syncthreads();
+    }
+    const int n = n0 + nl;
+    if (n >= B) return;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int o = o0 + og + 8 * j;
+        if (o < Out) y[int64_t(n) * Out + o] = relu ? fmaxf(s[j], 0.0f) : s[j];
+    }
 }
+
+inline dim3 fc_grid(int B, int Out) { return dim3(unsigned((Out + kFcO - 1) / kFcO), unsigned((B + kFcN - 1) / kFcN)); }
 
 // dx[n, i] = sum_o w[o, i] dy[n, o], times the ReLU mask of x when given
 __global__ __launch_bounds__(kBlk) void k_fc_bwd_data(const float *dy, const float *w, const float *xact,
@@ -1002,20 +1064,15 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
     for (int l = 1; l < kLayers; ++l) {
         const int H = c->Hs[l];
         const dim3 grid = conv_grid(int64_t(B) * H * H, c->C[l + 1]);
-        if (l < kLayers - 1 && conv_pool_lds_fits(H, H, c->C[l], c->C[l + 1])) {
-            const dim3 g(unsigned(B * (H / 8) * (H / 16)), unsigned(c->C[l + 1] / 64));
-            const u16 *in = c->pool[l - 1];
-            const float *bias = c->p + c->b_off[l];
-            if (c->C[l] == 32)
-                hipLaunchKernelGGL(k_conv_pool_lds<32>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
-                                   c->mask[l], B, H, H, c->C[l + 1]);
-            else if (c->C[l] == 64)
-                hipLaunchKernelGGL(k_conv_pool_lds<64>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
-                                   c->mask[l], B, H, H, c->C[l + 1]);
-            else
-                hipLaunchKernelGGL(k_conv_pool_lds<128>, g, dim3(kBlk), 0, c->stream, in, c->wf[l], bias, c->pool[l],
-                                   c->mask[l], B, H, H, c->C[l + 1]);
-        } else if (l < kLayers - 1)
+        const int tw = conv_lds_tw(H, H, c->C[l], c->C[l + 1]);
+        const bool pool = l < kLayers - 1;
+        if (tw && pool)
+            launch_conv_lds<kEpiPool>(c->stream, tw, c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->pool[l],
+                                      c->mask[l], B, H, c->C[l], c->C[l + 1]);
+        else if (tw)
+            launch_conv_lds<kEpiStore>(c->stream, tw, c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->act,
+                                       nullptr, B, H, c->C[l], c->C[l + 1]);
+        else if (pool)
             hipLaunchKernelGGL((k_conv_mfma<kEpiPool, kConvWM, kConvWN>), grid, dim3(kBlk), 0, c->stream,
                                c->pool[l - 1], c->wf[l], c->p + c->b_off[l], c->pool[l], nullptr, c->mask[l], B, H, H,
                                c->C[l], c->C[l + 1]);
@@ -1029,9 +1086,9 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
     hipLaunchKernelGGL(k_gap_fwd, dim3(nblk(int64_t(B) * CL)), dim3(kBlk), 0, c->stream, c->act, c->gap,
                        B, HL * HL, CL);
     const int hid = c->cfg.hidden, out = c->cfg.outputs;
-    hipLaunchKernelGGL(k_fc_fwd, dim3(nblk(int64_t(B) * hid)), dim3(kBlk), 0, c->stream, c->gap,
+    hipLaunchKernelGGL(k_fc_fwd, fc_grid(B, hid), dim3(kBlk), 0, c->stream, c->gap,
                        c->p + c->w_off[kLayers], c->p + c->b_off[kLayers], c->h1, B, CL, hid, 1);
-    hipLaunchKernelGGL(k_fc_fwd, dim3(nblk(int64_t(B) * out)), dim3(kBlk), 0, c->stream, c->h1,
+    hipLaunchKernelGGL(k_fc_fwd, fc_grid(B, out), dim3(kBlk), 0, c->stream, c->h1,
                        c->p + c->w_off[kLayers + 1], c->p + c->b_off[kLayers + 1], c->y, B, hid, out, 0);
     CHIP(c, hipGetLastError());
     if (y) CHIP(c, hipMemcpyAsync(y, c->y, size_t(B) * out * 4, hipMemcpyDeviceToDevice, c->stream));
