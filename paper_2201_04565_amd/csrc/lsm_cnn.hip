@@ -81,6 +81,12 @@ __device__ inline float conv1_at(const float *w, const float *b, int c, const fl
 
 __global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const float *w, const float *b,
                                                         u16 *pool, int B, int H, int W, int C) {
+    // weights and biases once per workgroup in LDS (C <= 256): every lane
+    // reads the same word, a broadcast
+    __shared__ float ws[256 * 9], bs[256];
+    for (int t = threadIdx.x; t < C * 9; t += kBlk) ws[t] = w[t];
+    for (int t = threadIdx.x; t < C; t += kBlk) bs[t] = b[t];
+    __syncthreads();
     const int Ho = H / 2, Wo = W / 2;
     const int64_t q = int64_t(blockIdx.x) * kBlk + threadIdx.x;
     if (q >= int64_t(B) * Ho * Wo) return;
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const
         for (int e = 0; e < 8; ++e) {
             float s4 = 0.0f;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) s4 += bf2f(f2bf(fmaxf(conv1_at(w, b, c0 + e, v, d >> 1, d & 1), 0.0f)));
+            for (int d = 0; d < 4; ++d) s4 += bf2f(f2bf(fmaxf(conv1_at(ws, bs, c0 + e, v, d >> 1, d & 1), 0.0f)));
             h[e] = f2bf(0.25f * s4);
         }
         *reinterpret_cast<uint4 *>(pool + q * C + c0) = *reinterpret_cast<const uint4 *>(h);
@@ -664,21 +670,22 @@ __global__ __launch_bounds__(kBlk) void k_gap_bwd_relu(const float *dg, const u1
 
 // ---------------------------------------------------------- dense layers
 // y[n, o] = act(b[o] + sum_i w[o, i] x[n, i]), summed in the order i = 0,
-// 1, ...  A workgroup computes 32 samples x 64 outputs (eight outputs per
+// 1, ...  A workgroup computes 8 samples x 64 outputs (two outputs per
 // thread), staging 64-wide slices of x and w in LDS with coalesced row
-// loads (rows padded by one float against bank conflicts).
-constexpr int kFcN = 32, kFcO = 64, kFcI = 64;
+// loads (rows padded by one float against bank conflicts); the small tile
+// gives a few hundred workgroups for a batch of 512.
+constexpr int kFcN = 8, kFcO = 64, kFcI = 64;
 
 __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w, const float *b, float *y, int B,
                                                 int In, int Out, int relu) {
     __shared__ float xs[kFcN][kFcI + 1];
     __shared__ float ws[kFcO][kFcI + 1];
     const int n0 = blockIdx.y * kFcN, o0 = blockIdx.x * kFcO;
-    const int nl = threadIdx.x >> 3, og = threadIdx.x & 7;  // sample, group of outputs og + 8 j
-    float s[8];
+    const int nl = threadIdx.x >> 5, og = threadIdx.x & 31;  // sample, outputs og and og + 32
+    float s[2];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int o = o0 + og + 8 * j;
+    for (int j = 0; j < 2; ++j) {
+        const int o = o0 + og + 32 * j;
         s[j] = o < Out ? b[o] : 0.0f;
     }
     for (int i0 = 0; i0 < In; i0 += kFcI) {
@@ -697,15 +704,15 @@ __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w,
         for (int c = 0; c < ni; ++c) {
             const float xv = xs[nl][c];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s[j] = fmaf(ws[og + 8 * j][c], xv, s[j]);
+            for (int j = 0; j < 2; ++j) s[j] = fmaf(ws[og + 32 * j][c], xv, s[j]);
         }
         __syncthreads();
     }
     const int n = n0 + nl;
     if (n >= B) return;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const int o = o0 + og + 8 * j;
+    for (int j = 0; j < 2; ++j) {
+        const int o = o0 + og + 32 * j;
         if (o < Out) y[int64_t(n) * Out + o] = relu ? fmaxf(s[j], 0.0f) : s[j];
     }
 }
