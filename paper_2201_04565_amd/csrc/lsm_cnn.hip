@@ -282,24 +282,24 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 
 // Forward convolution (ReLU, then 2x2 average pooling or a plain store)
 // with the input patch staged in LDS.  A workgroup computes an 8 x TW pixel
-// tile of one image (TW = 16 or 8) and 64 output channels: the (8 + 2) x
-// (TW + 2) x CIN input patch (zeros off the image) is loaded into LDS once
-// and serves all nine taps, so each input value is fetched once per tile
-// instead of once per tap.  With TW = 16 the four wavefronts split the tile
-// into 2 x 2 blocks of 64 pixels (4 tile rows) x 32 channels; with TW = 8
-// each takes all 64 pixels and 16 channels.  A wavefront's pixels form four
+// tile of one image (TW = 16 or 8) and BN output channels (64 or 128): the
+// (8 + 2) x (TW + 2) x CIN input patch (zeros off the image) is loaded into
+// LDS once and serves all nine taps, so each input value is fetched once
+// per tile instead of once per tap.  With TW = 16 the four wavefronts split
+// the tile into 2 x 2 blocks of 64 pixels (4 tile rows) x BN / 2 channels;
+// with TW = 8 each takes all 64 pixels and BN / 4 channels.  A wavefront's pixels form four
 // 16-row MFMA tiles of four 2x2 quads each (the row order of the pooling
 // epilogue above).  The reduction runs in the same K steps and order as
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
-template <int CIN, int TW, int EPI>
+template <int CIN, int TW, int BN, int EPI>
 __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
                                                   uint8_t *mask_out, int B, int H, int W, int Cout) {
     constexpr int PH = 10, PW = TW + 2;
     constexpr int PS = CIN + 8;  // u16 per staged pixel (16 bytes of padding against bank conflicts)
     constexpr int KPT = CIN / 32;
     constexpr int NK = 9 * KPT;
-    constexpr int NT = TW == 16 ? 2 : 1;  // 16-column MFMA tiles per wavefront
+    constexpr int NT = TW == 16 ? BN / 32 : BN / 64;  // 16-column MFMA tiles per wavefront
     constexpr int QW = TW / 2;            // quads per tile row pair
     __shared__ __attribute__((aligned(16))) u16 patch[PH * PW * PS];
     const int tiles_x = W / TW, tiles_y = H / 8;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int wm = TW == 16 ? (wv & 1) : 0;
-    const int cw = blockIdx.y * 64 + (TW == 16 ? 32 * (wv >> 1) : 16 * wv);  // first channel of the wavefront
+    const int cw = blockIdx.y * BN + (TW == 16 ? (BN / 2) * (wv >> 1) : (BN / 4) * wv);  // wavefront's first channel
     const int r16 = lane & 15, kq = lane >> 4;
     // patch pixel (before the tap shift) of this lane's row in each M tile:
     // row 16 r + r16 is quad 4 r + r16 / 4, position r16 mod 4
@@ -394,26 +394,34 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
 }
 
 // The staged-patch kernel takes layers with 32, 64 or 128 input channels
-// whose 8 x TW tiles and 64-channel blocks divide the layer exactly.
+// whose 8 x TW tiles and 64-channel blocks divide the layer exactly; layers
+// with a multiple of 128 output channels take 128-channel blocks (one
+// staged patch feeds twice the MFMA work).
 inline int conv_lds_tw(int H, int W, int Cin, int Cout) {
     if (!(Cin == 32 || Cin == 64 || Cin == 128) || H % 8 != 0 || Cout % 64 != 0) return 0;
     return W % 16 == 0 ? 16 : (W % 8 == 0 ? 8 : 0);
 }
 
-template <int EPI, int TW>
-void launch_conv_lds_tw(hipStream_t st, const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask,
+template <int EPI, int TW, int BN>
+void launch_conv_lds_bn(hipStream_t st, const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask,
                         int B, int H, int Cin, int Cout) {
-    const dim3 g(unsigned(B * (H / 8) * (H / TW)), unsigned(Cout / 64));
-    if (Cin == 32) hipLaunchKernelGGL((k_conv_lds<32, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
-    else if (Cin == 64) hipLaunchKernelGGL((k_conv_lds<64, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
-    else hipLaunchKernelGGL((k_conv_lds<128, TW, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+    const dim3 g(unsigned(B * (H / 8) * (H / TW)), unsigned(Cout / BN));
+    if (Cin == 32)
+        hipLaunchKernelGGL((k_conv_lds<32, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+    else if (Cin == 64)
+        hipLaunchKernelGGL((k_conv_lds<64, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+    else
+        hipLaunchKernelGGL((k_conv_lds<128, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
 }
 
 template <int EPI>
 void launch_conv_lds(hipStream_t st, int tw, const u16 *in, const u16 *wt, const float *bias, u16 *out,
                      uint8_t *mask, int B, int H, int Cin, int Cout) {
-    if (tw == 16) launch_conv_lds_tw<EPI, 16>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
-    else launch_conv_lds_tw<EPI, 8>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
+    const bool wide = Cout % 128 == 0;
+    if (tw == 16 && wide) launch_conv_lds_bn<EPI, 16, 128>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
+    else if (tw == 16) launch_conv_lds_bn<EPI, 16, 64>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
+    else if (wide) launch_conv_lds_bn<EPI, 8, 128>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
+    else launch_conv_lds_bn<EPI, 8, 64>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
 }
 
 constexpr int kConvWM = 4, kConvWN = 4;  // 64 pixels x 64 channels per wavefront
@@ -701,10 +709,21 @@ __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w,
         }
         __syncthreads();
         const int ni = min(kFcI, In - i0);
-        for (int c = 0; c < ni; ++c) {
-            const float xv = xs[nl][c];
+        if (ni == kFcI) {
+            // full slice: unrolled, so the LDS reads are issued ahead of the
+            // dependent multiply-add chains
+#pragma unroll 16
+            for (int c = 0; c < kFcI; ++c) {
+                const float xv = xs[nl][c];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) s[j] = fmaf(ws[og + 32 * j][c], xv, s[j]);
+                for (int j = 0; j < 2; ++j) s[j] = fmaf(ws[og + 32 * j][c], xv, s[j]);
+            }
+        } else {
+            for (int c = 0; c < ni; ++c) {
+                const float xv = xs[nl][c];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) s[j] = fmaf(ws[og + 32 * j][c], xv, s[j]);
+            }
         }
         __syncthreads();
     }
