@@ -296,12 +296,16 @@ template <int CIN, int TW, int BN, int EPI>
 __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
                                                   uint8_t *mask_out, int B, int H, int W, int Cout) {
     constexpr int PH = 10, PW = TW + 2;
-    constexpr int PS = CIN + 8;  // u16 per staged pixel (16 bytes of padding against bank conflicts)
+    // u16 per staged pixel and per staged row: pixel strides of 4 (mod 32)
+    // LDS banks and row strides of 16 put the eight pixels that one
+    // 16-byte read phase touches (two quads) on distinct banks
+    constexpr int PS = CIN + 8;
+    constexpr int RS = PW * PS + 16;
     constexpr int KPT = CIN / 32;
     constexpr int NK = 9 * KPT;
     constexpr int NT = TW == 16 ? BN / 32 : BN / 64;  // 16-column MFMA tiles per wavefront
     constexpr int QW = TW / 2;            // quads per tile row pair
-    __shared__ __attribute__((aligned(16))) u16 patch[PH * PW * PS];
+    __shared__ __attribute__((aligned(16))) u16 patch[PH * RS];
     const int tiles_x = W / TW, tiles_y = H / 8;
     const int tile = blockIdx.x;
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y;
@@ -313,7 +317,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
         uint4 v = make_uint4(0, 0, 0, 0);
         if (gy >= 0 && gy < H && gx >= 0 && gx < W)
             v = *reinterpret_cast<const uint4 *>(in + ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8);
-        *reinterpret_cast<uint4 *>(patch + pix * PS + 8 * c8) = v;
+        *reinterpret_cast<uint4 *>(patch + (pix / PW) * RS + (pix % PW) * PS + 8 * c8) = v;
     }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -327,7 +331,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
     for (int r = 0; r < 4; ++r) {
         const int ql = 4 * r + (r16 >> 2), sub = r16 & 3;
         const int y = 4 * wm + 2 * (ql / QW) + (sub >> 1), x = 2 * (ql % QW) + (sub & 1);
-        abase[r] = ((y + 1) * PW + (x + 1)) * PS + 8 * kq;
+        abase[r] = (y + 1) * RS + (x + 1) * PS + 8 * kq;
     }
     const u16 *wrow[NT];
 #pragma unroll
@@ -348,7 +352,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
             for (int c = 0; c < NT; ++c) bnext[c].u = *reinterpret_cast<const uint4 *>(wrow[c] + (kk + 1) * 32);
         }
         const int tap = kk / KPT, ci0 = (kk - tap * KPT) * 32;
-        const int shift = ((tap / 3 - 1) * PW + (tap % 3 - 1)) * PS + ci0;
+        const int shift = (tap / 3 - 1) * RS + (tap % 3 - 1) * PS + ci0;
         Frag a[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r].u = *reinterpret_cast<const uint4 *>(patch + abase[r] + shift);
