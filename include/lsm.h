@@ -121,7 +121,8 @@ typedef struct {
 
 /* One launch configuration of the step kernel and its measured time. */
 typedef struct {
-    int32_t variant;          /* LSM_KERNEL_* as set (AUTO: chosen per lattice) */
+    int32_t variant;          /* LSM_KERNEL_*; from lsm_get_launch the kernel that
+                                 runs the interior steps (AUTO resolved) */
     int32_t rows_per_wave;    /* sweep row chunk */
     int32_t prefetch;         /* sweep rows prefetched ahead */
     int32_t steps_per_launch; /* interior steps per launch: 2 for the two-step

@@ -1173,7 +1173,9 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
 
 int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
     if (!h || !out) return LSM_EINVAL;
-    *out = lsm_tuning{h->variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
+    // the kernel that runs the interior steps (AUTO resolved)
+    const int variant = use_sweep2(h) ? LSM_KERNEL_SWEEP2 : (use_sweep(h) ? LSM_KERNEL_SWEEP : LSM_KERNEL_GATHER);
+    *out = lsm_tuning{variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
     return LSM_OK;
 }
 
