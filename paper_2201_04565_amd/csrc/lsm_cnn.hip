@@ -293,7 +293,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
 template <int CIN, int TW, int BN, int EPI>
-__global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
                                                   uint8_t *mask_out, int B, int H, int W, int Cout) {
     constexpr int PH = 10, PW = TW + 2;
     // u16 per staged pixel and per staged row: pixel strides of 4 (mod 32)
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds(const u16 *in, const u16 *wt,
 #pragma unroll
     for (int c = 0; c < NT; ++c) bcur[c].u = *reinterpret_cast<const uint4 *>(wrow[c]);
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 1
     for (int kk = 0; kk < NK; ++kk) {
         if (kk + 1 < NK) {
 #pragma unroll
