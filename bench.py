@@ -341,7 +341,7 @@ def main():
     if args.workload == "c3":
         kname = "k_step<3,1,1> (fp32 compensated, one thread per particle)"
     else:
-        kname = {2: "k_sweep2d_x2<1,1,0> (fp32 compensated, two interior steps per launch)",
+        kname = {2: "k_sweep2d_x2<1,1> (fp32 compensated, two interior steps per launch)",
                  1: "k_sweep2d<1,1,1,0> (fp32 compensated, one interior step per launch)"}[spl]
     roofline = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm_gbs / HBM_PEAK_GBS,
