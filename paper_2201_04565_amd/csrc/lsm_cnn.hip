@@ -293,8 +293,9 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
 template <int CIN, int TW, int BN, int EPI>
-__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_lds(const u16 *in, const u16 *wt, const float *bias, u16 *out,
-                                                  uint8_t *mask_out, int B, int H, int W, int Cout) {
+__device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *in, const u16 *wt, const float *bias,
+                                                                    u16 *out, uint8_t *mask_out, int B, int H, int W,
+                                                                    int Cout) {
     constexpr int PH = 10, PW = TW + 2;
     // u16 per staged pixel and per staged row: pixel strides of 4 (mod 32)
     // LDS banks and row strides of 16 put the eight pixels that one
@@ -397,6 +398,21 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
     }
 }
 
+// Register target of four waves per SIMD; with 128 input channels the
+// 49 KB patch leaves room for three workgroups per CU anyway, and that
+// variant keeps its registers (measured faster than squeezed).
+template <int CIN, int TW, int BN, int EPI>
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_lds(
+    const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask_out, int B, int H, int W, int Cout) {
+    conv_lds_body<CIN, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+}
+
+template <int TW, int BN, int EPI>
+__global__ __launch_bounds__(kBlk) void k_conv_lds128(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                                                     uint8_t *mask_out, int B, int H, int W, int Cout) {
+    conv_lds_body<128, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+}
+
 // The staged-patch kernel takes layers with 32, 64 or 128 input channels
 // whose 8 x TW tiles and 64-channel blocks divide the layer exactly; layers
 // with a multiple of 128 output channels take 128-channel blocks (one
@@ -415,7 +431,7 @@ void launch_conv_lds_bn(hipStream_t st, const u16 *in, const u16 *wt, const floa
     else if (Cin == 64)
         hipLaunchKernelGGL((k_conv_lds<64, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
     else
-        hipLaunchKernelGGL((k_conv_lds<128, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+        hipLaunchKernelGGL((k_conv_lds128<TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
 }
 
 template <int EPI>
