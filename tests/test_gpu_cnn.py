@@ -96,6 +96,29 @@ def test_forward_and_gradients_match_oracle(torch_cnn):
         assert a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30) > 0.99
 
 
+def test_forward_at_c5_size_matches_oracle(torch_cnn):
+    # 128 x 128 images, the surrogate's size: layers 2-4 (64, 32, 16 pixels
+    # square) run the staged-patch kernel with 8 x 16 tiles and pooling,
+    # layer 5 (8 x 8) the staged kernel with 8 x 8 tiles and a plain store
+    torch, cnn = torch_cnn
+    say("full network 128x128 batch 3: forward vs oracle")
+    net = cnn.Network(size=128, batch=3)
+    m = co.Model(net.channels, net.hidden, net.outputs, bf16=True)
+    p = co.he_init(m.spec, m.n, 11)
+    rng = np.random.default_rng(11)
+    for sp in m.spec:
+        o, nb = sp["b"]
+        p[o:o + nb] = rng.normal(0, 0.05, nb)
+    p32 = p.astype(np.float32).astype(np.float64)
+    net.set_params(p32)
+    imgs = (rng.random((3, 128, 128)) < 0.35).astype(np.uint8)
+    y = net.forward(torch.from_numpy(imgs).to("cuda:0"))
+    net.synchronize()
+    yg = y.cpu().numpy().astype(np.float64)
+    yo = m.forward(p32, imgs)
+    assert np.max(np.abs(yg - yo)) <= 0.02 * np.max(np.abs(yo)) + 1e-4
+
+
 def test_adam_and_training_reduce_loss(torch_cnn):
     torch, cnn = torch_cnn
     say("training 200 steps on 64 images 32x32")
