@@ -48,6 +48,7 @@ struct lsm_handle {
     bool built = false, bound = false;
     int64_t nx = 0, ny = 0, nz = 0, nsites = 0, n = 0, m = 0;
     std::vector<uint8_t> flags;
+    std::vector<uint8_t> mask_init;   // 2D: break bits of absent springs (host copy for upload)
     std::vector<uint32_t> sbase;
     std::vector<int32_t> site_of;  // particle id -> site
     TypeRec types[lsm::kMaxTypes]{};
@@ -164,6 +165,30 @@ bool fwd_neighbor(const lsm_handle *h, int64_t i, int64_t j, int64_t k, int d, i
     if (h->flags[g] == lsm::kVoid) return false;
     *gq = g;
     return true;
+}
+
+// Break bits of a fresh 2D lattice of nx x ny sites: bits 0-2 (forward
+// springs E, UL, UR) and 3-5 (their opposites W, DR, DL) are set for every
+// spring that does not exist -- a void or off-lattice neighbour -- and a
+// void site has all six, so the row sweeps test one bit per spring.  Only
+// existing springs are ever reported, so the extra bits are never read as
+// broken ones.
+void absent_spring_bits_2d(const uint8_t *fl, int64_t nx, int64_t ny, uint8_t *mask) {
+    for (int64_t g = 0; g < nx * ny; ++g) mask[g] = 0x3F;
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            const int64_t g = i + nx * j;
+            if (fl[g] == lsm::kVoid) continue;
+            for (int d = 0; d < 3; ++d) {
+                const int *o = (j & 1) ? kFwd2Odd[d] : kFwd2Even[d];
+                const int64_t qi = i + o[0], qj = j + o[1];
+                if (qi < 0 || qi >= nx || qj < 0 || qj >= ny) continue;
+                const int64_t q = qi + nx * qj;
+                if (fl[q] == lsm::kVoid) continue;
+                mask[g] &= uint8_t(~(1u << d));
+                mask[q] &= uint8_t(~(8u << d));
+            }
+        }
 }
 
 void site_X0(const lsm_handle *h, int64_t g, double *X) {
@@ -609,6 +634,16 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_types, h->types, sizeof(h->types), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemcpyAsync(h->d_flags, h->flags.data(), h->flags.size(), hipMemcpyHostToDevice, h->stream));
     HIPCHK(h, hipMemsetAsync(h->d_flags + h->nsites, lsm::kVoid, 1, h->stream));  // sentinel site
+    if (h->dim == 2) {
+        // break bits of absent springs, in both break-bit buffers, and a
+        // sentinel whose springs are all absent
+        h->mask_init.assign(size_t(h->nsites) + 1, 0x3F);
+        absent_spring_bits_2d(h->flags.data(), h->nx, h->ny, h->mask_init.data());
+        HIPCHK(h, hipMemcpyAsync(h->d_mask, h->mask_init.data(), h->mask_init.size(), hipMemcpyHostToDevice,
+                                 h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->d_mask_alt, h->mask_init.data(), h->mask_init.size(), hipMemcpyHostToDevice,
+                                 h->stream));
+    }
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->plist.empty())
         HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -1213,6 +1248,7 @@ struct lsm_batch {
     std::vector<int32_t> nx, ny;
     std::vector<int64_t> base, npart, nspring;
     std::vector<uint8_t> flags;
+    std::vector<uint8_t> mask_init;  // break bits of absent springs (host copy for upload)
     TypeRec types[lsm::kMaxTypes]{};
     std::vector<SpecDesc> specs;
     int64_t npartials = 0;
@@ -1689,6 +1725,15 @@ int lsm_batch_bind(lsm_batch *b, void *dptr, size_t bytes, void *hip_stream) {
     BHIPCHK(b, hipMemcpyAsync(b->d_types, b->types, sizeof(b->types), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipMemcpyAsync(b->d_flags, b->flags.data(), b->flags.size(), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipMemsetAsync(b->d_flags + b->nsites, lsm::kVoid, 1, b->stream));  // sentinel site
+    // break bits of absent springs per specimen, in both buffers (the second
+    // one exists for FP32-compensated batches), and an all-absent sentinel
+    b->mask_init.assign(size_t(b->nsites) + 1, 0x3F);
+    for (int64_t sp = 0; sp < b->nspec; ++sp)
+        absent_spring_bits_2d(b->flags.data() + b->base[sp], b->nx[sp], b->ny[sp], b->mask_init.data() + b->base[sp]);
+    BHIPCHK(b, hipMemcpyAsync(b->d_mask, b->mask_init.data(), b->mask_init.size(), hipMemcpyHostToDevice, b->stream));
+    if (b->prec)
+        BHIPCHK(b, hipMemcpyAsync(b->d_mask_alt, b->mask_init.data(), b->mask_init.size(), hipMemcpyHostToDevice,
+                                  b->stream));
     BHIPCHK(b, hipMemcpyAsync(b->d_specs, b->specs.data(), b->specs.size() * sizeof(SpecDesc),
                               hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));

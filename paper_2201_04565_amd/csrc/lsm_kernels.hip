@@ -724,11 +724,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, DevRecord *re
 // (the edge lane reads zero; edge lanes are never owned).
 __device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
 __device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
-// Site flags: the edge lane reads a void site, so its springs across the
-// wavefront edge are absent (zero positions there would otherwise send them
-// down the FP64 break test on every row).
-__device__ inline int flag_next(int f) { return __builtin_amdgcn_update_dpp(int(kVoid), f, 0x130, 0xF, 0xF, false); }
-__device__ inline int flag_prev(int f) { return __builtin_amdgcn_update_dpp(int(kVoid), f, 0x138, 0xF, 0xF, false); }
 __device__ inline float lane_next(float x) { return __int_as_float(lane_next(__float_as_int(x))); }
 __device__ inline float lane_prev(float x) { return __int_as_float(lane_prev(__float_as_int(x))); }
 __device__ inline double lane_next(double x) {
@@ -831,7 +826,7 @@ __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, i
                                   double ex64, double ey64, const typename State<2, PREC>::R *ph,
                                   const typename State<2, PREC>::R *pl,
                                   const typename State<2, PREC>::R *qh,
-                                  const typename State<2, PREC>::R *ql, int fq,
+                                  const typename State<2, PREC>::R *ql, int fq, bool edge_ok,
                                   typename State<2, PREC>::R *f, int &present, int &brk,
                                   double &margin, int &ti) {
     using R = typename State<2, PREC>::R;
@@ -841,7 +836,10 @@ __device__ inline void fwd_spring(const TTy *tt, const TypeRec *types, int fp, i
         // phases are below LSM_MAX_PHASES = 8, so masking keeps void lanes in
         // the table
         ti = (fp & 7) * LSM_MAX_PHASES + (fq & 7);
-        const bool act = present && !(mask & (1 << d));
+        // the break bits also mark springs that do not exist (void or
+        // off-lattice neighbour, void site), so one bit decides; a lane whose
+        // neighbour lies across the wavefront edge is never owned and skips it
+        const bool act = edge_ok && !(mask & (1 << d));
         R dv[2];
         dv[0] = ex + ((qh[0] - ph[0]) + (ql[0] - pl[0]));
         dv[1] = (qh[1] - ph[1]) + (ql[1] - pl[1]);
@@ -919,7 +917,8 @@ template <int PREC, int PAR, class TTy>
 __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
                                    const SweepRow<typename State<2, PREC>::R> &rc,
                                    const SweepRow<typename State<2, PREC>::R> &ru,
-                                   RowSprings<typename State<2, PREC>::R> &o, double a64) {
+                                   RowSprings<typename State<2, PREC>::R> &o, double a64, bool not_last,
+                                   bool not_first) {
     using R = typename State<2, PREC>::R;
     const R a = R(a64), hy = R(kHalfSqrt3 * a64);
     const double hy64 = kHalfSqrt3 * a64;
@@ -930,7 +929,7 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
         o.eh[cc] = lane_next(rc.uh[cc]);
         o.el[cc] = PREC ? lane_next(rc.ul[cc]) : R(0);
     }
-    ef = flag_next(rc.f);
+    ef = lane_next(rc.f);
     if constexpr (PAR == 0) {
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
@@ -939,7 +938,7 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
             o.urh[cc] = ru.uh[cc];
             o.url[cc] = ru.ul[cc];
         }
-        ulf = flag_prev(ru.f);
+        ulf = lane_prev(ru.f);
         urf = ru.f;
     } else {
 #pragma unroll
@@ -950,13 +949,15 @@ __device__ inline void row_springs(const TTy *tt, const TypeRec *types,
             o.url[cc] = PREC ? lane_next(ru.ul[cc]) : R(0);
         }
         ulf = ru.f;
-        urf = flag_next(ru.f);
+        urf = lane_next(ru.f);
     }
-    fwd_spring<PREC>(tt, types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, o.eh, o.el, ef, o.fe, o.pe,
+    fwd_spring<PREC>(tt, types, rc.f, rc.m, 0, a, R(0), a64, 0.0, rc.uh, rc.ul, o.eh, o.el, ef, not_last, o.fe, o.pe,
                      o.be, o.me, o.te);
     fwd_spring<PREC>(tt, types, rc.f, rc.m, 1, -half_a, hy, -0.5 * a64, hy64, rc.uh, rc.ul, o.ulh, o.ull, ulf,
+                     PAR == 0 ? not_first : true,
                      o.ful, o.pul, o.bul, o.mul, o.tul);
     fwd_spring<PREC>(tt, types, rc.f, rc.m, 2, half_a, hy, 0.5 * a64, hy64, rc.uh, rc.ul, o.urh, o.url, urf,
+                     PAR == 0 ? true : not_last,
                      o.fur, o.pur, o.bur, o.mur, o.tur);
     o.nb = o.be | (o.bul << 1) | (o.bur << 2);
     o.fb = o.nb | (rc.m & 7);
@@ -1031,6 +1032,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const int i = it.i0 + lane;
         const bool col_ok = i >= 0 && i < it.nx;
         const bool own_lane = col_ok && lane >= 1 && lane <= kSweepCols;
+        const bool not_last = lane != 63, not_first = lane != 0;  // DPP neighbours inside the wavefront
         const int j0 = it.j0;
         const int j1 = it.j1;
         const int jstart = j0 > 0 ? j0 - 1 : 0;
@@ -1047,7 +1049,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
             constexpr int PAR = decltype(parc)::value;
             load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn);
             RowSprings<R> o;
-            row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a);
+            row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a, not_last, not_first);
             const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
             const R *fe = o.fe, *ful = o.ful, *fur = o.fur;
             const int pe = o.pe, pul = o.pul, pur = o.pur, be = o.be, bul = o.bul, bur = o.bur;
@@ -1220,6 +1222,7 @@ __device__ __attribute__((always_inline)) inline void sweep2d_x2_body(const Step
     const int i = it.i0 + lane;
     const bool col_ok = i >= 0 && i < it.nx;
     const bool own = col_ok && lane >= 2 && lane <= kSweepCols2 + 1;
+    const bool not_last = lane != 63, not_first = lane != 0;  // DPP neighbours inside the wavefront
     const int j0 = it.j0, j1 = it.j1;
     const int ja = j0 >= 2 ? j0 - 2 : 0;
     const int a0 = ja & ~1;  // even: the parity of each unrolled row is a constant
@@ -1239,7 +1242,7 @@ __device__ __attribute__((always_inline)) inline void sweep2d_x2_body(const Step
         load_sweep_row<PREC>(P, it, i, col_ok, jn <= j1 + 1 ? jn : -1, rn);
         // ---- stage A: row a, step s
         RowSprings<R> oa;
-        row_springs<PREC, PAR>(tt, P.types, rc, ru, oa, P.a);
+        row_springs<PREC, PAR>(tt, P.types, rc, ru, oa, P.a, not_last, not_first);
         SweepRow<R> &Acur = rc;
         if (a >= j0 - 1) {
             R F[2];
@@ -1266,7 +1269,7 @@ __device__ __attribute__((always_inline)) inline void sweep2d_x2_body(const Step
         const int b = a - 1;
         if (b >= j0 - 1) {
             RowSprings<R> ob;
-            row_springs<PREC, PAR ^ 1>(tt, P.types, Aprev, Acur, ob, P.a);
+            row_springs<PREC, PAR ^ 1>(tt, P.types, Aprev, Acur, ob, P.a, not_last, not_first);
             if (b >= j0) {
                 R F[2];
                 int nm;
