@@ -761,13 +761,14 @@ __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, 
     // specimen a lane reads its flag and break bits from the sentinel site
     // after the last one (void, no bits) and its displacement and velocity
     // from the specimen's first site: springs with a void end and unowned
-    // sites never use them.  Offsets are 32-bit: the sweeps run lattices
-    // and batches of fewer than 2^28 sites.
+    // sites never use them.  Offsets are 32-bit and relative to the
+    // specimen's first site, whose address is uniform over the wavefront
+    // (the sweeps run lattices and batches of fewer than 2^28 sites).
     using R = typename State<2, PREC>::R;
     const bool ok = col_ok && jj >= 0 && jj < it.ny;
-    const uint32_t g = uint32_t(it.base) + (ok ? uint32_t(i + it.nx * jj) : 0u);
-    const uint32_t gf = ok ? g : uint32_t(P.nsites);
-    const char *ub = static_cast<const char *>(P.u_in) + g * 16u;
+    const uint32_t g = ok ? uint32_t(i + it.nx * jj) : 0u;
+    const uint32_t gf = ok ? g : uint32_t(P.nsites - it.base);
+    const char *ub = static_cast<const char *>(P.u_in) + size_t(it.base) * 16u + g * 16u;
     if constexpr (PREC == 1) {
         const float4 t = *reinterpret_cast<const float4 *>(ub);
         r.uh[0] = t.x; r.uh[1] = t.y; r.ul[0] = t.z; r.ul[1] = t.w;
@@ -775,11 +776,11 @@ __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, 
         const double2 t = *reinterpret_cast<const double2 *>(ub);
         r.uh[0] = t.x; r.uh[1] = t.y; r.ul[0] = 0.0; r.ul[1] = 0.0;
     }
-    r.f = P.flags[gf];
-    r.m = reinterpret_cast<const uint8_t *>(P.mask)[gf];
+    r.f = (P.flags + it.base)[gf];
+    r.m = (reinterpret_cast<const uint8_t *>(P.mask) + it.base)[gf];
     // the velocity too, also on the halo row below the chunk that is never
     // advanced: one more load there costs less than the branch around it
-    const char *vb = static_cast<const char *>(P.v) + g * uint32_t(2 * sizeof(R));
+    const char *vb = static_cast<const char *>(P.v) + size_t(it.base) * (2 * sizeof(R)) + g * uint32_t(2 * sizeof(R));
     if constexpr (PREC == 1) {
         const float2 t = *reinterpret_cast<const float2 *>(vb);
         r.v[0] = t.x; r.v[1] = t.y;
@@ -1275,13 +1276,14 @@ __device__ __attribute__((always_inline)) inline void sweep2d_x2_body(const Step
                 int nm;
                 row_force<PAR ^ 1>(ob, bUL, bUR, bbrk, Aprev.m, F, nm);
                 if (own && Aprev.f != kVoid) {
-                    const uint32_t g = uint32_t(it.base + i + it.nx * b);
-                    reinterpret_cast<uint8_t *>(P.mask_out)[g] = uint8_t(nm);
+                    // offset from the specimen's first site (uniform base addresses)
+                    const uint32_t g = uint32_t(i + it.nx * b);
+                    (reinterpret_cast<uint8_t *>(P.mask_out) + it.base)[g] = uint8_t(nm);
                     if (ob.nb) {
                         if constexpr (BATCH)
                             atomicAdd(&P.spec_broken[it.spec], uint32_t(ob.be + ob.bul + ob.bur));
                         else
-                            log_breaks<PREC>(P, g, ob, step_local + 1);
+                            log_breaks<PREC>(P, g, ob, step_local + 1);  // one lattice: base 0
                     }
                     R uh[2], ul[2], v[2];
 #pragma unroll
@@ -1294,8 +1296,8 @@ __device__ __attribute__((always_inline)) inline void sweep2d_x2_body(const Step
                     site_acc<2, PREC>(F, v, 0.0, imass_f[Aprev.f & 63], gam, acc);
                     mid_kick_drift<2, PREC>(uh, ul, v, acc, h, dt);
                     const RowStore<PREC> st{g};
-                    st.v(P.v_out, v);
-                    st.u(P.u_out, uh, ul);
+                    st.v(static_cast<char *>(P.v_out) + size_t(it.base) * (2 * sizeof(R)), v);
+                    st.u(static_cast<char *>(P.u_out) + size_t(it.base) * 16u, uh, ul);
                 }
             }
 #pragma unroll

@@ -202,6 +202,28 @@ def test_c2_full_size_first_steps(lsm):
     assert np.max(np.abs(xg[idx] - xo)) < 1e-6
 
 
+def test_c3_full_size_first_steps(lsm):
+    # the 256^3 random-field lattice in the launch the bench times (the
+    # gather kernel, one thread per particle) against the oracle
+    img = inputs.c3_image()
+    wl = inputs.WORKLOADS["c3"]
+    say("c3 256^3 fp32k full size: 1 increment x 10 steps vs oracle")
+    g = gpu_for(lsm, img, wl, "fp32k")
+    g.apply_increment(wl["d_eps"])
+    g.relax(10)
+    rg = g.read_state()
+    xg = g.x
+    del g
+    say("  oracle (about a second per step)")
+    o = oracle_for(img, wl)
+    o.apply_increment(wl["d_eps"])
+    o.relax(10)
+    ro = o.record()
+    compare_records([ro], [rg], 1e-3, 3)
+    idx = np.random.default_rng(0).choice(o.n, 20000, replace=False)
+    assert np.max(np.abs(xg[idx] - o.x[idx])) < 1e-6
+
+
 # ------------------------------------------------------------- properties
 def test_two_step_sweep_rejects_fp64(lsm):
     g = gpu_for(lsm, inputs.brick_and_mortar(40, 12, seed=1), inputs.WORKLOADS["c2"], "fp64")
