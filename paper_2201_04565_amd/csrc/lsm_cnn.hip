@@ -40,10 +40,8 @@ constexpr int kLayers = 5;
 constexpr int kBlk = 256;
 
 __device__ inline u16 f2bf(float x) {
-    // round to nearest even (inputs are finite)
-    unsigned int u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u16(u >> 16);
+    // round to nearest even: one hardware conversion (v_cvt_pk_bf16_f32)
+    return __builtin_bit_cast(u16, __bf16(x));
 }
 __device__ inline float bf2f(u16 h) { return __uint_as_float(unsigned(h) << 16); }
 
@@ -682,6 +680,9 @@ __global__ __launch_bounds__(kBlk) void k_gap_fwd(const u16 *in, float *out, int
     const int c = int(i % C);
     const int64_t n = i / C;
     float s = 0.0f;
+    // unrolled so the loads of eight pixels are in flight together (the sum
+    // keeps its order)
+#pragma unroll 8
     for (int p = 0; p < HW; ++p) s += bf2f(in[(n * HW + p) * C + c]);
     out[i] = s / float(HW);
 }
@@ -699,10 +700,11 @@ __global__ __launch_bounds__(kBlk) void k_gap_bwd_relu(const float *dg, const u1
 // ---------------------------------------------------------- dense layers
 // y[n, o] = act(b[o] + sum_i w[o, i] x[n, i]), summed in the order i = 0,
 // 1, ...  A workgroup computes 8 samples x 64 outputs (two outputs per
-// thread), staging 64-wide slices of x and w in LDS with coalesced row
+// thread), staging 128-wide slices of x and w in LDS with coalesced row
 // loads (rows padded by one float against bank conflicts); the small tile
-// gives a few hundred workgroups for a batch of 512.
-constexpr int kFcN = 8, kFcO = 64, kFcI = 64;
+// gives a few hundred workgroups for a batch of 512, and the wide slices
+// few staging round trips (two for 256 inputs).
+constexpr int kFcN = 8, kFcO = 64, kFcI = 128;
 
 __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w, const float *b, float *y, int B,
                                                 int In, int Out, int relu) {
@@ -717,15 +719,44 @@ __global__ __launch_bounds__(kBlk) void k_fc_fwd(const float *x, const float *w,
         s[j] = o < Out ? b[o] : 0.0f;
     }
     for (int i0 = 0; i0 < In; i0 += kFcI) {
-        for (int e = threadIdx.x; e < kFcN * kFcI; e += kBlk) {
-            const int r = e / kFcI, c = e % kFcI;
-            const int n = n0 + r, i = i0 + c;
-            xs[r][c] = (n < B && i < In) ? x[int64_t(n) * In + i] : 0.0f;
-        }
-        for (int e = threadIdx.x; e < kFcO * kFcI; e += kBlk) {
-            const int r = e / kFcI, c = e % kFcI;
-            const int o = o0 + r, i = i0 + c;
-            ws[r][c] = (o < Out && i < In) ? w[int64_t(o) * In + i] : 0.0f;
+        // fixed trip counts, unrolled; a slice inside the matrices (uniform
+        // over the workgroup) loads without guards, so every staging load is
+        // in flight before the first LDS store waits
+        static_assert((kFcN * kFcI) % kBlk == 0 && (kFcO * kFcI) % kBlk == 0, "whole staging rounds");
+        const bool inside = n0 + kFcN <= B && o0 + kFcO <= Out && i0 + kFcI <= In;
+        if (inside) {
+            float xv[kFcN * kFcI / kBlk], wv[kFcO * kFcI / kBlk];
+#pragma unroll
+            for (int t = 0; t < kFcN * kFcI / kBlk; ++t) {
+                const int e = int(threadIdx.x) + t * kBlk;
+                xv[t] = x[int64_t(n0 + e / kFcI) * In + i0 + e % kFcI];
+            }
+#pragma unroll
+            for (int t = 0; t < kFcO * kFcI / kBlk; ++t) {
+                const int e = int(threadIdx.x) + t * kBlk;
+                wv[t] = w[int64_t(o0 + e / kFcI) * In + i0 + e % kFcI];
+            }
+#pragma unroll
+            for (int t = 0; t < kFcN * kFcI / kBlk; ++t) {
+                const int e = int(threadIdx.x) + t * kBlk;
+                xs[e / kFcI][e % kFcI] = xv[t];
+            }
+#pragma unroll
+            for (int t = 0; t < kFcO * kFcI / kBlk; ++t) {
+                const int e = int(threadIdx.x) + t * kBlk;
+                ws[e / kFcI][e % kFcI] = wv[t];
+            }
+        } else {
+            for (int e = threadIdx.x; e < kFcN * kFcI; e += kBlk) {
+                const int r = e / kFcI, c = e % kFcI;
+                const int n = n0 + r, i = i0 + c;
+                xs[r][c] = (n < B && i < In) ? x[int64_t(n) * In + i] : 0.0f;
+            }
+            for (int e = threadIdx.x; e < kFcO * kFcI; e += kBlk) {
+                const int r = e / kFcI, c = e % kFcI;
+                const int o = o0 + r, i = i0 + c;
+                ws[r][c] = (o < Out && i < In) ? w[int64_t(o) * In + i] : 0.0f;
+            }
         }
         __syncthreads();
         const int ni = min(kFcI, In - i0);
@@ -766,6 +797,7 @@ __global__ __launch_bounds__(kBlk) void k_fc_bwd_data(const float *dy, const flo
     const int i = int(t % In);
     const int64_t n = t / In;
     float s = 0.0f;
+#pragma unroll 8
     for (int o = 0; o < Out; ++o) s = fmaf(w[int64_t(o) * In + i], dy[n * Out + o], s);
     if (xact && !(xact[t] > 0.0f)) s = 0.0f;
     dx[t] = s;
@@ -779,7 +811,15 @@ __global__ __launch_bounds__(kBlk) void k_fc_bwd_weight(const float *dy, const f
     const int i = int(t % (In + 1));
     const int o = int(t / (In + 1));
     float s = 0.0f;
-    for (int n = 0; n < B; ++n) s = fmaf(dy[int64_t(n) * Out + o], i < In ? x[int64_t(n) * In + i] : 1.0f, s);
+    // unrolled so the loads of sixteen samples are in flight together (the
+    // sum keeps its order); the bias column multiplies by one
+    if (i < In) {
+#pragma unroll 16
+        for (int n = 0; n < B; ++n) s = fmaf(dy[int64_t(n) * Out + o], x[int64_t(n) * In + i], s);
+    } else {
+#pragma unroll 16
+        for (int n = 0; n < B; ++n) s = fmaf(dy[int64_t(n) * Out + o], 1.0f, s);
+    }
     if (i < In)
         dw[int64_t(o) * In + i] = s;
     else
