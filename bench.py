@@ -175,6 +175,48 @@ def cnn_forward_flops(size=128, channels=(32, 64, 128, 128, 256), hidden=256, ou
     return f + 2 * (cin * hidden + hidden * outputs)
 
 
+def small_c1(args, inputs, lsm):
+    """C1 (32 x 32 two-phase lattice, FP64, 20 x 0.5 % x 500 steps): a
+    lattice this small is launch-bound, so the interior steps run in one
+    workgroup with the state in LDS (one launch per relaxation chunk);
+    timed beside per-step launches of the gather and two-step sweep
+    kernels, with the oracle's full run on one host core."""
+    wl = inputs.WORKLOADS["c1"]
+    img = inputs.c1_image()
+    res = {"workload": "c1 32x32 two-phase triangular lattice, fp64, 20 x 0.5% x 500 steps"}
+    for variant in ("small", "gather", "sweep"):
+        lat = lsm.Lattice.from_workload(wl, img, precision="fp64", device="cuda:0")
+        lat.set_launch(variant)
+        lat.apply_increment(wl["d_eps"])  # warm-up: graphs and code objects
+        lat.relax(wl["steps"])
+        lat.set_timing(True)
+        lat.read_timing()
+        lat.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(wl["n_inc"] - 1):
+            lat.apply_increment(wl["d_eps"])
+            lat.relax(wl["steps"])
+        lat.synchronize()
+        wall = time.perf_counter() - t0
+        ms, n = lat.read_timing()
+        rec = lat.read_state()
+        res[variant] = {"us_per_interior_step": 1e3 * ms / max(n, 1),
+                        "steps_per_s_wall": (wl["n_inc"] - 1) * wl["steps"] / wall,
+                        "broken_springs_at_end": rec["n_broken"]}
+        del lat
+    if not args.no_cpu:
+        from oracle import Net, Params
+        o = Net.lattice(img, Params(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
+                                    dt=wl["dt"], gamma=wl["gamma"], void_value=wl.get("void_value", -1)))
+        t0 = time.perf_counter()
+        for _ in range(wl["n_inc"]):
+            o.apply_increment(wl["d_eps"])
+            o.relax(wl["steps"])
+        res["cpu_baseline"] = {"seconds_full_run": time.perf_counter() - t0, "cores": 1, "kind": "oracle",
+                               "broken_springs_at_end": len(o.events())}
+    return res
+
+
 def cnn_kernels(torch, batch=512, size=128, iters=10):
     """Surrogate network kernels alone: one training step (forward, loss,
     backward, Adam) and one inference pass on a batch of 128 x 128 images,
@@ -273,6 +315,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip the batched-model + surrogate pipeline (on by default at reduced size)")
     ap.add_argument("--cnn-bench", action="store_true", help="also time the surrogate network kernels")
+    ap.add_argument("--no-c1", action="store_true", help="skip the small-lattice (C1) section")
     ap.add_argument("--sur-train", type=int, default=4096,
                     help="training specimens (the full C5 configuration: 50000)")
     ap.add_argument("--sur-test", type=int, default=1024, help="test specimens (C5: 5000)")
@@ -400,6 +443,9 @@ def main():
         out["batched"] = batched_c4(args, torch, inputs, lsm)
         if not args.no_cpu:
             out["batched"]["cpu_baseline"] = cpu_c4(args, inputs)
+    if args.workload == "c2" and not args.no_c1:
+        print("[bench] c1 small lattice", file=sys.stderr, flush=True)
+        out["c1"] = small_c1(args, inputs, lsm)
     if args.cnn_bench:
         print("[bench] surrogate network kernels", file=sys.stderr, flush=True)
         out["cnn"] = cnn_kernels(torch)

@@ -60,6 +60,13 @@ extern "C" {
 #define LSM_KERNEL_SWEEP2 3 /* 2D, FP32-compensated: row sweep advancing two interior
                                steps per launch (same results as LSM_KERNEL_SWEEP, about
                                half the memory traffic); LSM_EINVAL for FP64 lattices */
+#define LSM_KERNEL_SMALL 4  /* 2D lattices whose state fits one workgroup's LDS (about
+                               1,100 sites in FP64, 1,300 FP32-compensated): all
+                               interior steps of a relaxation chunk in one launch of one
+                               workgroup (same results as LSM_KERNEL_GATHER, whose kernel
+                               runs the start and end steps); LSM_EINVAL for 3D or larger
+                               lattices (a lattice built later and too large runs the
+                               gather kernel) */
 
 /* Model and integration parameters.
  *  k[P*P], break_stretch[P*P]: row-major, symmetric spring constant and

@@ -251,8 +251,16 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
 }
 
 bool use_sweep(const lsm_handle *h) {
-    return h->dim == 2 && h->variant != LSM_KERNEL_GATHER && h->nsites <= lsm::kSweepMaxSites;
+    return h->dim == 2 && (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_SWEEP ||
+                           h->variant == LSM_KERNEL_SWEEP2) &&
+           h->nsites <= lsm::kSweepMaxSites;
 }
+// one workgroup with the state in LDS for the interior steps (as asked for;
+// start and end steps run the gather kernel)
+bool small_fits(const lsm_handle *h) {
+    return h->dim == 2 && h->nsites > 0 && lsm::small_lds_bytes(h->nsites, h->prec) <= lsm::kSmallLdsBytes;
+}
+bool use_small(const lsm_handle *h) { return h->variant == LSM_KERNEL_SMALL && small_fits(h); }
 // interior steps in pairs per launch: the default for 2D FP32-compensated lattices
 bool use_sweep2(const lsm_handle *h) {
     return use_sweep(h) && h->prec && (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
@@ -306,13 +314,21 @@ hipError_t launch_phase(const lsm_handle *h, StepParams &p, int mode, int step_l
 // Launches of `chunk` interior steps: pairs per launch with the two-step
 // sweep (an odd chunk ends with a single step), single steps otherwise.
 int two_step_launches(const lsm_handle *h, int chunk) { return use_sweep2(h) ? chunk / 2 : 0; }
-int mid_launches(const lsm_handle *h, int chunk) { return use_sweep2(h) ? chunk / 2 + (chunk & 1) : chunk; }
+int mid_launches(const lsm_handle *h, int chunk) {
+    if (use_small(h)) return chunk > 0 ? 1 : 0;
+    return use_sweep2(h) ? chunk / 2 + (chunk & 1) : chunk;
+}
 
 // Interior steps local .. local + chunk - 1 from displacement buffer c; the
 // two-step launches read velocities / break bits from the current buffers
 // and write the other ones, swapping them for the next launch.
 hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
     hipError_t le = hipSuccess;
+    if (use_small(h)) {
+        if (chunk < 1) return hipSuccess;
+        StepParams p = make_params(h, c, c ^ 1);
+        return lsm::launch_small_mid(p, h->prec, h->stream, chunk, local);
+    }
     void *vc = h->d_V, *va = h->d_V_alt, *mc = h->d_mask, *ma = h->d_mask_alt;
     int s = 0;
     while (s < chunk && le == hipSuccess) {
@@ -1107,8 +1123,11 @@ int lsm_set_prefetch(lsm_handle *h, int rows_ahead) {
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     if (!h) return LSM_EINVAL;
     if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP &&
-        variant != LSM_KERNEL_SWEEP2)
+        variant != LSM_KERNEL_SWEEP2 && variant != LSM_KERNEL_SMALL)
         return fail(h, LSM_EINVAL, "unknown kernel variant");
+    if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");
+    if (variant == LSM_KERNEL_SMALL && h->built && !small_fits(h))
+        return fail(h, LSM_EINVAL, "lattice too large for the one-workgroup kernel");
     if ((variant == LSM_KERNEL_SWEEP || variant == LSM_KERNEL_SWEEP2) && h->dim != 2)
         return fail(h, LSM_EINVAL, "row sweep is 2D only");
     if (variant == LSM_KERNEL_SWEEP2 && !h->prec)
@@ -1209,7 +1228,10 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
 int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
     if (!h || !out) return LSM_EINVAL;
     // the kernel that runs the interior steps (AUTO resolved)
-    const int variant = use_sweep2(h) ? LSM_KERNEL_SWEEP2 : (use_sweep(h) ? LSM_KERNEL_SWEEP : LSM_KERNEL_GATHER);
+    const int variant = use_sweep2(h)  ? LSM_KERNEL_SWEEP2
+                        : use_sweep(h) ? LSM_KERNEL_SWEEP
+                        : use_small(h) ? LSM_KERNEL_SMALL
+                                       : LSM_KERNEL_GATHER;
     *out = lsm_tuning{variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
     return LSM_OK;
 }

@@ -113,6 +113,14 @@ hipError_t launch_increment(const StepParams &p, int dim, int prec, hipStream_t 
                             double eps_new, double d_eps, int inc, int affine);
 hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStream_t stream,
                        int step_local);
+// Small 2D lattices: nsteps interior steps (step_local ..) in one launch of
+// one workgroup holding the state in LDS (same results as nsteps launches
+// of launch_step); reads u_in, writes u_out, velocities and break bits in
+// place.  Lattices whose state needs more than kSmallLdsBytes are rejected.
+constexpr int kSmallBlock = 1024;
+constexpr size_t kSmallLdsBytes = 56 * 1024;
+size_t small_lds_bytes(int64_t nsites, int prec);
+hipError_t launch_small_mid(const StepParams &p, int prec, hipStream_t stream, int nsteps, int step_local);
 // 2D row-sweep variant of the start/mid/end steps (same semantics as launch_step).
 hipError_t launch_sweep2d(const StepParams &p, int prec, int mode, hipStream_t stream,
                           int step_local);

@@ -387,12 +387,187 @@ __device__ inline void integrate_site(const StepParams &P, const ST &st, uint8_t
 }
 
 // ------------------------------------------------------------ step kernel
+// One time step of one site: all incident springs in direction order
+// (break test, Eq. 1-2 force), then the integrator.  Everything is read and
+// written through P, so a caller may point the state arrays at LDS.
 template <int DIM, int PREC, int MODE>
-__global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
+__device__ __attribute__((always_inline)) inline void step_site(
+    const StepParams &P, const typename TT<PREC>::type *tt, const double *mass_s,
+    const typename State<DIM, PREC>::R *imass_s, int g, int i, int j, int k, uint8_t fp, double *red,
+    int step_local) {
     using S = State<DIM, PREC>;
     using R = typename S::R;
     using G = Geo<DIM>;
     using Mask = typename G::Mask;
+    using TTy = typename TT<PREC>::type;
+    const R a = R(P.a);
+    const R hy = R(kHalfSqrt3 * P.a);
+    R uph[DIM], upl[DIM];
+    S::load_u(P.u_in, g, P.nsites, uph, upl);
+    const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
+    Mask newmask = mask;
+    const int pa = flag_phase(fp);
+    const bool commit = (MODE != kEval) || P.commit;
+    R F[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) F[c] = R(0);
+    int rank = 0;
+    // neighbours in groups of kGrp: all loads of a group are issued
+    // unconditionally (from the site itself when the neighbour is outside
+    // the lattice) before any of them is used
+    constexpr int kGrp = 6;
+#pragma unroll
+    for (int d0 = 0; d0 < G::ND; d0 += kGrp) {
+    int qs[kGrp];
+    bool inb[kGrp];
+    uint8_t fqs[kGrp];
+    R uqhs[kGrp][DIM], uqls[kGrp][DIM];
+#pragma unroll
+    for (int t = 0; t < kGrp; ++t) {
+        const int d = d0 + t;
+        const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
+        const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+        inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+        qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+        fqs[t] = P.flags[qs[t]];
+        S::load_u(P.u_in, qs[t], P.nsites, uqhs[t], uqls[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kGrp; ++t) {
+        const int d = d0 + t;
+        if (!inb[t]) continue;
+        const uint8_t fq = fqs[t];
+        if (fq == kVoid) continue;
+        const bool fwd = d < G::NF;
+        const int myrank = rank;
+        if (fwd) ++rank;
+        if (mask & (Mask(1) << d)) continue;
+        const R *uqh = uqhs[t];
+        const R *uql = uqls[t];
+        // lattice vector X0_q - X0_p
+        R e[DIM];
+        double e64[DIM];
+        if constexpr (DIM == 2) {
+            e[0] = R(G::ex(d)) * a;
+            e[1] = R(G::ey(d)) * hy;
+            e64[0] = G::ex(d) * P.a;
+            e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                e[c] = R(G::off(d, c)) * a;
+                e64[c] = double(G::off(d, c)) * P.a;
+            }
+        }
+        R dv[DIM];
+        R r2 = R(0);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
+            r2 += dv[c] * dv[c];
+        }
+        const int pb = flag_phase(fq);
+        const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
+        const TTy T = tt[ti];
+        bool brk;
+        double margin = 0.0;
+        double d64[DIM];
+        double r64 = 0.0;
+        bool have64 = false;
+        if constexpr (PREC == 1) {
+            // FP32 test; inside the band (or above rc) the FP64 test decides
+            if (r2 > T.z) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) {
+                    d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
+                                       (double(uql[c]) - double(upl[c])));
+                    s2 += d64[c] * d64[c];
+                }
+                r64 = sqrt(s2);
+                have64 = true;
+                const double rc = P.types[ti].rc64;
+                brk = r64 > rc;
+                margin = (r64 - rc) / rc;
+            } else {
+                brk = false;
+            }
+        } else {
+            r64 = sqrt(double(r2));
+            have64 = true;
+            brk = r64 > T.z;
+            if (brk) margin = (r64 - T.z) / T.z;
+        }
+        if (brk) {
+            if (commit) {
+                newmask |= Mask(1) << d;
+                if (fwd) {
+                    const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                    if (idx < P.ev_cap) {
+                        lsm_event ev;
+                        ev.increment = P.ctl->inc;
+                        ev.step = P.ctl->step_base + step_local;
+                        ev.spring_id = int64_t(P.sbase[g]) + myrank;
+                        ev.margin = margin;
+                        P.events[idx] = ev;
+                    }
+                }
+            }
+            continue;
+        }
+        if constexpr (PREC == 1) {
+            const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
+            const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, dv[c], F[c]);
+        } else {
+            const double coef = T.x * (r64 - T.y) / r64;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                F[c] += coef * dv[c];
+                d64[c] = dv[c];
+            }
+        }
+        if constexpr (MODE == kEnd) {
+            if (fwd) {
+                // virial (Eq. 7) and potential energy (Eq. 1) in FP64
+                const TypeRec &T64 = P.types[ti];
+                if (!have64) {
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) {
+                        d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
+                                           (double(uql[c]) - double(upl[c])));
+                        s2 += d64[c] * d64[c];
+                    }
+                    r64 = sqrt(s2);
+                }
+                const double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
+#pragma unroll
+                for (int aa = 0; aa < DIM; ++aa)
+#pragma unroll
+                    for (int bb = 0; bb < DIM; ++bb) red[aa * 3 + bb] += d64[aa] * (coef64 * d64[bb]);
+                red[18] += 0.5 * T64.k64 * (r64 - T64.r0_64) * (r64 - T64.r0_64);
+            }
+        }
+    }
+    }
+    if (commit && newmask != mask) reinterpret_cast<Mask *>(P.mask)[g] = newmask;
+
+    if constexpr (MODE == kEval) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) P.f64[int64_t(g) * DIM + c] = double(F[c]);
+    } else {
+        R w[DIM];
+        if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
+        integrate_site<DIM, PREC, MODE>(P, SiteStore<DIM, PREC>{g, P.nsites}, fp, mass_s[pa], imass_s[pa],
+                                        uph, upl, F, w, red);
+    }
+}
+
+template <int DIM, int PREC, int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
+    using R = typename State<DIM, PREC>::R;
     using TTy = typename TT<PREC>::type;
 
     __shared__ TTy tt[kMaxTypes];
@@ -426,176 +601,11 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
     const uint8_t fp = active ? P.flags[g] : kVoid;
     active = active && fp != kVoid;
 
-    const R a = R(P.a);
-    const R hy = R(kHalfSqrt3 * P.a);
-
     double red[MODE == kEnd ? kNumPartials : 1];
 #pragma unroll
     for (int v = 0; v < (MODE == kEnd ? kNumPartials : 1); ++v) red[v] = 0.0;
 
-    if (active) {
-        R uph[DIM], upl[DIM];
-        S::load_u(P.u_in, g, P.nsites, uph, upl);
-        const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
-        Mask newmask = mask;
-        const int pa = flag_phase(fp);
-        const bool commit = (MODE != kEval) || P.commit;
-        R F[DIM];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) F[c] = R(0);
-        int rank = 0;
-        // neighbours in groups of kGrp: all loads of a group are issued
-        // unconditionally (from the site itself when the neighbour is outside
-        // the lattice) before any of them is used
-        constexpr int kGrp = 6;
-#pragma unroll
-        for (int d0 = 0; d0 < G::ND; d0 += kGrp) {
-        int qs[kGrp];
-        bool inb[kGrp];
-        uint8_t fqs[kGrp];
-        R uqhs[kGrp][DIM], uqls[kGrp][DIM];
-#pragma unroll
-        for (int t = 0; t < kGrp; ++t) {
-            const int d = d0 + t;
-            const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
-            const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-            inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
-            qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
-            fqs[t] = P.flags[qs[t]];
-            S::load_u(P.u_in, qs[t], P.nsites, uqhs[t], uqls[t]);
-        }
-#pragma unroll
-        for (int t = 0; t < kGrp; ++t) {
-            const int d = d0 + t;
-            if (!inb[t]) continue;
-            const uint8_t fq = fqs[t];
-            if (fq == kVoid) continue;
-            const bool fwd = d < G::NF;
-            const int myrank = rank;
-            if (fwd) ++rank;
-            if (mask & (Mask(1) << d)) continue;
-            const R *uqh = uqhs[t];
-            const R *uql = uqls[t];
-            // lattice vector X0_q - X0_p
-            R e[DIM];
-            double e64[DIM];
-            if constexpr (DIM == 2) {
-                e[0] = R(G::ex(d)) * a;
-                e[1] = R(G::ey(d)) * hy;
-                e64[0] = G::ex(d) * P.a;
-                e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    e[c] = R(G::off(d, c)) * a;
-                    e64[c] = double(G::off(d, c)) * P.a;
-                }
-            }
-            R dv[DIM];
-            R r2 = R(0);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
-                r2 += dv[c] * dv[c];
-            }
-            const int pb = flag_phase(fq);
-            const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
-            const TTy T = tt[ti];
-            bool brk;
-            double margin = 0.0;
-            double d64[DIM];
-            double r64 = 0.0;
-            bool have64 = false;
-            if constexpr (PREC == 1) {
-                // FP32 test; inside the band (or above rc) the FP64 test decides
-                if (r2 > T.z) {
-                    double s2 = 0.0;
-#pragma unroll
-                    for (int c = 0; c < DIM; ++c) {
-                        d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
-                                           (double(uql[c]) - double(upl[c])));
-                        s2 += d64[c] * d64[c];
-                    }
-                    r64 = sqrt(s2);
-                    have64 = true;
-                    const double rc = P.types[ti].rc64;
-                    brk = r64 > rc;
-                    margin = (r64 - rc) / rc;
-                } else {
-                    brk = false;
-                }
-            } else {
-                r64 = sqrt(double(r2));
-                have64 = true;
-                brk = r64 > T.z;
-                if (brk) margin = (r64 - T.z) / T.z;
-            }
-            if (brk) {
-                if (commit) {
-                    newmask |= Mask(1) << d;
-                    if (fwd) {
-                        const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
-                        if (idx < P.ev_cap) {
-                            lsm_event ev;
-                            ev.increment = P.ctl->inc;
-                            ev.step = P.ctl->step_base + step_local;
-                            ev.spring_id = int64_t(P.sbase[g]) + myrank;
-                            ev.margin = margin;
-                            P.events[idx] = ev;
-                        }
-                    }
-                }
-                continue;
-            }
-            if constexpr (PREC == 1) {
-                const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
-                const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, dv[c], F[c]);
-            } else {
-                const double coef = T.x * (r64 - T.y) / r64;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    F[c] += coef * dv[c];
-                    d64[c] = dv[c];
-                }
-            }
-            if constexpr (MODE == kEnd) {
-                if (fwd) {
-                    // virial (Eq. 7) and potential energy (Eq. 1) in FP64
-                    const TypeRec &T64 = P.types[ti];
-                    if (!have64) {
-                        double s2 = 0.0;
-#pragma unroll
-                        for (int c = 0; c < DIM; ++c) {
-                            d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
-                                               (double(uql[c]) - double(upl[c])));
-                            s2 += d64[c] * d64[c];
-                        }
-                        r64 = sqrt(s2);
-                    }
-                    const double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
-#pragma unroll
-                    for (int aa = 0; aa < DIM; ++aa)
-#pragma unroll
-                        for (int bb = 0; bb < DIM; ++bb) red[aa * 3 + bb] += d64[aa] * (coef64 * d64[bb]);
-                    red[18] += 0.5 * T64.k64 * (r64 - T64.r0_64) * (r64 - T64.r0_64);
-                }
-            }
-        }
-        }
-        if (commit && newmask != mask) reinterpret_cast<Mask *>(P.mask)[g] = newmask;
-
-        if constexpr (MODE == kEval) {
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) P.f64[int64_t(g) * DIM + c] = double(F[c]);
-        } else {
-            R w[DIM];
-            if (flag_grip(fp) == 0) S::load_v(P.v, g, P.nsites, w);
-            integrate_site<DIM, PREC, MODE>(P, SiteStore<DIM, PREC>{g, P.nsites}, fp, mass_s[pa], imass_s[pa],
-                                            uph, upl, F, w, red);
-        }
-    }
+    if (active) step_site<DIM, PREC, MODE>(P, tt, mass_s, imass_s, g, i, j, k, fp, red, step_local);
 
     if constexpr (MODE == kEnd) {
         block_sum(red, red_lds);
@@ -603,6 +613,73 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 #pragma unroll
             for (int v = 0; v < kNumPartials; ++v) P.partials[int64_t(blockIdx.x) * kNumPartials + v] = red[v];
         }
+    }
+}
+
+// Interior steps of a small 2D lattice in one launch: one workgroup keeps
+// the whole state in LDS (two displacement buffers, velocities, flags and
+// break bits, in the global layouts) and runs `nsteps` interior steps with
+// a barrier between steps, then writes the state back (displacements to
+// u_out).  Each step runs the gather kernel's per-site code on the LDS
+// copy, so the results are bitwise those of nsteps gather launches; what
+// it saves is a launch per step.
+template <int PREC>
+__global__ __launch_bounds__(kSmallBlock) void k_small_mid(StepParams P, int nsteps, int step_local) {
+    using R = typename State<2, PREC>::R;
+    using TTy = typename TT<PREC>::type;
+    constexpr int VB = 2 * int(sizeof(R));  // velocity record
+    extern __shared__ __attribute__((aligned(16))) char small_lds[];
+    __shared__ TTy tt[kMaxTypes];
+    __shared__ double mass_s[LSM_MAX_PHASES];
+    __shared__ R imass_s[LSM_MAX_PHASES];
+    const int ns = int(P.nsites);
+    char *const uA = small_lds;
+    char *const uB = uA + size_t(ns) * 16;
+    char *const vv = uB + size_t(ns) * 16;
+    uint8_t *const fl = reinterpret_cast<uint8_t *>(vv + size_t(ns) * VB);
+    uint8_t *const mk = fl + ns;
+    for (int t = threadIdx.x; t < kMaxTypes; t += blockDim.x) tt[t] = TT<PREC>::make(P.types[t]);
+    if (threadIdx.x < LSM_MAX_PHASES) {
+        mass_s[threadIdx.x] = P.mass[threadIdx.x];
+        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    }
+    // both displacement buffers start as u_in (void sites are never
+    // written, so either buffer can be the last)
+    for (int g = threadIdx.x; g < ns; g += blockDim.x) {
+        const uint4 u = reinterpret_cast<const uint4 *>(P.u_in)[g];
+        reinterpret_cast<uint4 *>(uA)[g] = u;
+        reinterpret_cast<uint4 *>(uB)[g] = u;
+        if constexpr (VB == 16)
+            reinterpret_cast<uint4 *>(vv)[g] = reinterpret_cast<const uint4 *>(P.v)[g];
+        else
+            reinterpret_cast<uint2 *>(vv)[g] = reinterpret_cast<const uint2 *>(P.v)[g];
+        fl[g] = P.flags[g];
+        mk[g] = reinterpret_cast<const uint8_t *>(P.mask)[g];
+    }
+    __syncthreads();
+    StepParams L = P;
+    L.flags = fl;
+    L.mask = mk;
+    L.v = vv;
+    for (int s = 0; s < nsteps; ++s) {
+        L.u_in = (s & 1) ? uB : uA;
+        L.u_out = (s & 1) ? uA : uB;
+        for (int g = threadIdx.x; g < ns; g += blockDim.x) {
+            const uint8_t fp = fl[g];
+            if (fp == kVoid) continue;
+            double red[1] = {0.0};
+            step_site<2, PREC, kMid>(L, tt, mass_s, imass_s, g, g % P.nx, g / P.nx, 0, fp, red, step_local + s);
+        }
+        __syncthreads();
+    }
+    const char *uf = (nsteps & 1) ? uB : uA;
+    for (int g = threadIdx.x; g < ns; g += blockDim.x) {
+        reinterpret_cast<uint4 *>(P.u_out)[g] = reinterpret_cast<const uint4 *>(uf)[g];
+        if constexpr (VB == 16)
+            reinterpret_cast<uint4 *>(P.v)[g] = reinterpret_cast<const uint4 *>(vv)[g];
+        else
+            reinterpret_cast<uint2 *>(P.v)[g] = reinterpret_cast<const uint2 *>(vv)[g];
+        reinterpret_cast<uint8_t *>(P.mask)[g] = mk[g];
     }
 }
 
@@ -1535,6 +1612,19 @@ hipError_t launch_sweep2d_x2(const StepParams &p, int prec, hipStream_t s, int s
     if (!prec) return hipErrorInvalidValue;  // FP32-compensated lattices only
     if (p.sw_pf >= 2) hipLaunchKernelGGL((k_sweep2d_x2<1, 2>), grid, block, 0, s, p, step_local);
     else hipLaunchKernelGGL((k_sweep2d_x2<1, 1>), grid, block, 0, s, p, step_local);
+    return hipGetLastError();
+}
+
+size_t small_lds_bytes(int64_t nsites, int prec) {
+    return size_t(nsites) * size_t(32 + (prec ? 8 : 16) + 2);
+}
+
+hipError_t launch_small_mid(const StepParams &p, int prec, hipStream_t s, int nsteps, int step_local) {
+    const size_t lds = small_lds_bytes(p.nsites, prec);
+    if (p.nsites <= 0 || lds > kSmallLdsBytes || nsteps < 1) return hipErrorInvalidValue;
+    const int threads = int(std::min<int64_t>(kSmallBlock, (p.nsites + 63) / 64 * 64));
+    if (prec) hipLaunchKernelGGL((k_small_mid<1>), dim3(1), dim3(threads), lds, s, p, nsteps, step_local);
+    else hipLaunchKernelGGL((k_small_mid<0>), dim3(1), dim3(threads), lds, s, p, nsteps, step_local);
     return hipGetLastError();
 }
 

@@ -298,7 +298,7 @@ def test_empty_lattice(lsm):
 
 
 # ------------------------------------------------------- kernel variants
-@pytest.mark.parametrize("variant", ["gather", "sweep"])
+@pytest.mark.parametrize("variant", ["gather", "sweep", "small"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32k"])
 def test_c1_kernel_variants(lsm, variant, precision):
     wl = inputs.WORKLOADS["c1"]
@@ -317,6 +317,33 @@ def test_c1_kernel_variants(lsm, variant, precision):
     rtol, tie = TOL[precision]
     div_inc, k = compare_events(o.events(), g.read_broken(), tie)
     compare_records(ro, rg, rtol, 2, upto_inc=div_inc)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_small_kernel_is_bitwise_the_gather_kernel(lsm, precision):
+    # one workgroup with the state in LDS against per-step gather launches:
+    # the C1 lattice and ragged two-phase lattices (a single row, one
+    # column short of a full wavefront, more sites than threads), odd and
+    # even chunks, fracture in every case; state, masks and events equal
+    wl = dict(inputs.WORKLOADS["c1"], s=[[0.02, NAN], [NAN, 0.08]])
+    cases = [(inputs.c1_image(), 300), (inputs.bernoulli_two_phase(37, 23, 0.4, seed=3), 301),
+             (inputs.bernoulli_two_phase(63, 1, 0.5, seed=4), 200),
+             (inputs.bernoulli_two_phase(36, 30, 0.3, seed=5), 257)]
+    for img, steps in cases:
+        say(f"small vs gather {img.shape} {precision} relax({steps})")
+        out = []
+        for variant in ("gather", "small"):
+            g = gpu_for(lsm, img, wl, precision)
+            g.set_launch(variant)
+            assert g.launch()["variant"] == variant
+            for _ in range(4):
+                g.apply_increment(0.01)
+                g.relax(steps)
+            out.append((g.save_state(), g.read_broken(), g.read_state()))
+        if img.shape[0] > 1:
+            assert len(out[0][1]) > 0, "the case should break springs"
+        assert np.array_equal(out[1][1], out[0][1])
+        assert out[1][0] == out[0][0]
 
 
 @pytest.mark.parametrize("precision", [

@@ -97,6 +97,18 @@ def test_3d_step_bytes_count_the_particle_list():
     assert g64.step_bytes() == g64.n * (2 * (24 + 24) + 1 + 4 + 4)
 
 
+def test_small_kernel_variant_rules():
+    # the one-workgroup kernel: 2D lattices whose state fits its LDS
+    wl = inputs.WORKLOADS["c1"]
+    _model(inputs.c1_image(), wl).set_launch("small")
+    _model(inputs.c1_image(), wl, precision="fp32k").set_launch("small")
+    with pytest.raises(lsm.LsmError):
+        _model(inputs.bernoulli_two_phase(64, 64, 0.3, seed=1), wl).set_launch("small")
+    img3 = inputs.gaussian_random_field_3d(12, seed=3)
+    with pytest.raises(lsm.LsmError):
+        _model(img3, inputs.WORKLOADS["c3"]).set_launch("small")
+
+
 def test_table2_paper_mode_types():
     # explicit interface constants (paper's spring table), r0 = 10
     k = [[2e-5, 1.25e-4], [1.25e-4, 2e-3]]
