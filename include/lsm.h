@@ -246,6 +246,8 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes);
  * and prefetch depth from the bound device's compute units and the
  * kernel's occupancy (wavefronts of nearly equal work filling whole rounds
  * of resident slots).  Results are bitwise independent of rows_per_wave.
+ * LSM_KERNEL_SMALL is LSM_EINVAL for 3D lattices and for built lattices
+ * whose state exceeds its LDS budget.
  * Only between relaxations (LSM_ESTATE otherwise); drops cached graphs.  */
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave);
 
