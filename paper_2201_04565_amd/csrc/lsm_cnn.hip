@@ -58,14 +58,34 @@ union Frag {
 // full-resolution map ever reaching memory (the backward pass recomputes its
 // sign from the image).
 __device__ inline void conv1_patch(const uint8_t *x, int H, int W, int64_t n, int yo, int xo, float v[4][4]) {
+    // sixteen unconditional loads from clamped addresses, zeroed off the
+    // image by a factor (a select would let the compiler put each load
+    // behind a branch that waits for it)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int sy = 2 * yo - 1 + r;
+        const int cy = min(max(sy, 0), H - 1);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int sx = 2 * xo - 1 + c;
-            v[r][c] = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? float(x[(n * H + sy) * W + sx]) : 0.0f;
+            const int cx = min(max(sx, 0), W - 1);
+            const float on = (sy >= 0 && sy < H && sx >= 0 && sx < W) ? 1.0f : 0.0f;
+            v[r][c] = float(x[(n * H + cy) * W + cx]) * on;
         }
+    }
+}
+
+// pooled pixel q -> (x, y, image); 32-bit division where q fits
+__device__ inline void split_pooled(int64_t q, int Wo, int Ho, int &xo, int &yo, int64_t &n) {
+    if (q <= 0x7FFFFFFF) {
+        const uint32_t u = uint32_t(q), t = u / uint32_t(Wo);
+        xo = int(u - t * uint32_t(Wo));
+        yo = int(t % uint32_t(Ho));
+        n = int64_t(t / uint32_t(Ho));
+    } else {
+        xo = int(q % Wo);
+        yo = int((q / Wo) % Ho);
+        n = q / (int64_t(Ho) * Wo);
     }
 }
 
@@ -88,8 +108,9 @@ __global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const
     const int Ho = H / 2, Wo = W / 2;
     const int64_t q = int64_t(blockIdx.x) * kBlk + threadIdx.x;
     if (q >= int64_t(B) * Ho * Wo) return;
-    const int xo = int(q % Wo), yo = int((q / Wo) % Ho);
-    const int64_t n = q / (int64_t(Ho) * Wo);
+    int xo, yo;
+    int64_t n;
+    split_pooled(q, Wo, Ho, xo, yo, n);
     float v[4][4];
     conv1_patch(x, H, W, n, yo, xo, v);
     for (int c0 = 0; c0 < C; c0 += 8) {
@@ -645,8 +666,9 @@ __global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const floa
     for (int64_t q = b0 + lane; q < b1; q += 64) {
         const uint4 gv = *reinterpret_cast<const uint4 *>(dpool + q * C + grp * 8);
         const u16 *gh = reinterpret_cast<const u16 *>(&gv);
-        const int xo = int(q % Wo), yo = int((q / Wo) % Ho);
-        const int64_t n = q / (int64_t(Ho) * Wo);
+        int xo, yo;
+        int64_t n;
+        split_pooled(q, Wo, Ho, xo, yo, n);
         float v[4][4];
         conv1_patch(x, H, W, n, yo, xo, v);
 #pragma unroll
