@@ -624,6 +624,8 @@ __global__ __launch_bounds__(kBlk) void k_sum_splits(const float *partial, float
     if (i >= n) return;
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     int k = 0;
+    // unrolled: sixteen loads in flight, each chain still summed in split order
+#pragma unroll 4
     for (; k + 4 <= splits; k += 4) {
         s0 += partial[int64_t(k) * n + i];
         s1 += partial[int64_t(k + 1) * n + i];
@@ -712,9 +714,18 @@ __global__ __launch_bounds__(kBlk) void k_gap_fwd(const u16 *in, float *out, int
 __global__ __launch_bounds__(kBlk) void k_gap_bwd_relu(const float *dg, const u16 *act, u16 *dact, int B, int HW,
                                                       int C) {
     const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (i >= int64_t(B) * HW * C) return;
-    const int c = int(i % C);
-    const int64_t n = i / (int64_t(HW) * C);
+    const int64_t total = int64_t(B) * HW * C;
+    if (i >= total) return;
+    int c;
+    int64_t n;
+    if (total <= 0x7FFFFFFF) {  // 32-bit division where the index fits
+        const uint32_t u = uint32_t(i);
+        c = int(u % uint32_t(C));
+        n = int64_t(u / uint32_t(HW * C));
+    } else {
+        c = int(i % C);
+        n = i / (int64_t(HW) * C);
+    }
     const float g = dg[n * C + c] / float(HW);
     dact[i] = f2bf(bf2f(act[i]) > 0.0f ? g : 0.0f);
 }
