@@ -120,3 +120,27 @@ def test_batch_derived_against_oracle(lsm):
         assert np.allclose(res["sigma_xx"][s, :k], ro["sigma_xx"][:k], rtol=1e-4)
         # strength within the paper's qualitative agreement band after fracture
         assert res["strength"][s] == pytest.approx(ro["strength"], rel=0.05)
+
+
+def test_c4_stratified_sample_against_oracle(lsm):
+    # the C4 workload (FP32 compensated, 0.5 % x 500 steps, failure rule,
+    # cap 64) on one specimen per side length, against the FP64 oracle's
+    # run to failure: the full protocol for sides 64-128, the first eight
+    # increments for 192 and 256 (the oracle needs about a minute per
+    # 256-side specimen for all 64)
+    wl = inputs.WORKLOADS["c4"]
+    for sides, cap in (((64, 96, 128), wl["max_inc"]), ((192, 256), 8)):
+        imgs = [inputs.circular_inclusions(L, seed=1000 + i) for i, L in enumerate(sides)]
+        say(f"c4 sample sides {sides} fp32k, {cap} increments x {wl['steps']} steps vs oracle")
+        b = lsm.Batch.from_workload(wl, imgs, precision="fp32k")
+        b.run(wl["d_eps"], wl["steps"], cap)
+        res = b.read()
+        prm = Params(k=wl["k"], s=wl["s"], mass=wl["mass"], dt=wl["dt"], gamma=wl["gamma"])
+        for s, img in enumerate(imgs):
+            ro = Net.lattice(img, prm).run_to_failure(wl["d_eps"], wl["steps"], cap)
+            say(f"  side {img.shape[0]}: {ro['n_inc']} increments, modulus {ro['modulus']:.6g}")
+            assert res["modulus"][s] == pytest.approx(ro["modulus"], rel=1e-3)
+            k = max(int(np.argmax(ro["n_broken"] > 0)), 1) if (ro["n_broken"] > 0).any() else ro["n_inc"]
+            peak = np.max(np.abs(ro["sigma_xx"][:ro["n_inc"]]))
+            assert np.allclose(res["sigma_xx"][s, :k], ro["sigma_xx"][:k], rtol=1e-3, atol=1e-3 * peak)
+            assert res["strength"][s] == pytest.approx(ro["strength"], rel=0.05)
