@@ -54,7 +54,9 @@ extern "C" {
 #define LSM_PRED_AFFINE 0     /* free particles follow the strain increment */
 #define LSM_PRED_GRIPS_ONLY 1 /* only the grips move at an increment */
 #define LSM_MAX_PHASES 8
-#define LSM_KERNEL_AUTO 0   /* row sweep for 2D lattices, site gather for 3D */
+#define LSM_KERNEL_AUTO 0   /* 2D: LSM_KERNEL_SMALL where the lattice fits it, else the
+                               two-step (FP32-compensated) or one-step (FP64) row sweep;
+                               3D: the gather kernel */
 #define LSM_KERNEL_GATHER 1 /* one thread per site, all incident springs */
 #define LSM_KERNEL_SWEEP 2  /* 2D: wavefronts sweep rows, forward springs once */
 #define LSM_KERNEL_SWEEP2 3 /* 2D, FP32-compensated: row sweep advancing two interior

@@ -250,17 +250,21 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     return p;
 }
 
-bool use_sweep(const lsm_handle *h) {
-    return h->dim == 2 && (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_SWEEP ||
-                           h->variant == LSM_KERNEL_SWEEP2) &&
-           h->nsites <= lsm::kSweepMaxSites;
-}
-// one workgroup with the state in LDS for the interior steps (as asked for;
-// start and end steps run the gather kernel)
+// one workgroup with the state in LDS for the interior steps (start and end
+// steps run the gather kernel): asked for, or the default for 2D lattices
+// that fit (measured faster than the sweeps and the gather kernel on
+// lattices of 256 to 1,024 sites)
 bool small_fits(const lsm_handle *h) {
     return h->dim == 2 && h->nsites > 0 && lsm::small_lds_bytes(h->nsites, h->prec) <= lsm::kSmallLdsBytes;
 }
-bool use_small(const lsm_handle *h) { return h->variant == LSM_KERNEL_SMALL && small_fits(h); }
+bool use_small(const lsm_handle *h) {
+    return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h);
+}
+bool use_sweep(const lsm_handle *h) {
+    return h->dim == 2 && ((h->variant == LSM_KERNEL_AUTO && !small_fits(h)) || h->variant == LSM_KERNEL_SWEEP ||
+                           h->variant == LSM_KERNEL_SWEEP2) &&
+           h->nsites <= lsm::kSweepMaxSites;
+}
 // interior steps in pairs per launch: the default for 2D FP32-compensated lattices
 bool use_sweep2(const lsm_handle *h) {
     return use_sweep(h) && h->prec && (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
@@ -1167,6 +1171,7 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
         for (int rows : {2, 4, 6, 8, 12, 16, 32})
             for (int pf : {1, 2}) cands.push_back({LSM_KERNEL_SWEEP, rows, pf});
     }
+    if (small_fits(h)) cands.push_back({LSM_KERNEL_SMALL, 0, 1});
     cands.push_back({LSM_KERNEL_GATHER, 0, 1});
     const int saved_variant = h->variant, saved_rows = h->sw_rows, saved_pf = h->sw_pf;
     hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
@@ -1182,10 +1187,14 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
         HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
         int cc = h->cur;
         hipError_t le = hipSuccess;
-        for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s) {
-            StepParams p = make_params(h, cc, cc ^ 1);
-            le = launch_phase(h, p, lsm::kMid, 1 + s);
-            cc ^= 1;
+        if (use_small(h)) {
+            le = launch_mid_steps(h, steps_per_trial, 1, cc);  // one launch for all the steps
+        } else {
+            for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s) {
+                StepParams p = make_params(h, cc, cc ^ 1);
+                le = launch_phase(h, p, lsm::kMid, 1 + s);
+                cc ^= 1;
+            }
         }
         hipGraph_t graph = nullptr;
         hipError_t ce = hipStreamEndCapture(h->stream, &graph);
