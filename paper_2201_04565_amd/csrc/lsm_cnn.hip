@@ -393,7 +393,7 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int co = cw + 16 * c + r16;
-            const float bv = bias[co];
+            const float bv = EPI == kEpiRaw ? 0.0f : bias[co];  // no bias for a raw product
             if constexpr (EPI == kEpiPool) {
                 const int64_t q = (int64_t(n) * (H / 2) + qy) * (W / 2) + qx;
                 float s4 = 0.0f;
@@ -410,7 +410,8 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int y = 2 * qy + (i >> 1), x = 2 * qx + (i & 1);
-                    out[((int64_t(n) * H + y) * W + x) * Cout + co] = f2bf(fmaxf(acc[r][c][i] + bv, 0.0f));
+                    const float v = acc[r][c][i] + bv;
+                    out[((int64_t(n) * H + y) * W + x) * Cout + co] = f2bf(EPI == kEpiRaw ? v : fmaxf(v, 0.0f));
                 }
             }
         }
@@ -1275,6 +1276,12 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                 hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
                                    int(cout), int(cin));
+            else if (cout == 64 && cin % 32 == 0 && H % 16 == 0)
+                // the staged-patch kernel (same K order, same bits): 64-channel
+                // gradient input, 32-channel blocks of the output
+                hipLaunchKernelGGL((k_conv_lds<64, 16, 32, kEpiRaw>), dim3(unsigned(B * (H / 8) * (H / 16)),
+                                   unsigned(cin / 32)), dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
+                                   c->dpool0, nullptr, B, H, H, int(cin));
             else
                 hipLaunchKernelGGL((k_conv_mfma<kEpiRaw, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dpool0, nullptr, nullptr, B, H, H, int(cout),
