@@ -393,8 +393,26 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int co = cw + 16 * c + r16;
-            const float bv = EPI == kEpiRaw ? 0.0f : bias[co];  // no bias for a raw product
-            if constexpr (EPI == kEpiPool) {
+            // input gradients (raw, expand) carry no bias
+            const float bv = (EPI == kEpiRaw || EPI == kEpiExpand) ? 0.0f : bias[co];
+            if constexpr (EPI == kEpiExpand) {
+                // input gradient of a pooled layer: this layer's output grid
+                // is the pooled grid of the one below; each value, times a
+                // quarter, goes to the 2 x 2 pixels whose ReLU was active
+                // (mask_out holds the masks of the layer below, read here)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int y = 2 * qy + (i >> 1), x = 2 * qx + (i & 1);
+                    const int64_t pp = (int64_t(n) * H + y) * W + x;
+                    const u16 h = f2bf(0.25f * bf2f(f2bf(acc[r][c][i])));
+                    const unsigned m = mask_out[pp * Cout + co];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const int64_t o = ((int64_t(n) * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * Cout + co;
+                        out[o] = (m >> d) & 1u ? h : u16(0);
+                    }
+                }
+            } else if constexpr (EPI == kEpiPool) {
                 const int64_t q = (int64_t(n) * (H / 2) + qy) * (W / 2) + qx;
                 float s4 = 0.0f;
                 unsigned m = 0;
@@ -1272,7 +1290,16 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             // epilogue applies the pooling and ReLU of the layer below (the
             // first layer's backward takes the pooled gradient itself)
             const dim3 g2 = conv_grid(npix, int(cin));
-            if (l > 1)
+            const dim3 g16(unsigned(B * (H / 8) * (H / 16)), 1);
+            if (l > 1 && cout == 128 && cin == 64 && H % 16 == 0)
+                // staged-patch kernel (same K order, same bits); the mask
+                // slot carries the masks of the layer below, read
+                hipLaunchKernelGGL((k_conv_lds128<16, 64, kEpiExpand>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
+                                   c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
+            else if (l > 1 && cout == 128 && cin == 128 && H % 16 == 0)
+                hipLaunchKernelGGL((k_conv_lds128<16, 128, kEpiExpand>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
+                                   c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
+            else if (l > 1)
                 hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
                                    int(cout), int(cin));
