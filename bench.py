@@ -326,8 +326,9 @@ def main():
     if args.steps is None:
         args.steps = 198 if args.workload == "c2" else 5
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a single "
+              "lattice would shard as x-slabs with a halo exchange, a batch by specimen)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,7 +10,7 @@ CNNs trained on them, and an uncertainty gate that falls back to the model.
   (std / mean over the members) exceeds the gate is sent to the batched
   model instead, so every accepted answer carries the ensemble's agreement.
 
-The lattice spring model is both the fallback and the judge of the
+The lattice spring model is both the fallback and the reference for the
 surrogate's error (the paper motivates the code by fast data generation
 for machine-learning materials design: Abstract, Section 4).
 """
@@ -177,7 +177,7 @@ def curve_strength(pred: np.ndarray) -> np.ndarray:
 
 def evaluate(sur: Surrogate, images: np.ndarray, lab: Labels, gate: float = 0.05,
              steps: int = 500, d_eps: float = 0.005) -> dict:
-    """Gated pipeline on a test split, judged by the model's own labels.
+    """Gated pipeline on a test split, scored against the model's own labels.
 
     Specimens whose ensemble spread exceeds the gate are re-run on the
     batched model (their answer is the model's, error zero by definition);
