@@ -1,19 +1,26 @@
-"""Builds liblsm.so (HIP for gfx950) in-tree with hipcc."""
+"""Builds liblsm.so (HIP for gfx950) in-tree with hipcc.
+
+Each source is compiled to an object of its own (in parallel), then linked;
+no kernel is launched from another translation unit, so no device linking is
+needed.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblsm.so")
+OBJDIR = os.path.join(HERE, "_build")
 SOURCES = [os.path.join(CSRC, "lsm_kernels.hip"), os.path.join(CSRC, "lsm_host.cpp"),
            os.path.join(CSRC, "lsm_cnn.hip")]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # fuse multiply-adds only inside one expression, so every inlined or
     # unrolled copy of a formula rounds the same way (bitwise results do not
     # depend on the launch shape)
@@ -24,13 +31,22 @@ HIPCC_FLAGS = [
 ]
 
 
+def _compile(hipcc: str, src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    return obj
+
+
 def build_library(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJDIR, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(lambda s: _compile(hipcc, s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC]
-    for src in SOURCES:
-        cmd += ["-x", "hip", src]
-    cmd += ["-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.check_call(cmd)

@@ -32,6 +32,8 @@ constexpr int kMinSweepRows = 2;
 constexpr int kMaxSweepRows = 4096;
 constexpr uint32_t kStateMagic = 0x4C534D31u;
 constexpr double kHalfSqrt3 = 0.86602540378443864676;
+// lsm_autotune is withheld (see there) while this is false
+constexpr bool kSingleLatticeTunerEnabled = false;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -1150,6 +1152,33 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     return LSM_OK;
 }
 
+// Candidate trials of the single-lattice tuner.  Every exit path restores
+// the checkpointed dynamics and the saved launch (unless a best candidate was
+// chosen), drops the trial graph and returns the events to the pool.
+namespace {
+struct TuneGuard {
+    lsm_handle *h;
+    std::vector<char> snap;
+    int variant, rows, pf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool keep_launch = false;
+    ~TuneGuard() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (e0) h->ev_pool.push_back(e0);
+        if (e1) h->ev_pool.push_back(e1);
+        for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+        h->graphs.clear();
+        if (!keep_launch) {
+            h->variant = variant;
+            h->sw_rows = rows;
+            h->sw_pf = pf;
+        }
+        if (!snap.empty()) (void)lsm_load_state(h, snap.data(), snap.size());
+    }
+};
+}  // namespace
+
 int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int cap, int *n_results) {
     int rc = check_bound(h);
     if (rc) return rc;
@@ -1157,62 +1186,67 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
         return fail(h, LSM_EINVAL, "steps_per_trial must be even, 2..1000");
     if (h->half) return fail(h, LSM_ESTATE, "autotune only between relaxations");
     if (cap < 0 || (cap > 0 && !results)) return LSM_EINVAL;
+    // Withheld: one GPU run of an earlier version of this tuner stopped
+    // producing output for 180 s and no cause has been shown; until one is,
+    // the call only reports that it is unavailable (the default launch of
+    // every lattice comes from the occupancy model and needs no trials).
+    if (!kSingleLatticeTunerEnabled)
+        return fail(h, LSM_ESTATE, "the single-lattice autotuner is withheld until the cause of a GPU stall "
+                                   "in its trials is found; the default launch needs no tuning");
+    TuneGuard g{h, {}, h->variant, h->sw_rows, h->sw_pf};
     // the trials advance the dynamics: checkpoint the state and restore it
-    // afterwards, so tuning never changes results
+    // afterwards (the guard), so tuning never changes results
     size_t snap_n = 0;
     rc = lsm_save_state(h, nullptr, &snap_n);
     if (rc) return rc;
     std::vector<char> snap(snap_n);
     rc = lsm_save_state(h, snap.data(), &snap_n);
     if (rc) return rc;
+    g.snap.swap(snap);
     struct Cand { int variant, rows, pf; };
     std::vector<Cand> cands;
-    if (h->dim == 2) {
-        for (int rows : {2, 4, 6, 8, 12, 16, 32})
-            for (int pf : {1, 2}) cands.push_back({LSM_KERNEL_SWEEP, rows, pf});
+    if (h->dim == 2 && h->nsites <= lsm::kSweepMaxSites) {
+        for (int rows : {4, 8, 12, 16, 18, 24, 32})
+            for (int pf : {1, 2}) {
+                if (h->prec) cands.push_back({LSM_KERNEL_SWEEP2, rows, pf});
+                cands.push_back({LSM_KERNEL_SWEEP, rows, pf});
+            }
     }
     if (small_fits(h)) cands.push_back({LSM_KERNEL_SMALL, 0, 1});
     cands.push_back({LSM_KERNEL_GATHER, 0, 1});
-    const int saved_variant = h->variant, saved_rows = h->sw_rows, saved_pf = h->sw_pf;
-    hipEvent_t e0 = pool_event(h), e1 = pool_event(h);
-    if (!e0 || !e1) return fail(h, LSM_EHIP, "hipEventCreate failed");
+    g.e0 = pool_event(h);
+    g.e1 = pool_event(h);
+    if (!g.e0 || !g.e1) return fail(h, LSM_EHIP, "hipEventCreate failed");
     double best = 1e300;
-    Cand bestc = {saved_variant, saved_rows, saved_pf};
+    Cand bestc = {g.variant, g.rows, g.pf};
     int nres = 0;
     for (const Cand &c : cands) {
         h->variant = c.variant;
         if (c.rows) h->sw_rows = c.rows;
         h->sw_pf = c.pf;
-        hipGraphExec_t exec = nullptr;
         HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        int cc = h->cur;
-        hipError_t le = hipSuccess;
-        if (use_small(h)) {
-            le = launch_mid_steps(h, steps_per_trial, 1, cc);  // one launch for all the steps
-        } else {
-            for (int s = 0; s < steps_per_trial && le == hipSuccess; ++s) {
-                StepParams p = make_params(h, cc, cc ^ 1);
-                le = launch_phase(h, p, lsm::kMid, 1 + s);
-                cc ^= 1;
-            }
-        }
+        const hipError_t le = launch_mid_steps(h, steps_per_trial, 1, h->cur);
         hipGraph_t graph = nullptr;
-        hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+        const hipError_t ce = hipStreamEndCapture(h->stream, &graph);
         if (le != hipSuccess || ce != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
             return fail(h, LSM_EHIP, "autotune capture failed");
         }
-        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
-        if (ie != hipSuccess) return fail(h, LSM_EHIP, "autotune instantiate failed");
-        HIPCHK(h, hipGraphLaunch(exec, h->stream));  // warm-up
-        HIPCHK(h, hipEventRecord(e0, h->stream));
-        HIPCHK(h, hipGraphLaunch(exec, h->stream));
-        HIPCHK(h, hipEventRecord(e1, h->stream));
+        if (ie != hipSuccess) {
+            g.exec = nullptr;
+            return fail(h, LSM_EHIP, "autotune instantiate failed");
+        }
+        HIPCHK(h, hipGraphLaunch(g.exec, h->stream));  // warm-up
+        HIPCHK(h, hipEventRecord(g.e0, h->stream));
+        HIPCHK(h, hipGraphLaunch(g.exec, h->stream));
+        HIPCHK(h, hipEventRecord(g.e1, h->stream));
         HIPCHK(h, hipStreamSynchronize(h->stream));
         float ms = 0.0f;
-        HIPCHK(h, hipEventElapsedTime(&ms, e0, e1));
-        (void)hipGraphExecDestroy(exec);
+        HIPCHK(h, hipEventElapsedTime(&ms, g.e0, g.e1));
+        (void)hipGraphExecDestroy(g.exec);
+        g.exec = nullptr;
         const double us = 1e3 * ms / steps_per_trial;
         if (nres < cap) results[nres] = lsm_tuning{c.variant, c.rows, c.pf, 0, us};
         ++nres;
@@ -1221,17 +1255,14 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
             bestc = c;
         }
     }
-    h->ev_pool.push_back(e0);
-    h->ev_pool.push_back(e1);
-    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
-    h->graphs.clear();
     h->variant = bestc.variant;
     if (bestc.rows) h->sw_rows = bestc.rows;
     h->sw_pf = bestc.pf;
-    (void)saved_rows;
-    (void)saved_pf;
+    g.keep_launch = true;
     if (n_results) *n_results = nres;
-    return lsm_load_state(h, snap.data(), snap_n);
+    std::vector<char> done;
+    done.swap(g.snap);  // restored here, so its status is returned
+    return lsm_load_state(h, done.data(), done.size());
 }
 
 int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
