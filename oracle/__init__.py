@@ -55,6 +55,7 @@ def lib():
         L.orc_lattice.argtypes = [C.c_int, vp, i64, i64, i64, dbl, C.c_int, vp, vp, dbl, dbl,
                                   vp, C.c_int]
         L.orc_set_dynamics.argtypes = [vp, dbl, dbl, C.c_int]
+        L.orc_set_strain_rate.argtypes = [vp, dbl]
         L.orc_apply_increment.argtypes = [vp, dbl]
         L.orc_relax.argtypes = [vp, i64]
         L.orc_record_state.argtypes = [vp, P(Record)]
@@ -158,6 +159,23 @@ class Net:
     # --- dynamics ------------------------------------------------------
     def set_dynamics(self, dt, gamma, predictor=0):
         lib().orc_set_dynamics(self._h, float(dt), float(gamma), int(predictor))
+
+    def set_strain_rate(self, rate):
+        """Constant strain-rate loading (per unit time) from the next step."""
+        lib().orc_set_strain_rate(self._h, float(rate))
+
+    def run_rate(self, rate, nsteps, every):
+        """The paper's protocol: grips at a constant strain rate for nsteps,
+        a record (strain, stress, energies) every `every` steps."""
+        self.set_strain_rate(rate)
+        out = []
+        done = 0
+        while done < nsteps:
+            n = min(every, nsteps - done)
+            self.relax(n)
+            done += n
+            out.append(self.record())
+        return out
 
     def apply_increment(self, d_eps):
         rc = lib().orc_apply_increment(self._h, float(d_eps))

@@ -80,6 +80,10 @@ typedef struct orc_net {
     double dt, gamma;
     int predictor; /* 0 affine, 1 grips only */
     double eps;
+    /* constant strain-rate loading: grips at eps0 + s (rate dt) at the s-th
+       step since the rate was set or the last increment */
+    double rate, rate_eps0;
+    int64_t rate_steps;
     int32_t inc, step;
     orc_event *ev;
     int64_t nev, evcap;
@@ -385,6 +389,8 @@ int orc_apply_increment(orc_net *N, double d_eps)
     N->inc += 1;
     N->step = 0;
     N->eps += d_eps;
+    N->rate_eps0 = N->eps;
+    N->rate_steps = 0;
     for (int64_t p = 0; p < N->n; ++p) {
         if (N->grip[p]) {
             N->x[p * dim + 0] = N->X0[p * dim + 0] + N->eps * N->c[p];
@@ -400,15 +406,44 @@ int orc_apply_increment(orc_net *N, double d_eps)
     return ORC_OK;
 }
 
+/* Constant strain-rate loading, the paper's protocol (Section 3.1: the
+ * boundary particles move apart along x at a fixed strain rate; Section 2.3:
+ * the boundary displacement is the first operation of every time step).
+ * rate is per unit time.  From the next step on, the s-th step since this
+ * call (or since the last increment) first places the grips at
+ * X0_x + (eps0 + s (rate dt)) c, eps0 being the strain at that point; rate
+ * 0 stops them.  Free particles are only moved by the integrator. */
+void orc_set_strain_rate(orc_net *N, double rate)
+{
+    N->rate = rate;
+    N->rate_eps0 = N->eps;
+    N->rate_steps = 0;
+}
+
+/* grips to the strain of the next step of the constant-rate protocol */
+static void move_grips(orc_net *N)
+{
+    const int dim = N->dim;
+    N->rate_steps += 1;
+    N->eps = N->rate_eps0 + (double)N->rate_steps * (N->rate * N->dt);
+    for (int64_t p = 0; p < N->n; ++p) {
+        if (!N->grip[p]) continue;
+        N->x[p * dim + 0] = N->X0[p * dim + 0] + N->eps * N->c[p];
+        for (int e = 1; e < dim; ++e) N->x[p * dim + e] = N->X0[p * dim + e];
+    }
+}
+
 /* nsteps of velocity Verlet in the half-step form (Eq. 3-5, Section 2.2):
- * v += dt/2 a; x += dt v; F(x) with the break test; a = (F - gamma v)/m;
- * v += dt/2 a.  Grips are not integrated. */
+ * (grips moved first under constant-rate loading) v += dt/2 a; x += dt v;
+ * F(x) with the break test; a = (F - gamma v)/m; v += dt/2 a.  Grips are
+ * not integrated. */
 int orc_relax(orc_net *N, int64_t nsteps)
 {
     const int dim = N->dim;
     const double h = 0.5 * N->dt;
     for (int64_t it = 0; it < nsteps; ++it) {
         N->step += 1;
+        if (N->rate != 0.0) move_grips(N);
         for (int64_t p = 0; p < N->n; ++p) {
             if (N->grip[p]) continue;
             for (int e = 0; e < dim; ++e) {
