@@ -185,6 +185,30 @@ int lsm_apply_strain_increment(lsm_handle *h, double d_eps);
  * energies).  Launched as HIP graphs of the step kernel.                  */
 int lsm_relax(lsm_handle *h, int64_t nsteps);
 
+/* Constant strain-rate loading, the paper's protocol (Section 3.1: the
+ * boundary particles are displaced apart along x at a fixed strain rate;
+ * Section 2.3: the boundary displacement is the first operation of every
+ * time step).  rate is per unit time (the paper's 1e-6 with its dt = 1).
+ * From the next step on, step S of the increment first places the grips at
+ * X0_x + eps_S i a, eps_S = eps0 + (S - S0) (rate dt), where eps0 is the
+ * strain at this call (step S0) or at the next lsm_apply_strain_increment
+ * (S0 = 0), which continues at the same rate from its new strain; free
+ * particles move only by integration.  The record's eps is eps_S of its
+ * last step.  rate = 0 stops the grips.  While a rate is set the interior
+ * steps run one step per launch (the two-step sweep and the one-workgroup
+ * kernel are not used).  Bound handles only; synchronises.  LSM_EINVAL
+ * for a non-finite rate.                                                   */
+int lsm_set_strain_rate(lsm_handle *h, double rate);
+
+/* lsm_relax in chunks of `every` steps (the last may be shorter) with a
+ * record after each chunk -- the paper's periodic callbacks that report the
+ * potential and kinetic energies (Section 2.3) -- written to out[0 ..
+ * cap-1] (host); *n (may be NULL) receives the number written.  A chunk
+ * ending on a non-finite state stops the run with LSM_EUNSTABLE (its record
+ * is written).  Synchronises after every chunk.                            */
+int lsm_relax_trace(lsm_handle *h, int64_t nsteps, int64_t every, lsm_record *out, int64_t cap,
+                    int64_t *n);
+
 /* Synchronises the stream and copies the record of the last relaxation.
  * Returns LSM_EUNSTABLE (with *out filled) if the state was not finite.   */
 int lsm_read_state(lsm_handle *h, lsm_record *out);
@@ -394,6 +418,28 @@ int lsm_cnn_mse(lsm_cnn *c, const float *target, float *dy, float *loss);
  * the one from lsm_cnn_mse); overwrites the gradient vector               */
 int lsm_cnn_backward(lsm_cnn *c, const float *dy);
 int lsm_cnn_adam_step(lsm_cnn *c, float lr, float beta1, float beta2, float eps, int64_t t);
+/* Test hook: copies one internal buffer of the last forward / backward pass
+ * to host memory (synchronises), so each kernel can be checked on its own
+ * inputs.  layer counts conv layers from 0; sizes are for the configured
+ * batch (the first `batch` images of the last call are meaningful) and H_l
+ * is the side of conv layer l's input (H_0 = height, halved after each
+ * pooled layer).  host == NULL returns the size in *bytes; otherwise *bytes
+ * is the host capacity (LSM_ENOMEM if short) and receives the size copied.
+ * LSM_EINVAL for a buffer or layer that does not exist.                   */
+#define LSM_CNN_BUF_POOLED 0  /* l = 0..3: pooled ReLU output, BF16 [B][H_l/2][H_l/2][C_l] */
+#define LSM_CNN_BUF_MASK 1    /* l = 1..3: ReLU signs of the four pixels under each pooled
+                                 pixel, bit d = (d / 2, d mod 2), uint8 [B][H_l/2][H_l/2][C_l] */
+#define LSM_CNN_BUF_ACT 2     /* last conv output after ReLU, BF16 [B][H_4][H_4][C_4] */
+#define LSM_CNN_BUF_DACT 3    /* l = 1..4: gradient of conv output l (after the ReLU
+                                 mask), BF16 [B][H_l][H_l][C_l] */
+#define LSM_CNN_BUF_DPOOL0 4  /* gradient of the first pooled map, BF16 [B][H_0/2][H_0/2][C_0] */
+#define LSM_CNN_BUF_GAP 5     /* global average pool, FP32 [B][C_4] */
+#define LSM_CNN_BUF_DGAP 6    /* its gradient */
+#define LSM_CNN_BUF_HIDDEN 7  /* dense layer 1 after ReLU, FP32 [B][hidden] */
+#define LSM_CNN_BUF_DHIDDEN 8 /* its gradient (after the ReLU mask) */
+#define LSM_CNN_BUF_OUT 9     /* network output, FP32 [B][outputs] */
+#define LSM_CNN_BUF_DOUT 10   /* output gradient of lsm_cnn_mse or lsm_cnn_backward */
+int lsm_cnn_read_buffer(lsm_cnn *c, int buffer, int layer, void *host, size_t *bytes);
 /* one implicit-GEMM convolution (layers 1..4, bias + ReLU) on device BF16
  * NHWC buffers with this network's weights (kernel tests)                 */
 int lsm_cnn_conv_forward(lsm_cnn *c, int layer, const void *in, void *out, int64_t batch);

@@ -16,8 +16,15 @@ CNN_EXPORTS = (
     "lsm_cnn_create", "lsm_cnn_destroy", "lsm_cnn_last_error", "lsm_cnn_param_count",
     "lsm_cnn_layout", "lsm_cnn_workspace_bytes", "lsm_cnn_bind", "lsm_cnn_set_params",
     "lsm_cnn_get_params", "lsm_cnn_get_grads", "lsm_cnn_forward", "lsm_cnn_mse",
-    "lsm_cnn_backward", "lsm_cnn_adam_step", "lsm_cnn_conv_forward",
+    "lsm_cnn_backward", "lsm_cnn_adam_step", "lsm_cnn_conv_forward", "lsm_cnn_read_buffer",
 )
+
+# internal buffers readable by Network.buffer (LSM_CNN_BUF_* of lsm.h):
+# name -> (id, element type, BF16 stored as uint16)
+BUFFERS = {"pooled": (0, np.uint16), "mask": (1, np.uint8), "act": (2, np.uint16),
+           "dact": (3, np.uint16), "dpool0": (4, np.uint16), "gap": (5, np.float32),
+           "dgap": (6, np.float32), "hidden": (7, np.float32), "dhidden": (8, np.float32),
+           "out": (9, np.float32), "dout": (10, np.float32)}
 
 DEFAULT_CHANNELS = (32, 64, 128, 128, 256)
 
@@ -49,6 +56,7 @@ def _load():
     L.lsm_cnn_backward.argtypes = [vp, vp]
     L.lsm_cnn_adam_step.argtypes = [vp, fl, fl, fl, fl, i64]
     L.lsm_cnn_conv_forward.argtypes = [vp, C.c_int, vp, vp, i64]
+    L.lsm_cnn_read_buffer.argtypes = [vp, C.c_int, C.c_int, vp, P(C.c_size_t)]
     L._cnn_ready = True
     return L
 
@@ -193,6 +201,19 @@ class Network:
         self._check(self._L.lsm_cnn_conv_forward(self._h, int(layer), _dptr(x_bf16),
                                                  _dptr(out_bf16), B))
         self._leave(x_bf16, out_bf16)
+
+    def buffer(self, name, layer=0):
+        """Copy of an internal buffer of the last pass (flat array over the
+        configured batch; BF16 buffers are returned as FP32 values)."""
+        bid, dt = BUFFERS[name]
+        n = C.c_size_t()
+        self._check(self._L.lsm_cnn_read_buffer(self._h, bid, int(layer), None, C.byref(n)))
+        out = np.zeros(n.value // np.dtype(dt).itemsize, dt)
+        self._check(self._L.lsm_cnn_read_buffer(self._h, bid, int(layer),
+                                                out.ctypes.data_as(C.c_void_p), C.byref(n)))
+        if dt == np.uint16:
+            return (out.astype(np.uint32) << 16).view(np.float32)
+        return out
 
     def synchronize(self):
         self.stream.synchronize()

@@ -1351,6 +1351,52 @@ int lsm_cnn_layout(const lsm_cnn *c, int64_t *w_off, int64_t *b_off, int64_t *w_
     return LSM_OK;
 }
 
+int lsm_cnn_read_buffer(lsm_cnn *c, int buffer, int layer, void *host, size_t *bytes) {
+    if (!c || !bytes) return LSM_EINVAL;
+    if (!c->bound) return cfail(c, LSM_ESTATE, "bind first");
+    const int64_t B = c->cfg.batch;
+    const int L = kLayers - 1;
+    const void *src = nullptr;
+    size_t n = 0;
+    const bool lok = layer >= 0 && layer < kLayers;
+    const int64_t hw = lok ? int64_t(c->Hs[layer]) * c->Hs[layer] : 0;
+    const int64_t ch = lok ? c->C[layer + 1] : 0;
+    switch (buffer) {
+    case LSM_CNN_BUF_POOLED:
+        if (lok && layer < L) src = c->pool[layer], n = size_t(B * hw / 4 * ch) * 2;
+        break;
+    case LSM_CNN_BUF_MASK:
+        if (lok && layer > 0 && layer < L) src = c->mask[layer], n = size_t(B * hw / 4 * ch);
+        break;
+    case LSM_CNN_BUF_ACT:
+        src = c->act, n = size_t(B * c->Hs[L] * c->Hs[L] * c->C[L + 1]) * 2;
+        break;
+    case LSM_CNN_BUF_DACT:
+        if (lok && layer > 0) src = c->dact[layer], n = size_t(B * hw * ch) * 2;
+        break;
+    case LSM_CNN_BUF_DPOOL0:
+        src = c->dpool0, n = size_t(B * c->Hs[0] * c->Hs[0] / 4 * c->C[1]) * 2;
+        break;
+    case LSM_CNN_BUF_GAP: src = c->gap, n = size_t(B) * c->C[kLayers] * 4; break;
+    case LSM_CNN_BUF_DGAP: src = c->dgap, n = size_t(B) * c->C[kLayers] * 4; break;
+    case LSM_CNN_BUF_HIDDEN: src = c->h1, n = size_t(B) * c->cfg.hidden * 4; break;
+    case LSM_CNN_BUF_DHIDDEN: src = c->dh1, n = size_t(B) * c->cfg.hidden * 4; break;
+    case LSM_CNN_BUF_OUT: src = c->y, n = size_t(B) * c->cfg.outputs * 4; break;
+    case LSM_CNN_BUF_DOUT: src = c->dy, n = size_t(B) * c->cfg.outputs * 4; break;
+    default: break;
+    }
+    if (!src) return cfail(c, LSM_EINVAL, "no such buffer");
+    if (!host) {
+        *bytes = n;
+        return LSM_OK;
+    }
+    if (*bytes < n) return cfail(c, LSM_ENOMEM, "host buffer too small");
+    CHIP(c, hipMemcpyAsync(host, src, n, hipMemcpyDeviceToHost, c->stream));
+    CHIP(c, hipStreamSynchronize(c->stream));
+    *bytes = n;
+    return LSM_OK;
+}
+
 int lsm_cnn_conv_forward(lsm_cnn *c, int layer, const void *in, void *out, int64_t batch) {
     // single layer of the implicit-GEMM convolution (layers 1..4) on caller
     // buffers, with this network's weights: used to test the kernel alone

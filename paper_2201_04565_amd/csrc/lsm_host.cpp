@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -83,6 +84,10 @@ struct lsm_handle {
     bool half = false;  // velocities are half-step (between an increment and the end of a relax)
     int32_t inc = 0, step = 0;
     double eps = 0.0;
+    // constant strain-rate loading (0: off): the strain was rate_eps0 at step
+    // rate_s0 of the increment and advances rate * dt per step
+    double rate = 0.0, rate_eps0 = 0.0;
+    int32_t rate_s0 = 0;
     std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;
     // the two-step sweep reads velocities and break bits from d_V / d_mask
     // and writes them to these; the pointers swap after each such launch
@@ -259,8 +264,9 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
 bool small_fits(const lsm_handle *h) {
     return h->dim == 2 && h->nsites > 0 && lsm::small_lds_bytes(h->nsites, h->prec) <= lsm::kSmallLdsBytes;
 }
+// (not under constant-rate loading, which moves the grips before every step)
 bool use_small(const lsm_handle *h) {
-    return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h);
+    return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h) && h->rate == 0.0;
 }
 bool use_sweep(const lsm_handle *h) {
     return h->dim == 2 && ((h->variant == LSM_KERNEL_AUTO && !small_fits(h)) || h->variant == LSM_KERNEL_SWEEP ||
@@ -268,8 +274,10 @@ bool use_sweep(const lsm_handle *h) {
            h->nsites <= lsm::kSweepMaxSites;
 }
 // interior steps in pairs per launch: the default for 2D FP32-compensated lattices
+// (not under constant-rate loading: the grips move between the two steps)
 bool use_sweep2(const lsm_handle *h) {
-    return use_sweep(h) && h->prec && (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO);
+    return use_sweep(h) && h->prec && (h->variant == LSM_KERNEL_SWEEP2 || h->variant == LSM_KERNEL_AUTO) &&
+           h->rate == 0.0;
 }
 // Default rows per wavefront of the 2D sweep.  The sweep's wavefronts all
 // carry about the same work, (R + 1) row evaluations for the one-step
@@ -343,6 +351,10 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         p.mask = mc;
         p.v_out = va;
         p.mask_out = ma;
+        if (h->rate != 0.0) {
+            le = lsm::launch_grips(p, h->dim, h->prec, h->stream, local + s);
+            if (le != hipSuccess) break;
+        }
         if (use_sweep2(h) && s + 1 < chunk) {
             le = lsm::launch_sweep2d_x2(p, h->prec, h->stream, local + s);
             std::swap(vc, va);
@@ -426,6 +438,18 @@ int run_mid_chunk(lsm_handle *h, int chunk, int local) {
         h->vm ^= 1;
     }
     return LSM_OK;
+}
+
+// Strain at step `step` of the increment under constant-rate loading, as
+// the grip kernel computes it (product and sum rounded separately).
+double rate_strain(const lsm_handle *h, int32_t step) {
+    const double prod = double(step - h->rate_s0) * (h->rate * h->cfg.dt);
+    return h->rate_eps0 + prod;
+}
+
+void drop_graphs(lsm_handle *h) {
+    for (auto &kv : h->graphs) (void)hipGraphExecDestroy(kv.second);
+    h->graphs.clear();
 }
 
 int check_bound(lsm_handle *h) {
@@ -694,6 +718,8 @@ int lsm_apply_strain_increment(lsm_handle *h, double d_eps) {
     h->inc += 1;
     h->eps = eps_new;
     h->step = 0;
+    h->rate_eps0 = eps_new;
+    h->rate_s0 = 0;
     return LSM_OK;
 }
 
@@ -716,10 +742,52 @@ int lsm_relax(lsm_handle *h, int64_t nsteps) {
         local += chunk;
     }
     StepParams p = make_params(h, h->cur, h->cur);
+    if (h->rate != 0.0) HIPCHK(h, lsm::launch_grips(p, h->dim, h->prec, h->stream, int(nsteps)));
     HIPCHK(h, launch_phase(h, p, lsm::kEnd, int(nsteps)));
     HIPCHK(h, lsm::launch_finalize(p, h->dim, h->stream, h->d_rec, h->omega, int(nsteps)));
     h->half = false;
     h->step += int32_t(nsteps);
+    if (h->rate != 0.0) h->eps = rate_strain(h, h->step);
+    return LSM_OK;
+}
+
+int lsm_set_strain_rate(lsm_handle *h, double rate) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!std::isfinite(rate)) return fail(h, LSM_EINVAL, "strain rate must be finite");
+    if ((rate != 0.0) != (h->rate != 0.0)) drop_graphs(h);  // a grip launch joins every step
+    h->rate = rate;
+    h->rate_eps0 = h->eps;
+    h->rate_s0 = h->step;
+    Ctl c{};
+    c.rate_s0 = h->rate_s0;
+    c.rate_eps0 = h->rate_eps0;
+    c.rate_de = rate * h->cfg.dt;
+    // only the rate fields of the loop control: rate_s0 .. rate_de
+    const size_t o = offsetof(Ctl, rate_s0);
+    HIPCHK(h, hipMemcpyAsync(reinterpret_cast<char *>(h->d_ctl) + o, reinterpret_cast<const char *>(&c) + o,
+                             sizeof(Ctl) - o, hipMemcpyHostToDevice, h->stream));
+    return sync(h);
+}
+
+int lsm_relax_trace(lsm_handle *h, int64_t nsteps, int64_t every, lsm_record *out, int64_t cap, int64_t *n) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (nsteps < 1 || every < 1 || cap < 0 || (cap > 0 && !out)) return fail(h, LSM_EINVAL, "bad trace arguments");
+    int64_t done = 0, k = 0;
+    if (n) *n = 0;
+    while (done < nsteps) {
+        const int64_t chunk = std::min(every, nsteps - done);
+        rc = lsm_relax(h, chunk);
+        if (rc) return rc;
+        done += chunk;
+        lsm_record r;
+        rc = lsm_read_state(h, &r);
+        if (k < cap) out[k] = r;
+        ++k;
+        if (n) *n = std::min(k, cap);
+        if (rc) return rc;
+    }
     return LSM_OK;
 }
 
@@ -1005,8 +1073,8 @@ int lsm_eval_forces(lsm_handle *h, double *f, int commit_breaks) {
 struct StateHeader {
     uint32_t magic, version;
     int64_t nsites, m;
-    int32_t dim, prec, half, inc, step, pad;
-    double eps;
+    int32_t dim, prec, half, inc, step, rate_s0;
+    double eps, rate, rate_eps0;
 };
 
 static size_t state_size(const lsm_handle *h, uint32_t nev) {
@@ -1032,7 +1100,8 @@ int lsm_save_state(lsm_handle *h, void *buf, size_t *n) {
     if (*n < need) return fail(h, LSM_ENOMEM, "checkpoint buffer too small");
     const size_t ns = size_t(h->nsites);
     char *o = static_cast<char *>(buf);
-    StateHeader hd{kStateMagic, 1, h->nsites, h->m, h->dim, h->prec, h->half ? 1 : 0, h->inc, h->step, 0, h->eps};
+    StateHeader hd{kStateMagic, 2,      h->nsites, h->m,   h->dim,  h->prec,       h->half ? 1 : 0,
+                   h->inc,      h->step, h->rate_s0, h->eps, h->rate, h->rate_eps0};
     std::memcpy(o, &hd, sizeof(hd));
     o += sizeof(hd);
     HIPCHK(h, hipMemcpyAsync(o, h->d_U[h->cur], ns * h->ub, hipMemcpyDeviceToHost, h->stream)); o += ns * h->ub;
@@ -1058,7 +1127,7 @@ int lsm_load_state(lsm_handle *h, const void *buf, size_t n) {
     if (!buf || n < sizeof(StateHeader)) return LSM_EINVAL;
     StateHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != kStateMagic || hd.version != 1 || hd.nsites != h->nsites || hd.m != h->m ||
+    if (hd.magic != kStateMagic || hd.version != 2 || hd.nsites != h->nsites || hd.m != h->m ||
         hd.dim != h->dim || hd.prec != h->prec)
         return fail(h, LSM_EINVAL, "checkpoint does not match this lattice");
     const char *o = static_cast<const char *>(buf) + sizeof(hd);
@@ -1083,6 +1152,10 @@ int lsm_load_state(lsm_handle *h, const void *buf, size_t n) {
     h->inc = hd.inc;
     h->step = hd.step;
     h->eps = hd.eps;
+    if ((hd.rate != 0.0) != (h->rate != 0.0)) drop_graphs(h);
+    h->rate = hd.rate;
+    h->rate_eps0 = hd.rate_eps0;
+    h->rate_s0 = hd.rate_s0;
     h->ev_cached = 0xFFFFFFFFu;
     return LSM_OK;
 }

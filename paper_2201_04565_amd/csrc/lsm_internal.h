@@ -39,7 +39,9 @@ struct Ctl {
     int32_t inc;
     int32_t step_base;  // steps already done inside the current increment
     uint32_t n_events;
-    int32_t pad;
+    int32_t rate_s0;    // constant-rate loading: step inside the increment at which
+    double rate_eps0;   // the strain was rate_eps0, advancing rate_de per step
+    double rate_de;
 };
 
 // Device record (same layout as lsm_record).
@@ -134,6 +136,10 @@ int sweep_waves_per_cu(int two_step, int prec, int pf);
 hipError_t launch_sweep2d_x2_batch(const StepParams &p, int prec, hipStream_t stream, int step_local,
                                    int capacity2);
 hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
+// Constant-rate loading: places the grips of u_in at the strain of step
+// step_local of the increment (rate fields of the loop control) and records
+// that strain; launched before every step kernel while a rate is set.
+hipError_t launch_grips(const StepParams &p, int dim, int prec, hipStream_t stream, int step_local);
 // Batch versions: the grid covers `capacity` work items; items beyond
 // *p.n_items exit at once.
 hipError_t launch_sweep2d_batch(const StepParams &p, int prec, int mode, hipStream_t stream,

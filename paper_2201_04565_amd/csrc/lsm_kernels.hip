@@ -694,6 +694,9 @@ __global__ __launch_bounds__(256) void k_increment(StepParams P, double eps_new,
         P.ctl->eps = eps_new;
         P.ctl->inc = inc;
         P.ctl->step_base = 0;
+        // a constant loading rate continues from the new strain
+        P.ctl->rate_eps0 = eps_new;
+        P.ctl->rate_s0 = 0;
     }
     if (g >= P.nsites) return;
     const uint8_t f = P.flags[g];
@@ -747,6 +750,36 @@ __global__ __launch_bounds__(256) void k_kick_drift(StepParams P) {
     }
     S::store_u(P.u_in, int(g), P.nsites, hi, lo);
     S::store_v(P.v, int(g), P.nsites, w);
+}
+
+// ------------------------------------------- constant-rate grip motion
+// The paper's loading (Section 3.1: the boundary particles move apart along
+// x at a constant strain rate; Section 2.3: the boundary displacement is the
+// first operation of every time step).  Step S of the increment sees the
+// grips at X0_x + eps_S i a with eps_S = eps0 + (S - S0) (rate dt), where
+// eps0 was the strain at step S0 (the rate was set, or the increment
+// began); the product and the sum are rounded separately, as written.  One
+// thread per grip-column site (first and last column of every row).
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k_grips(StepParams P, int step_local) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int steps = P.ctl->step_base + step_local - P.ctl->rate_s0;
+    const double eps = __dadd_rn(P.ctl->rate_eps0, __dmul_rn(double(steps), P.ctl->rate_de));
+    if (t == 0) P.ctl->eps = eps;
+    if (t >= 2 * int64_t(P.ny) * P.nz) return;
+    const int i = (t & 1) ? P.nx - 1 : 0;
+    const int64_t g = i + int64_t(P.nx) * (t >> 1);
+    const uint8_t f = P.flags[g];
+    if (f == kVoid || !flag_grip(f)) return;
+    const double ux = eps * (double(i) * P.a) + 0.0;
+    R hi[DIM], lo[DIM];
+    hi[0] = R(ux);
+    lo[0] = R(ux - double(hi[0]));
+#pragma unroll
+    for (int c = 1; c < DIM; ++c) { hi[c] = R(0); lo[c] = R(0); }
+    S::store_u(P.u_in, int(g), P.nsites, hi, lo);
 }
 
 // ------------------------------------------------------- record finalize
@@ -1654,6 +1687,18 @@ hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t
     } else {
         if (prec) hipLaunchKernelGGL((k_kick_drift<3, 1>), grid, block, 0, s, p);
         else hipLaunchKernelGGL((k_kick_drift<3, 0>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grips(const StepParams &p, int dim, int prec, hipStream_t s, int step_local) {
+    const dim3 grid(unsigned((2 * int64_t(p.ny) * p.nz + 255) / 256)), block(256);
+    if (dim == 2) {
+        if (prec) hipLaunchKernelGGL((k_grips<2, 1>), grid, block, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_grips<2, 0>), grid, block, 0, s, p, step_local);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_grips<3, 1>), grid, block, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_grips<3, 0>), grid, block, 0, s, p, step_local);
     }
     return hipGetLastError();
 }

@@ -127,6 +127,27 @@ def circular_inclusions(L: int, seed: int, r_min: float = 3.0, r_max: float = 12
     return img
 
 
+def edge_notch(img: np.ndarray, depth: int, width: int = 1, x0: int | None = None) -> np.ndarray:
+    """Copy of a 2D image with a straight notch of VOID pixels for a mode-I
+    test under tension along x: ``width`` columns starting at ``x0`` (default:
+    centred), from the bottom edge (row 0) up to row ``depth - 1``.  The
+    paper's specimens carry such a notch (Section 3.1 mode-I tests; its size
+    is only drawn in a figure, so it is a parameter here)."""
+    out = np.array(img, dtype=np.uint8, copy=True)
+    ny, nx = out.shape
+    if x0 is None:
+        x0 = (nx - width) // 2
+    out[:max(0, min(depth, ny)), max(0, x0):min(nx, x0 + width)] = VOID
+    return out
+
+
+def notched_composite(L: int = 96, seed: int = 7, depth_frac: float = 0.2) -> np.ndarray:
+    """A Poisson composite (STIFF matrix, SOFT inclusions placed as a Poisson
+    process, Section 3.1) of side ``L`` with a centred one-pixel edge notch
+    of depth ``depth_frac * L``."""
+    return edge_notch(circular_inclusions(L, seed=seed), int(round(depth_frac * L)))
+
+
 BATCH_SIZES = (64, 96, 128, 192, 256)
 
 
@@ -166,6 +187,15 @@ WORKLOADS = {
     "c3": dict(dim=3, k=[[1.0]], s=[[0.03]], mass=[1.0], a=1.0, k_face=1.0, k_diag=0.5,
                dt=0.01, gamma=0.1, d_eps=0.0005, n_inc=100, steps=2000,
                precision="fp32k", void_value=VOID),
+    # the paper's own loading of a notched Poisson composite (Section 3.1):
+    # spring constants and critical lengths of its spring table (stiff-stiff
+    # 2e-3 / 10.1, soft-soft 2e-5 / 11.0, stiff-soft 1.25e-4 / 10.4 at r0 = 10,
+    # as critical stretches), unit masses, dt = 1, no damping, grips pulled
+    # apart at a strain rate of 1e-6 per unit time, energies every 500 steps.
+    "mode1": dict(dim=2, k=[[2.0e-5, 1.25e-4], [1.25e-4, 2.0e-3]],
+                  s=[[0.10, 0.04], [0.04, 0.01]], mass=[1.0, 1.0], a=10.0, dt=1.0,
+                  gamma=0.0, rate=1e-6, steps=16000, every=500, precision="fp64",
+                  void_value=VOID),
     # batched circular-inclusion specimens: stiff matrix, soft inclusions.
     "c4": dict(dim=2, k=[[0.1, NAN], [NAN, 1.0]], s=[[0.20, NAN], [NAN, 0.05]],
                mass=[1.0, 1.0], a=1.0, dt=0.01, gamma=0.1, d_eps=0.005, max_inc=64,

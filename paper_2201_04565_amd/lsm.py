@@ -30,7 +30,7 @@ EXPORTS = (
     "lsm_get_velocities", "lsm_set_positions", "lsm_set_velocities", "lsm_eval_forces",
     "lsm_save_state", "lsm_load_state", "lsm_set_timing", "lsm_read_timing", "lsm_step_bytes",
     "lsm_set_launch", "lsm_set_prefetch", "lsm_autotune", "lsm_get_launch", "lsm_last_error",
-    "lsm_strerror",
+    "lsm_strerror", "lsm_set_strain_rate", "lsm_relax_trace",
 )
 
 
@@ -90,6 +90,8 @@ def load_library():
     L.lsm_apply_strain_increment.argtypes = [vp, dbl]
     L.lsm_relax.argtypes = [vp, i64]
     L.lsm_read_state.argtypes = [vp, P(Record)]
+    L.lsm_set_strain_rate.argtypes = [vp, dbl]
+    L.lsm_relax_trace.argtypes = [vp, i64, i64, vp, i64, P(i64)]
     L.lsm_read_broken.argtypes = [vp, i64, i64, vp, P(i64)]
     L.lsm_n_broken.argtypes = [vp, P(i64)]
     L.lsm_get_springs.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -144,6 +146,11 @@ def make_config(*, lattice, k, s, mass, a=1.0, k_face=1.0, k_diag=1.0, dt=0.01, 
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _record_dict(R) -> dict:
+    return dict(eps=R.eps, sigma=np.array(R.sigma[:]).reshape(3, 3), ke=R.ke, pe=R.pe,
+                n_broken=R.n_broken, inc=R.increment, step=R.step, status=R.status)
 
 
 class Lattice:
@@ -227,8 +234,21 @@ class Lattice:
         rc = self._L.lsm_read_state(self._h, C.byref(R))
         if rc != LSM_OK and not (allow_unstable and rc == LSM_EUNSTABLE):
             self._check(rc)
-        return dict(eps=R.eps, sigma=np.array(R.sigma[:]).reshape(3, 3), ke=R.ke, pe=R.pe,
-                    n_broken=R.n_broken, inc=R.increment, step=R.step, status=R.status)
+        return _record_dict(R)
+
+    def set_strain_rate(self, rate: float):
+        """Constant strain-rate loading (per unit time) from the next step."""
+        self._check(self._L.lsm_set_strain_rate(self._h, float(rate)))
+
+    def relax_trace(self, rate, nsteps: int, every: int) -> list:
+        """The paper's protocol: grips at a constant strain rate for nsteps,
+        a record (strain, stress, energies) after every `every` steps."""
+        self.set_strain_rate(rate)
+        cap = -(-int(nsteps) // int(every))
+        buf = (Record * cap)()
+        n = C.c_int64()
+        self._check(self._L.lsm_relax_trace(self._h, int(nsteps), int(every), buf, cap, C.byref(n)))
+        return [_record_dict(buf[i]) for i in range(n.value)]
 
     def read_broken(self) -> np.ndarray:
         n = C.c_int64()

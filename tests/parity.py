@@ -8,26 +8,48 @@ def first_near_tie(ev, tie):
     return int(idx[0]) if len(idx) else len(ev)
 
 
-def compare_events(ev_o, ev_g, tie):
+def compare_events(ev_o, ev_g, tie, key="inc"):
     """Events before the first near-tie (in either run) must be identical.
-    Returns the increment from which the runs may legitimately diverge."""
+    Returns the increment (key="inc") or the step (key="step", for runs
+    without increments) from which the runs may legitimately diverge, and
+    the number of identical events."""
     k = min(first_near_tie(ev_o, tie), first_near_tie(ev_g, tie))
     ko = [(int(e["inc"]), int(e["step"]), int(e["id"])) for e in ev_o[:k]]
     kg = [(int(e["inc"]), int(e["step"]), int(e["id"])) for e in ev_g[:k]]
     assert ko == kg, _first_diff(ko, kg)
-    div_inc = 1 << 30
+    div = 1 << 30
+    # the first event past the identical prefix in either list (a list that
+    # ran out before the tie must not hide an extra event in the other)
     if k < len(ev_o):
-        div_inc = min(div_inc, int(ev_o[k]["inc"]))
+        div = min(div, int(ev_o[k][key]))
     if k < len(ev_g):
-        div_inc = min(div_inc, int(ev_g[k]["inc"]))
-    if k == len(ev_o) and k == len(ev_g):
-        return div_inc, k
-    # a list that ran out before the tie must not hide an extra event
-    if k == len(ev_o) and k < len(ev_g):
-        div_inc = min(div_inc, int(ev_g[k]["inc"]))
-    if k == len(ev_g) and k < len(ev_o):
-        div_inc = min(div_inc, int(ev_o[k]["inc"]))
-    return div_inc, k
+        div = min(div, int(ev_g[k][key]))
+    return div, k
+
+
+def compare_trace(rec_o, rec_g, rtol, upto_step=None, dim=2):
+    """Records of a constant-rate run (one per callback): the strain exactly,
+    sigma_xx, potential and kinetic energy within rtol of max(|value|, 1e-3
+    of the run's largest), broken-spring counts equal, for the callbacks
+    before step upto_step.  Returns the number compared."""
+    peak = {q: max(abs(f(r)) for r in rec_o) or 1.0
+            for q, f in (("sxx", lambda r: r["sigma"][0, 0]), ("pe", lambda r: r["pe"]),
+                         ("ke", lambda r: r["ke"]))}
+    n = 0
+    for ro, rg in zip(rec_o, rec_g):
+        if upto_step is not None and ro["step"] >= upto_step:
+            break
+        assert ro["step"] == rg["step"] and ro["inc"] == rg["inc"]
+        assert rg["eps"] == ro["eps"], f"step {ro['step']}: strain {rg['eps']!r} vs {ro['eps']!r}"
+        for q, vo, vg in (("sxx", ro["sigma"][0, 0], rg["sigma"][0, 0]), ("pe", ro["pe"], rg["pe"]),
+                          ("ke", ro["ke"], rg["ke"])):
+            scale = max(abs(vo), 1e-3 * peak[q])
+            assert abs(vg - vo) <= rtol * scale, f"step {ro['step']}: {q} {vo!r} vs {vg!r}"
+        so, sg = ro["sigma"][:dim, :dim], rg["sigma"][:dim, :dim]
+        assert np.max(np.abs(sg - so)) <= rtol * max(np.max(np.abs(so)), 1e-3 * peak["sxx"])
+        assert rg["n_broken"] == ro["n_broken"], f"step {ro['step']}"
+        n += 1
+    return n
 
 
 def _first_diff(a, b):
