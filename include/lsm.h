@@ -56,7 +56,8 @@ extern "C" {
 #define LSM_MAX_PHASES 8
 #define LSM_KERNEL_AUTO 0   /* 2D: LSM_KERNEL_SMALL where the lattice fits it, else the
                                two-step (FP32-compensated) or one-step (FP64) row sweep;
-                               3D: the gather kernel */
+                               3D: LSM_KERNEL_COMPACT (the gather kernel under
+                               constant-rate loading or beyond 2^28 particles) */
 #define LSM_KERNEL_GATHER 1 /* one thread per site, all incident springs */
 #define LSM_KERNEL_SWEEP 2  /* 2D: wavefronts sweep rows, forward springs once */
 #define LSM_KERNEL_SWEEP2 3 /* 2D, FP32-compensated: row sweep advancing two interior
@@ -69,6 +70,14 @@ extern "C" {
                                runs the start and end steps); LSM_EINVAL for 3D or larger
                                lattices (a lattice built later and too large runs the
                                gather kernel) */
+#define LSM_KERNEL_COMPACT 5 /* 3D: interior steps on a compact copy of the state (one
+                               record per particle instead of per grid site, neighbours
+                               found through a per-site prefix count), copied in and out
+                               around every chunk of interior steps; same results as
+                               LSM_KERNEL_GATHER, whose kernel runs the start and end
+                               steps.  LSM_EINVAL for 2D lattices and for lattices of
+                               2^28 particles or more.  Not under constant-rate loading
+                               (the gather kernel runs those steps) */
 
 /* Model and integration parameters.
  *  k[P*P], break_stretch[P*P]: row-major, symmetric spring constant and

@@ -76,6 +76,15 @@ struct lsm_handle {
     uint32_t *d_plist = nullptr;      // packed site coordinates per particle (3D gather)
     std::vector<uint32_t> plist;      // host copy; empty: site-grid launch
     int c_blocks = 0;
+    // compact 3D layout of the interior steps (empty: not available): per
+    // site the solid sites before it (<< 4) | phase, plus a sentinel; per
+    // particle the absent-spring directions and the flag byte
+    std::vector<uint32_t> crank, cabs;
+    std::vector<uint8_t> cflag;
+    int64_t cn = 0;                   // particle stride of the compact arrays
+    void *d_cu[2] = {nullptr, nullptr}, *d_cv = nullptr;
+    uint8_t *d_cflag = nullptr;
+    uint32_t *d_cmask = nullptr, *d_cabs = nullptr, *d_crank = nullptr;
     void *d_U[2] = {nullptr, nullptr};
     void *d_V = nullptr, *d_A = nullptr;
     double *d_f64 = nullptr, *d_partials = nullptr;
@@ -268,6 +277,12 @@ bool small_fits(const lsm_handle *h) {
 bool use_small(const lsm_handle *h) {
     return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h) && h->rate == 0.0;
 }
+// 3D interior steps in the compact layout: the default for 3D lattices
+// (not under constant-rate loading, whose grip kernel moves site-grid state)
+bool use_compact(const lsm_handle *h) {
+    return h->dim == 3 && !h->crank.empty() && h->rate == 0.0 &&
+           (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT);
+}
 bool use_sweep(const lsm_handle *h) {
     return h->dim == 2 && ((h->variant == LSM_KERNEL_AUTO && !small_fits(h)) || h->variant == LSM_KERNEL_SWEEP ||
                            h->variant == LSM_KERNEL_SWEEP2) &&
@@ -338,6 +353,31 @@ int mid_launches(const lsm_handle *h, int chunk) {
 // and write the other ones, swapping them for the next launch.
 hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
     hipError_t le = hipSuccess;
+    if (use_compact(h)) {
+        // copy the site-grid state in, run the chunk on the compact arrays,
+        // copy the result out to the buffer the gather kernel would have
+        // ended on
+        if (chunk < 1) return hipSuccess;
+        StepParams p = make_params(h, c, c ^ 1);
+        p.crank = h->d_crank;
+        p.cabs = h->d_cabs;
+        le = lsm::launch_pack_c3(p, h->prec, h->stream, 1, h->d_U[c], h->d_V, static_cast<uint32_t *>(h->d_mask),
+                                 h->d_cu[0], h->d_cv, h->d_cmask, h->cn);
+        StepParams q = p;
+        q.flags = h->d_cflag;
+        q.mask = h->d_cmask;
+        q.v = h->d_cv;
+        q.nsites = h->cn;
+        for (int s = 0; s < chunk && le == hipSuccess; ++s) {
+            q.u_in = h->d_cu[s & 1];
+            q.u_out = h->d_cu[(s & 1) ^ 1];
+            le = lsm::launch_step_c3(q, h->prec, h->stream, local + s);
+        }
+        if (le != hipSuccess) return le;
+        return lsm::launch_pack_c3(p, h->prec, h->stream, 0, h->d_U[c ^ (chunk & 1)], h->d_V,
+                                   static_cast<uint32_t *>(h->d_mask), h->d_cu[chunk & 1], h->d_cv, h->d_cmask,
+                                   h->cn);
+    }
     if (use_small(h)) {
         if (chunk < 1) return hipSuccess;
         StepParams p = make_params(h, c, c ^ 1);
@@ -521,6 +561,41 @@ void lsm_destroy(lsm_handle *h) {
     delete h;
 }
 
+// Tables of the compact 3D layout (particle indices must fit 28 bits).
+static void build_compact_3d(lsm_handle *h) {
+    h->crank.clear();
+    h->cabs.clear();
+    h->cflag.clear();
+    h->cn = 0;
+    if (h->n >= (int64_t(1) << 28)) return;
+    const int64_t nx = h->nx, ny = h->ny, nz = h->nz, ns = h->nsites;
+    h->crank.resize(size_t(ns) + 1);
+    uint32_t before = 0;
+    for (int64_t g = 0; g < ns; ++g) {
+        const uint8_t f = h->flags[size_t(g)];
+        h->crank[size_t(g)] = (before << 4) | (f == lsm::kVoid ? 0u : uint32_t(lsm::flag_phase(f)));
+        if (f != lsm::kVoid) ++before;
+    }
+    h->crank[size_t(ns)] = before << 4;
+    h->cabs.resize(size_t(h->n));
+    h->cflag.resize(size_t(h->n) + 1, lsm::kVoid);
+    for (int64_t c = 0; c < h->n; ++c) {
+        const int64_t g = h->site_of[size_t(c)];
+        const int64_t i = g % nx, j = (g / nx) % ny, k = g / (nx * ny);
+        uint32_t bits = 0;
+        for (int d = 0; d < 18; ++d) {
+            const int sgn = d < 9 ? 1 : -1;
+            const int64_t qi = i + sgn * kFwd3[d % 9][0], qj = j + sgn * kFwd3[d % 9][1],
+                          qk = k + sgn * kFwd3[d % 9][2];
+            const bool in = qi >= 0 && qi < nx && qj >= 0 && qj < ny && qk >= 0 && qk < nz;
+            if (!in || h->flags[size_t(qi + nx * (qj + ny * qk))] == lsm::kVoid) bits |= 1u << d;
+        }
+        h->cabs[size_t(c)] = bits;
+        h->cflag[size_t(c)] = h->flags[size_t(g)];
+    }
+    h->cn = (h->n + 63) / 64 * 64;
+}
+
 int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t ny, int64_t nz) {
     if (!h || !phase) return LSM_EINVAL;
     if (h->bound) return fail(h, LSM_ESTATE, "lattice already bound");
@@ -574,6 +649,7 @@ int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t n
             h->plist[size_t(c)] = uint32_t(i) | (uint32_t(j) << 10) | (uint32_t(k) << 21);
         }
         h->c_blocks = int(((h->n + 255) / 256 + 7) / 8) * 8;
+        build_compact_3d(h);
     }
     h->tiles_x = int((nx + lsm::kTileX - 1) / lsm::kTileX);
     h->tiles_y = int((ny + lsm::kTileY - 1) / lsm::kTileY);
@@ -601,7 +677,7 @@ int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
     return LSM_OK;
 }
 
-constexpr int kRegions = 16;
+constexpr int kRegions = 23;
 
 static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
     size_t o = 0;
@@ -625,6 +701,14 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         h->plist.size() * 4,                          // 13 particle list
         h->dim == 2 ? ns * h->vb : 0,                 // 14 second velocity buffer (two-step sweep)
         h->dim == 2 ? (ns + 1) * h->mb : 0,           // 15 second break-bit buffer
+        // compact 3D layout (empty when not available)
+        size_t(h->cn) * h->ub,                        // 16 compact U0
+        size_t(h->cn) * h->ub,                        // 17 compact U1
+        size_t(h->cn) * h->vb,                        // 18 compact V
+        h->cflag.size(),                              // 19 compact flags
+        h->cflag.size() * 4,                          // 20 compact break + absent bits
+        h->cabs.size() * 4,                           // 21 absent-spring bits
+        h->crank.size() * 4,                          // 22 prefix counts per site
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -669,6 +753,13 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_plist = reinterpret_cast<uint32_t *>(w + off[13]);
     h->d_V_alt = w + off[14];
     h->d_mask_alt = w + off[15];
+    h->d_cu[0] = w + off[16];
+    h->d_cu[1] = w + off[17];
+    h->d_cv = w + off[18];
+    h->d_cflag = reinterpret_cast<uint8_t *>(w + off[19]);
+    h->d_cmask = reinterpret_cast<uint32_t *>(w + off[20]);
+    h->d_cabs = reinterpret_cast<uint32_t *>(w + off[21]);
+    h->d_crank = reinterpret_cast<uint32_t *>(w + off[22]);
     h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     {
@@ -693,6 +784,12 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->plist.empty())
         HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (!h->crank.empty()) {
+        HIPCHK(h, hipMemcpyAsync(h->d_cflag, h->cflag.data(), h->cflag.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->d_cabs, h->cabs.data(), h->cabs.size() * 4, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->d_crank, h->crank.data(), h->crank.size() * 4, hipMemcpyHostToDevice,
+                                 h->stream));
+    }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->cur = 0;
     h->half = false;
@@ -1202,8 +1299,12 @@ int lsm_set_prefetch(lsm_handle *h, int rows_ahead) {
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     if (!h) return LSM_EINVAL;
     if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP &&
-        variant != LSM_KERNEL_SWEEP2 && variant != LSM_KERNEL_SMALL)
+        variant != LSM_KERNEL_SWEEP2 && variant != LSM_KERNEL_SMALL && variant != LSM_KERNEL_COMPACT)
         return fail(h, LSM_EINVAL, "unknown kernel variant");
+    if (variant == LSM_KERNEL_COMPACT && h->dim != 3)
+        return fail(h, LSM_EINVAL, "the compact layout is 3D only");
+    if (variant == LSM_KERNEL_COMPACT && h->built && h->crank.empty())
+        return fail(h, LSM_EINVAL, "lattice too large for the compact layout");
     if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");
     if (variant == LSM_KERNEL_SMALL && h->built && !small_fits(h))
         return fail(h, LSM_EINVAL, "lattice too large for the one-workgroup kernel");
@@ -1341,10 +1442,11 @@ int lsm_autotune(lsm_handle *h, int steps_per_trial, lsm_tuning *results, int ca
 int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
     if (!h || !out) return LSM_EINVAL;
     // the kernel that runs the interior steps (AUTO resolved)
-    const int variant = use_sweep2(h)  ? LSM_KERNEL_SWEEP2
-                        : use_sweep(h) ? LSM_KERNEL_SWEEP
-                        : use_small(h) ? LSM_KERNEL_SMALL
-                                       : LSM_KERNEL_GATHER;
+    const int variant = use_sweep2(h)    ? LSM_KERNEL_SWEEP2
+                        : use_sweep(h)   ? LSM_KERNEL_SWEEP
+                        : use_small(h)   ? LSM_KERNEL_SMALL
+                        : use_compact(h) ? LSM_KERNEL_COMPACT
+                                         : LSM_KERNEL_GATHER;
     *out = lsm_tuning{variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
     return LSM_OK;
 }

@@ -108,6 +108,12 @@ struct StepParams {
     const SweepItem *items;  // active work items
     const int32_t *n_items;  // number of active work items (device)
     uint32_t *spec_broken;   // broken-spring count per specimen
+    // compact 3D layout: per grid site (plus a sentinel) the number of solid
+    // sites before it in raster order (= the particle index of a solid site)
+    // shifted left by 4, or'ed with the site's phase; per particle the
+    // directions (bits 0-17) whose neighbour is void or off the grid
+    const uint32_t *crank;
+    const uint32_t *cabs;
 };
 
 // Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.
@@ -136,6 +142,12 @@ int sweep_waves_per_cu(int two_step, int prec, int pf);
 hipError_t launch_sweep2d_x2_batch(const StepParams &p, int prec, hipStream_t stream, int step_local,
                                    int capacity2);
 hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t stream);
+// 3D compact layout: one interior step (P's state pointers, flags and break
+// bits point at the compact arrays, P.nsites is their particle stride), and
+// the copies between the site-grid and compact states (cn: compact stride).
+hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t stream, int step_local);
+hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t stream, int to_compact, void *u_grid,
+                          void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn);
 // Constant-rate loading: places the grips of u_in at the strain of step
 // step_local of the increment (rate fields of the loop control) and records
 // that strain; launched before every step kernel while a rate is set.

@@ -390,11 +390,19 @@ __device__ inline void integrate_site(const StepParams &P, const ST &st, uint8_t
 // One time step of one site: all incident springs in direction order
 // (break test, Eq. 1-2 force), then the integrator.  Everything is read and
 // written through P, so a caller may point the state arrays at LDS.
-template <int DIM, int PREC, int MODE>
+//
+// CMP selects the compact 3D layout: g is then the particle index (state,
+// flags and break bits are per particle, stride P.nsites = the padded
+// particle count), gg the grid index of its site, and neighbours are found
+// through the grid's prefix-count table P.crank; the break bits of a
+// particle also mark its absent springs (neighbour void or off the grid),
+// whose directions are listed in P.cabs.  The spring arithmetic is shared,
+// so both layouts produce the same bits.
+template <int DIM, int PREC, int MODE, bool CMP = false>
 __device__ __attribute__((always_inline)) inline void step_site(
     const StepParams &P, const typename TT<PREC>::type *tt, const double *mass_s,
     const typename State<DIM, PREC>::R *imass_s, int g, int i, int j, int k, uint8_t fp, double *red,
-    int step_local) {
+    int step_local, int gg = 0) {
     using S = State<DIM, PREC>;
     using R = typename S::R;
     using G = Geo<DIM>;
@@ -426,10 +434,19 @@ __device__ __attribute__((always_inline)) inline void step_site(
     for (int t = 0; t < kGrp; ++t) {
         const int d = d0 + t;
         const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
-        const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-        inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
-        qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
-        fqs[t] = P.flags[qs[t]];
+        if constexpr (CMP) {
+            // an absent or broken spring reads the particle's own entry
+            const bool gone = (mask >> d) & 1;
+            const uint32_t cr = P.crank[gone ? gg : gg + ddi + P.nx * (ddj + P.ny * ddk)];
+            inb[t] = true;
+            qs[t] = int(cr >> 4);
+            fqs[t] = uint8_t(cr & 15u);
+        } else {
+            const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+            inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+            qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+            fqs[t] = P.flags[qs[t]];
+        }
         S::load_u(P.u_in, qs[t], P.nsites, uqhs[t], uqls[t]);
     }
 #pragma unroll
@@ -437,9 +454,9 @@ __device__ __attribute__((always_inline)) inline void step_site(
         const int d = d0 + t;
         if (!inb[t]) continue;
         const uint8_t fq = fqs[t];
-        if (fq == kVoid) continue;
+        if (!CMP && fq == kVoid) continue;
         const bool fwd = d < G::NF;
-        const int myrank = rank;
+        int myrank = rank;
         if (fwd) ++rank;
         if (mask & (Mask(1) << d)) continue;
         const R *uqh = uqhs[t];
@@ -502,12 +519,13 @@ __device__ __attribute__((always_inline)) inline void step_site(
             if (commit) {
                 newmask |= Mask(1) << d;
                 if (fwd) {
+                    if constexpr (CMP) myrank = __popc(~P.cabs[g] & ((1u << d) - 1u));
                     const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
                     if (idx < P.ev_cap) {
                         lsm_event ev;
                         ev.increment = P.ctl->inc;
                         ev.step = P.ctl->step_base + step_local;
-                        ev.spring_id = int64_t(P.sbase[g]) + myrank;
+                        ev.spring_id = int64_t(P.sbase[CMP ? gg : g]) + myrank;
                         ev.margin = margin;
                         P.events[idx] = ev;
                     }
@@ -613,6 +631,65 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 #pragma unroll
             for (int v = 0; v < kNumPartials; ++v) P.partials[int64_t(blockIdx.x) * kNumPartials + v] = red[v];
         }
+    }
+}
+
+// Interior step of a 3D lattice in the compact layout: one thread per
+// particle (raster order, which is the canonical particle order), state,
+// flags and break bits stored per particle, so a wavefront's loads and
+// stores touch only solid sites; the spring arithmetic is the gather
+// kernel's.  P's state pointers point at the compact arrays.
+template <int PREC>
+__global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local) {
+    using R = typename State<3, PREC>::R;
+    using TTy = typename TT<PREC>::type;
+    __shared__ TTy tt[kMaxTypes];
+    __shared__ double mass_s[LSM_MAX_PHASES];
+    __shared__ R imass_s[LSM_MAX_PHASES];
+    for (int t = threadIdx.x; t < kMaxTypes; t += kBlock) tt[t] = TT<PREC>::make(P.types[t]);
+    if (threadIdx.x < LSM_MAX_PHASES) {
+        mass_s[threadIdx.x] = P.mass[threadIdx.x];
+        imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
+    }
+    __syncthreads();
+    // each XCD takes a contiguous run of workgroups (neighbouring planes
+    // share its L2)
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
+    const int p = lb * kBlock + int(threadIdx.x);
+    if (p >= P.n_part) return;
+    const uint32_t pc = P.plist[p];
+    const int i = int(pc & 1023u), j = int((pc >> 10) & 2047u), k = int(pc >> 21);
+    const int gg = i + P.nx * (j + P.ny * k);
+    double red[1] = {0.0};
+    step_site<3, PREC, kMid, true>(P, tt, mass_s, imass_s, p, i, j, k, P.flags[p], red, step_local, gg);
+}
+
+// Copies between the site-grid state (displacements u_grid, velocities
+// v_grid, break bits m_grid, stride P.nsites) and the compact one (stride
+// cn); the compact break bits also carry the absent-spring bits.
+template <int PREC, bool TO_COMPACT>
+__global__ __launch_bounds__(256) void k_pack_c3(StepParams P, void *u_grid, void *v_grid, uint32_t *m_grid,
+                                                 void *u_c, void *v_c, uint32_t *m_c, int64_t cn) {
+    using S = State<3, PREC>;
+    using R = typename S::R;
+    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p >= P.n_part) return;
+    const uint32_t pc = P.plist[p];
+    const int g = int(pc & 1023u) + P.nx * (int((pc >> 10) & 2047u) + P.ny * int(pc >> 21));
+    R hi[3], lo[3], w[3];
+    if constexpr (TO_COMPACT) {
+        S::load_u(u_grid, g, P.nsites, hi, lo);
+        S::load_v(v_grid, g, P.nsites, w);
+        S::store_u(u_c, p, cn, hi, lo);
+        S::store_v(v_c, p, cn, w);
+        m_c[p] = m_grid[g] | P.cabs[p];
+    } else {
+        S::load_u(u_c, p, cn, hi, lo);
+        S::load_v(v_c, p, cn, w);
+        S::store_u(u_grid, g, P.nsites, hi, lo);
+        S::store_v(v_grid, g, P.nsites, w);
+        m_grid[g] = m_c[p] & ~P.cabs[p];
     }
 }
 
@@ -1664,6 +1741,27 @@ hipError_t launch_small_mid(const StepParams &p, int prec, hipStream_t s, int ns
 hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStream_t s, int step_local) {
     if (dim == 2) return prec ? launch_step_t<2, 1>(p, mode, s, step_local) : launch_step_t<2, 0>(p, mode, s, step_local);
     return prec ? launch_step_t<3, 1>(p, mode, s, step_local) : launch_step_t<3, 0>(p, mode, s, step_local);
+}
+
+hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local) {
+    const dim3 grid(p.c_blocks), block(kBlock);
+    if (prec) hipLaunchKernelGGL((k_step_c3<1>), grid, block, 0, s, p, step_local);
+    else hipLaunchKernelGGL((k_step_c3<0>), grid, block, 0, s, p, step_local);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t s, int to_compact, void *u_grid,
+                          void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn) {
+    const dim3 grid(unsigned((p.n_part + 255) / 256)), block(256);
+    if (p.n_part <= 0) return hipSuccess;
+    if (to_compact) {
+        if (prec) hipLaunchKernelGGL((k_pack_c3<1, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+        else hipLaunchKernelGGL((k_pack_c3<0, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_pack_c3<1, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+        else hipLaunchKernelGGL((k_pack_c3<0, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_increment(const StepParams &p, int dim, int prec, hipStream_t s, double eps_new,

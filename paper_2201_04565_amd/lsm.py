@@ -20,7 +20,7 @@ LSM_OK, LSM_EINVAL, LSM_ENOMEM, LSM_EHIP, LSM_EUNSTABLE, LSM_ESTATE = 0, -1, -2,
 TRI2D, SC3D = 0, 1
 FP64, FP32_KAHAN = 0, 1
 PRED_AFFINE, PRED_GRIPS_ONLY = 0, 1
-KERNEL_AUTO, KERNEL_GATHER, KERNEL_SWEEP, KERNEL_SWEEP2, KERNEL_SMALL = 0, 1, 2, 3, 4
+KERNEL_AUTO, KERNEL_GATHER, KERNEL_SWEEP, KERNEL_SWEEP2, KERNEL_SMALL, KERNEL_COMPACT = 0, 1, 2, 3, 4, 5
 MAX_PHASES = 8
 
 EXPORTS = (
@@ -339,7 +339,7 @@ class Lattice:
 
     def set_launch(self, variant="auto", rows_per_wave=0):
         v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
-             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL}[variant]
+             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def set_prefetch(self, rows_ahead):
@@ -352,7 +352,7 @@ class Lattice:
         n = C.c_int()
         self._check(self._L.lsm_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
         names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2",
-                 KERNEL_SMALL: "small"}
+                 KERNEL_SMALL: "small", KERNEL_COMPACT: "compact"}
         return [(names.get(t.variant, "auto"), t.rows_per_wave, t.prefetch, t.us_per_step)
                 for t in buf[:n.value]]
 
@@ -360,7 +360,7 @@ class Lattice:
         t = Tuning()
         self._check(self._L.lsm_get_launch(self._h, C.byref(t)))
         names = {KERNEL_AUTO: "auto", KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep",
-                 KERNEL_SWEEP2: "sweep2", KERNEL_SMALL: "small"}
+                 KERNEL_SWEEP2: "sweep2", KERNEL_SMALL: "small", KERNEL_COMPACT: "compact"}
         return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch,
                     steps_per_launch=t.steps_per_launch)
 
@@ -416,7 +416,7 @@ class HostModel:
     def set_launch(self, variant="auto", rows_per_wave=0):
         """Kernel variant whose bytes step_bytes reports (no device call)."""
         v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
-             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL}[variant]
+             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def step_bytes(self) -> int:

@@ -346,6 +346,39 @@ def test_small_kernel_is_bitwise_the_gather_kernel(lsm, precision):
         assert out[1][0] == out[0][0]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_compact_kernel_is_bitwise_the_gather_kernel(lsm, precision):
+    # interior steps on the compact per-particle state against the gather
+    # kernel on the site grid: a random-field specimen, a ragged crop of a
+    # two-phase field with scattered voids (dimensions that are no multiple
+    # of anything), and a relaxation longer than one captured chunk;
+    # fracture in every case; state, masks and events equal
+    wl3 = dict(inputs.WORKLOADS["c3"])
+    two = dict(wl3, k=[[1.0, NAN], [NAN, 0.3]], s=[[0.03, NAN], [NAN, 0.08]], mass=[1.0, 2.0])
+    rng = np.random.default_rng(11)
+    img2 = rng.integers(0, 2, size=(13, 17, 23)).astype(np.uint8)
+    img2[rng.random(img2.shape) < 0.25] = inputs.VOID
+    crop = inputs.gaussian_random_field_3d(24, corr_len=2.5, seed=5)[:11, :19, :21]
+    cases = [("grf 20^3", inputs.gaussian_random_field_3d(20, corr_len=3.0, seed=2), wl3, 4, 300, 0.01),
+             ("two-phase 23x17x13", img2, two, 3, 257, 0.012),
+             ("grf crop 21x19x11", crop, wl3, 2, 1203, 0.015)]
+    for name, img, wl, n_inc, steps, d_eps in cases:
+        say(f"compact vs gather {name} {precision} {n_inc} x relax({steps})")
+        out = []
+        for variant in ("gather", "compact"):
+            g = gpu_for(lsm, img, wl, precision)
+            g.set_launch(variant)
+            assert g.launch()["variant"] == variant
+            for _ in range(n_inc):
+                g.apply_increment(d_eps)
+                g.relax(steps)
+            out.append((g.save_state(), g.read_broken(), g.read_state()))
+        assert len(out[0][1]) > 0, "the case should break springs"
+        say(f"  {len(out[0][1])} events")
+        assert np.array_equal(out[1][1], out[0][1])
+        assert out[1][0] == out[0][0]
+
+
 @pytest.mark.parametrize("precision", [
     "fp32k",
     pytest.param("fp64", marks=pytest.mark.skip(

@@ -109,6 +109,15 @@ def test_small_kernel_variant_rules():
         _model(img3, inputs.WORKLOADS["c3"]).set_launch("small")
 
 
+def test_compact_kernel_variant_rules():
+    # the compact per-particle layout of the 3D interior steps: 3D only
+    img3 = inputs.gaussian_random_field_3d(12, seed=3)
+    _model(img3, inputs.WORKLOADS["c3"]).set_launch("compact")
+    _model(img3, inputs.WORKLOADS["c3"], precision="fp32k").set_launch("compact")
+    with pytest.raises(lsm.LsmError):
+        _model(inputs.c1_image(), inputs.WORKLOADS["c1"]).set_launch("compact")
+
+
 def test_table2_paper_mode_types():
     # explicit interface constants (paper's spring table), r0 = 10
     k = [[2e-5, 1.25e-4], [1.25e-4, 2e-3]]
