@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -79,12 +80,14 @@ struct lsm_handle {
     // compact 3D layout of the interior steps (empty: not available): per
     // site the solid sites before it (<< 4) | phase, plus a sentinel; per
     // particle the absent-spring directions and the flag byte
-    std::vector<uint32_t> crank, cabs;
+    std::vector<uint64_t> crow;
+    std::vector<uint32_t> cabs;
     std::vector<uint8_t> cflag;
     int64_t cn = 0;                   // particle stride of the compact arrays
     void *d_cu[2] = {nullptr, nullptr}, *d_cv = nullptr;
     uint8_t *d_cflag = nullptr;
-    uint32_t *d_cmask = nullptr, *d_cabs = nullptr, *d_crank = nullptr;
+    uint32_t *d_cmask = nullptr, *d_cabs = nullptr;
+    uint64_t *d_crow = nullptr;
     void *d_U[2] = {nullptr, nullptr};
     void *d_V = nullptr, *d_A = nullptr;
     double *d_f64 = nullptr, *d_partials = nullptr;
@@ -280,7 +283,7 @@ bool use_small(const lsm_handle *h) {
 // 3D interior steps in the compact layout: the default for 3D lattices
 // (not under constant-rate loading, whose grip kernel moves site-grid state)
 bool use_compact(const lsm_handle *h) {
-    return h->dim == 3 && !h->crank.empty() && h->rate == 0.0 &&
+    return h->dim == 3 && !h->crow.empty() && h->rate == 0.0 &&
            (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT);
 }
 bool use_sweep(const lsm_handle *h) {
@@ -359,15 +362,15 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         // ended on
         if (chunk < 1) return hipSuccess;
         StepParams p = make_params(h, c, c ^ 1);
-        p.crank = h->d_crank;
+        p.crow = h->d_crow;
         p.cabs = h->d_cabs;
         le = lsm::launch_pack_c3(p, h->prec, h->stream, 1, h->d_U[c], h->d_V, static_cast<uint32_t *>(h->d_mask),
                                  h->d_cu[0], h->d_cv, h->d_cmask, h->cn);
         StepParams q = p;
         q.flags = h->d_cflag;
+        q.nsites = h->cn;
         q.mask = h->d_cmask;
         q.v = h->d_cv;
-        q.nsites = h->cn;
         for (int s = 0; s < chunk && le == hipSuccess; ++s) {
             q.u_in = h->d_cu[s & 1];
             q.u_out = h->d_cu[(s & 1) ^ 1];
@@ -561,22 +564,33 @@ void lsm_destroy(lsm_handle *h) {
     delete h;
 }
 
-// Tables of the compact 3D layout (particle indices must fit 28 bits).
+// Tables of the compact 3D layout: the row table (per site: particles
+// before it, solid bit, phases at x - 1, x, x + 1), absent-spring bits and
+// flags per particle.  Particle indices must fit 32 bits and the kernels
+// address the compact arrays and the row table with 32-bit byte offsets.
 static void build_compact_3d(lsm_handle *h) {
-    h->crank.clear();
+    h->crow.clear();
     h->cabs.clear();
     h->cflag.clear();
     h->cn = 0;
-    if (h->n >= (int64_t(1) << 28)) return;
     const int64_t nx = h->nx, ny = h->ny, nz = h->nz, ns = h->nsites;
-    h->crank.resize(size_t(ns) + 1);
-    uint32_t before = 0;
-    for (int64_t g = 0; g < ns; ++g) {
+    if ((h->n + 63) / 64 * 64 * 24 >= (int64_t(1) << 32) || (ns + 1) * 8 >= (int64_t(1) << 32)) return;
+    auto phase_at = [&](int64_t g) -> uint64_t {
         const uint8_t f = h->flags[size_t(g)];
-        h->crank[size_t(g)] = (before << 4) | (f == lsm::kVoid ? 0u : uint32_t(lsm::flag_phase(f)));
-        if (f != lsm::kVoid) ++before;
+        return f == lsm::kVoid ? 0u : uint64_t(lsm::flag_phase(f));
+    };
+    h->crow.resize(size_t(ns) + 1);
+    uint64_t before = 0;
+    for (int64_t g = 0; g < ns; ++g) {
+        const int64_t i = g % nx;
+        const bool solid = h->flags[size_t(g)] != lsm::kVoid;
+        uint64_t e = (before << 32) | (uint64_t(solid) << 12) | (phase_at(g) << 4);
+        if (i > 0) e |= phase_at(g - 1);
+        if (i + 1 < nx) e |= phase_at(g + 1) << 8;
+        h->crow[size_t(g)] = e;
+        if (solid) ++before;
     }
-    h->crank[size_t(ns)] = before << 4;
+    h->crow[size_t(ns)] = before << 32;
     h->cabs.resize(size_t(h->n));
     h->cflag.resize(size_t(h->n) + 1, lsm::kVoid);
     for (int64_t c = 0; c < h->n; ++c) {
@@ -702,13 +716,13 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         h->dim == 2 ? ns * h->vb : 0,                 // 14 second velocity buffer (two-step sweep)
         h->dim == 2 ? (ns + 1) * h->mb : 0,           // 15 second break-bit buffer
         // compact 3D layout (empty when not available)
-        size_t(h->cn) * h->ub,                        // 16 compact U0
-        size_t(h->cn) * h->ub,                        // 17 compact U1
+        size_t(h->cn) * 24,                           // 16 compact U0
+        size_t(h->cn) * 24,                           // 17 compact U1
         size_t(h->cn) * h->vb,                        // 18 compact V
         h->cflag.size(),                              // 19 compact flags
         h->cflag.size() * 4,                          // 20 compact break + absent bits
         h->cabs.size() * 4,                           // 21 absent-spring bits
-        h->crank.size() * 4,                          // 22 prefix counts per site
+        h->crow.size() * 8,                           // 22 row table per site
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -759,7 +773,7 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_cflag = reinterpret_cast<uint8_t *>(w + off[19]);
     h->d_cmask = reinterpret_cast<uint32_t *>(w + off[20]);
     h->d_cabs = reinterpret_cast<uint32_t *>(w + off[21]);
-    h->d_crank = reinterpret_cast<uint32_t *>(w + off[22]);
+    h->d_crow = reinterpret_cast<uint64_t *>(w + off[22]);
     h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     {
@@ -784,10 +798,10 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->plist.empty())
         HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
-    if (!h->crank.empty()) {
+    if (!h->crow.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_cflag, h->cflag.data(), h->cflag.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_cabs, h->cabs.data(), h->cabs.size() * 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(h->d_crank, h->crank.data(), h->crank.size() * 4, hipMemcpyHostToDevice,
+        HIPCHK(h, hipMemcpyAsync(h->d_crow, h->crow.data(), h->crow.size() * 8, hipMemcpyHostToDevice,
                                  h->stream));
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -1303,7 +1317,7 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
         return fail(h, LSM_EINVAL, "unknown kernel variant");
     if (variant == LSM_KERNEL_COMPACT && h->dim != 3)
         return fail(h, LSM_EINVAL, "the compact layout is 3D only");
-    if (variant == LSM_KERNEL_COMPACT && h->built && h->crank.empty())
+    if (variant == LSM_KERNEL_COMPACT && h->built && h->crow.empty())
         return fail(h, LSM_EINVAL, "lattice too large for the compact layout");
     if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");
     if (variant == LSM_KERNEL_SMALL && h->built && !small_fits(h))

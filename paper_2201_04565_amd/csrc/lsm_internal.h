@@ -108,11 +108,13 @@ struct StepParams {
     const SweepItem *items;  // active work items
     const int32_t *n_items;  // number of active work items (device)
     uint32_t *spec_broken;   // broken-spring count per specimen
-    // compact 3D layout: per grid site (plus a sentinel) the number of solid
-    // sites before it in raster order (= the particle index of a solid site)
-    // shifted left by 4, or'ed with the site's phase; per particle the
-    // directions (bits 0-17) whose neighbour is void or off the grid
-    const uint32_t *crank;
+    // compact 3D layout: per grid site (plus a sentinel) a row-table entry:
+    // bits 32-63 the number of solid sites before it in raster order (= the
+    // particle index of a solid site), bit 12 whether it is solid, bits 0-3,
+    // 4-7, 8-11 the phases of the sites at x - 1, x, x + 1 of its row (0 if
+    // void or off the grid); per particle the directions (bits 0-17) whose
+    // neighbour is void or off the grid
+    const uint64_t *crow;
     const uint32_t *cabs;
 };
 

@@ -101,6 +101,29 @@ struct State<3, 1> {
 #pragma unroll
         for (int c = 0; c < 3; ++c) P[c * ns + g] = v[c];
     }
+    // the same with 32-bit byte offsets from the array base (compact
+    // arrays of fewer than 2^32 bytes)
+    __device__ static void load_u(const void *U, uint32_t g, uint32_t ns, float hi[3], float lo[3]) {
+        const char *b = static_cast<const char *>(U);
+        const float4 a = *reinterpret_cast<const float4 *>(b + g * 16u);
+        const float2 c = *reinterpret_cast<const float2 *>(b + (ns * 16u + g * 8u));
+        hi[0] = a.x; hi[1] = a.y; hi[2] = a.z; lo[0] = a.w; lo[1] = c.x; lo[2] = c.y;
+    }
+    __device__ static void store_u(void *U, uint32_t g, uint32_t ns, const float hi[3], const float lo[3]) {
+        char *b = static_cast<char *>(U);
+        *reinterpret_cast<float4 *>(b + g * 16u) = make_float4(hi[0], hi[1], hi[2], lo[0]);
+        *reinterpret_cast<float2 *>(b + (ns * 16u + g * 8u)) = make_float2(lo[1], lo[2]);
+    }
+    __device__ static void load_v(const void *V, uint32_t g, uint32_t ns, float v[3]) {
+        const char *b = static_cast<const char *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = *reinterpret_cast<const float *>(b + (uint32_t(c) * ns + g) * 4u);
+    }
+    __device__ static void store_v(void *V, uint32_t g, uint32_t ns, const float v[3]) {
+        char *b = static_cast<char *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) *reinterpret_cast<float *>(b + (uint32_t(c) * ns + g) * 4u) = v[c];
+    }
 };
 
 // 3D, FP64: three planes for u and for v.
@@ -126,6 +149,29 @@ struct State<3, 0> {
         double *P = reinterpret_cast<double *>(V);
 #pragma unroll
         for (int c = 0; c < 3; ++c) P[c * ns + g] = v[c];
+    }
+    __device__ static void load_u(const void *U, uint32_t g, uint32_t ns, double hi[3], double lo[3]) {
+        const char *b = static_cast<const char *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            hi[c] = *reinterpret_cast<const double *>(b + (uint32_t(c) * ns + g) * 8u);
+            lo[c] = 0.0;
+        }
+    }
+    __device__ static void store_u(void *U, uint32_t g, uint32_t ns, const double hi[3], const double *) {
+        char *b = static_cast<char *>(U);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) *reinterpret_cast<double *>(b + (uint32_t(c) * ns + g) * 8u) = hi[c];
+    }
+    __device__ static void load_v(const void *V, uint32_t g, uint32_t ns, double v[3]) {
+        const char *b = static_cast<const char *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = *reinterpret_cast<const double *>(b + (uint32_t(c) * ns + g) * 8u);
+    }
+    __device__ static void store_v(void *V, uint32_t g, uint32_t ns, const double v[3]) {
+        char *b = static_cast<char *>(V);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) *reinterpret_cast<double *>(b + (uint32_t(c) * ns + g) * 8u) = v[c];
     }
 };
 
@@ -195,8 +241,8 @@ struct D4 {
 };
 template <>
 struct TT<0> {
-    using type = D4;  // k, r0, rc
-    __device__ static type make(const TypeRec &t) { return D4{t.k64, t.r0_64, t.rc64, 0.0}; }
+    using type = D4;  // k, r0, rc, rc^2
+    __device__ static type make(const TypeRec &t) { return D4{t.k64, t.r0_64, t.rc64, t.rc64 * t.rc64}; }
 };
 
 __device__ inline void comp_add(float &hi, float &lo, float delta) {
@@ -216,6 +262,15 @@ __device__ inline void comp_add_fma(float &hi, float &lo, float a, float b) {
     const float bp = t - hi;
     lo = (hi - (t - bp)) + (y - bp);
     hi = t;
+}
+
+// 1/sqrt(x) for a positive normal x: the hardware estimate y0 refined by
+// the second-order expansion of (1 - e)^(-1/2), e = 1 - x y0^2:
+// y = y0 (1 + e/2 + 3 e^2 / 8), whose error is of order e^3.
+__device__ inline double rsqrt_pos(double x) {
+    const double y0 = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y0, y0, 1.0);
+    return fma(y0 * e, fma(e, 0.375, 0.5), y0);
 }
 
 __device__ inline double wave_sum(double x) {
@@ -313,6 +368,82 @@ struct SiteStore {
     __device__ void v(void *V, const R *w) const { S::store_v(V, g, ns, w); }
 };
 
+// ... or by 32-bit byte offsets in the compact 3D arrays ...
+template <int DIM, int PREC>
+struct SiteStore32 {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    uint32_t g, ns;
+    __device__ void u(void *U, const R *hi, const R *lo) const { S::store_u(U, g, ns, hi, lo); }
+    __device__ void v(void *V, const R *w) const { S::store_v(V, g, ns, w); }
+};
+
+// ... or in the compact 3D arrays, addressed by 32-bit byte offsets (arrays
+// of fewer than 2^32 bytes).  Displacements are two planes of ns records:
+// 16-byte (FP64 x, y; FP32-compensated x_hi, y_hi, z_hi, x_lo) then 8-byte
+// (FP64 z; FP32-compensated y_lo, z_lo), so a record takes two aligned
+// loads; velocities are 24-byte (FP64) or 12-byte records.
+template <int PREC>
+struct CState {
+    using R = typename State<3, PREC>::R;
+    struct __attribute__((aligned(8))) D3 { double a[3]; };
+    struct __attribute__((aligned(4))) F3 { float a[3]; };
+    __device__ static void load_u(const void *U, uint32_t q, uint32_t ns, R hi[3], R lo[3]) {
+        const char *b = static_cast<const char *>(U);
+        if constexpr (PREC == 1) {
+            const float4 a = *reinterpret_cast<const float4 *>(b + q * 16u);
+            const float2 c = *reinterpret_cast<const float2 *>(b + (ns * 16u + q * 8u));
+            hi[0] = a.x; hi[1] = a.y; hi[2] = a.z; lo[0] = a.w; lo[1] = c.x; lo[2] = c.y;
+        } else {
+            const double2 a = *reinterpret_cast<const double2 *>(b + q * 16u);
+            hi[0] = a.x; hi[1] = a.y;
+            hi[2] = *reinterpret_cast<const double *>(b + (ns * 16u + q * 8u));
+            lo[0] = 0.0; lo[1] = 0.0; lo[2] = 0.0;
+        }
+    }
+    __device__ static void store_u(void *U, uint32_t q, uint32_t ns, const R hi[3], const R lo[3]) {
+        char *b = static_cast<char *>(U);
+        if constexpr (PREC == 1) {
+            *reinterpret_cast<float4 *>(b + q * 16u) = make_float4(hi[0], hi[1], hi[2], lo[0]);
+            *reinterpret_cast<float2 *>(b + (ns * 16u + q * 8u)) = make_float2(lo[1], lo[2]);
+        } else {
+            *reinterpret_cast<double2 *>(b + q * 16u) = make_double2(hi[0], hi[1]);
+            *reinterpret_cast<double *>(b + (ns * 16u + q * 8u)) = hi[2];
+        }
+    }
+    __device__ static void load_v(const void *V, uint32_t q, R v[3]) {
+        if constexpr (PREC == 1) {
+            const F3 t = *reinterpret_cast<const F3 *>(static_cast<const char *>(V) + q * 12u);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = t.a[c];
+        } else {
+            const D3 t = *reinterpret_cast<const D3 *>(static_cast<const char *>(V) + q * 24u);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[c] = t.a[c];
+        }
+    }
+    __device__ static void store_v(void *V, uint32_t q, const R v[3]) {
+        if constexpr (PREC == 1) {
+            F3 t;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) t.a[c] = v[c];
+            *reinterpret_cast<F3 *>(static_cast<char *>(V) + q * 12u) = t;
+        } else {
+            D3 t;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) t.a[c] = v[c];
+            *reinterpret_cast<D3 *>(static_cast<char *>(V) + q * 24u) = t;
+        }
+    }
+};
+template <int PREC>
+struct CStore {
+    using R = typename State<3, PREC>::R;
+    uint32_t q, ns;
+    __device__ void u(void *U, const R *hi, const R *lo) const { CState<PREC>::store_u(U, q, ns, hi, lo); }
+    __device__ void v(void *V, const R *w) const { CState<PREC>::store_v(V, q, w); }
+};
+
 // ... or, in the 2D sweeps, by 32-bit byte offsets from the array base
 // (the sweeps run lattices and batches of fewer than 2^28 sites, so a
 // 16-byte record's offset fits), which the accesses take as base + offset.
@@ -386,30 +517,126 @@ __device__ inline void integrate_site(const StepParams &P, const ST &st, uint8_t
     }
 }
 
+// Spring p -> q in direction d from the displacements of both ends: the
+// vector and squared length, the critical-stretch test (Eq. 1-2, strict
+// r > rc, FP64 where FP32 cannot decide) and the margin of a break.
+template <int DIM, int PREC>
+struct SpringEval {
+    using R = typename State<DIM, PREC>::R;
+    R dv[DIM];
+    R r2;
+    bool brk;
+    bool have64;     // d64 / r64 hold the FP64 vector and length
+    double margin;
+    double e64[DIM];
+    double d64[DIM];
+    double r64;
+};
+
+template <int DIM, int PREC>
+__device__ __attribute__((always_inline)) inline void spring_eval(
+    const StepParams &P, const typename TT<PREC>::type &T, int ti, int d, const typename State<DIM, PREC>::R *uph,
+    const typename State<DIM, PREC>::R *upl, const typename State<DIM, PREC>::R *uqh,
+    const typename State<DIM, PREC>::R *uql, SpringEval<DIM, PREC> &o) {
+    using R = typename State<DIM, PREC>::R;
+    using G = Geo<DIM>;
+    const R a = R(P.a);
+    const R hy = R(kHalfSqrt3 * P.a);
+    // lattice vector X0_q - X0_p
+    R e[DIM];
+    if constexpr (DIM == 2) {
+        e[0] = R(G::ex(d)) * a;
+        e[1] = R(G::ey(d)) * hy;
+        o.e64[0] = G::ex(d) * P.a;
+        o.e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            e[c] = R(G::off(d, c)) * a;
+            o.e64[c] = double(G::off(d, c)) * P.a;
+        }
+    }
+    o.r2 = R(0);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        o.dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
+        o.r2 += o.dv[c] * o.dv[c];
+    }
+    o.margin = 0.0;
+    o.r64 = 0.0;
+    o.have64 = false;
+    if constexpr (PREC == 1) {
+        // FP32 test; inside the band (or above rc) the FP64 test decides
+        if (o.r2 > T.z) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                o.d64[c] = o.e64[c] + ((double(uqh[c]) - double(uph[c])) + (double(uql[c]) - double(upl[c])));
+                s2 += o.d64[c] * o.d64[c];
+            }
+            o.r64 = sqrt(s2);
+            o.have64 = true;
+            const double rc = P.types[ti].rc64;
+            o.brk = o.r64 > rc;
+            o.margin = (o.r64 - rc) / rc;
+        } else {
+            o.brk = false;
+        }
+    } else if constexpr (DIM == 3) {
+        // FP64, 3D: r^2 against rc^2 (the decision r > rc, except within an
+        // ulp of rc^2); the length only for a break's margin
+        o.brk = o.r2 > T.w;
+        if (o.brk) {
+            o.r64 = sqrt(double(o.r2));
+            o.margin = (o.r64 - T.z) / T.z;
+        }
+    } else {
+        o.r64 = sqrt(double(o.r2));
+        o.have64 = true;
+        o.brk = o.r64 > T.z;
+        if (o.brk) o.margin = (o.r64 - T.z) / T.z;
+    }
+}
+
+// Eq. 2 force of an intact spring added to the force on p.
+template <int DIM, int PREC>
+__device__ __attribute__((always_inline)) inline void spring_force_add(const typename TT<PREC>::type &T,
+                                                                       SpringEval<DIM, PREC> &o,
+                                                                       typename State<DIM, PREC>::R *F) {
+    if constexpr (PREC == 1) {
+        const float rinv = __builtin_amdgcn_rsqf(o.r2);  // r2 is a normal number
+        const float coef = fmaf(-T.y, rinv, T.x);        // k (r - r0) / r
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, o.dv[c], F[c]);
+    } else if constexpr (DIM == 3) {
+        // k (r - r0) / r = k - k r0 / r from 1 / r
+        const double coef = fma(-(T.x * T.y), rsqrt_pos(double(o.r2)), T.x);
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) F[c] += coef * o.dv[c];
+    } else {
+        const double coef = T.x * (o.r64 - T.y) / o.r64;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            F[c] += coef * o.dv[c];
+            o.d64[c] = o.dv[c];
+        }
+    }
+}
+
 // ------------------------------------------------------------ step kernel
 // One time step of one site: all incident springs in direction order
 // (break test, Eq. 1-2 force), then the integrator.  Everything is read and
 // written through P, so a caller may point the state arrays at LDS.
-//
-// CMP selects the compact 3D layout: g is then the particle index (state,
-// flags and break bits are per particle, stride P.nsites = the padded
-// particle count), gg the grid index of its site, and neighbours are found
-// through the grid's prefix-count table P.crank; the break bits of a
-// particle also mark its absent springs (neighbour void or off the grid),
-// whose directions are listed in P.cabs.  The spring arithmetic is shared,
-// so both layouts produce the same bits.
-template <int DIM, int PREC, int MODE, bool CMP = false>
+template <int DIM, int PREC, int MODE>
 __device__ __attribute__((always_inline)) inline void step_site(
     const StepParams &P, const typename TT<PREC>::type *tt, const double *mass_s,
     const typename State<DIM, PREC>::R *imass_s, int g, int i, int j, int k, uint8_t fp, double *red,
-    int step_local, int gg = 0) {
+    int step_local) {
     using S = State<DIM, PREC>;
     using R = typename S::R;
     using G = Geo<DIM>;
     using Mask = typename G::Mask;
     using TTy = typename TT<PREC>::type;
-    const R a = R(P.a);
-    const R hy = R(kHalfSqrt3 * P.a);
     R uph[DIM], upl[DIM];
     S::load_u(P.u_in, g, P.nsites, uph, upl);
     const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
@@ -434,19 +661,10 @@ __device__ __attribute__((always_inline)) inline void step_site(
     for (int t = 0; t < kGrp; ++t) {
         const int d = d0 + t;
         const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
-        if constexpr (CMP) {
-            // an absent or broken spring reads the particle's own entry
-            const bool gone = (mask >> d) & 1;
-            const uint32_t cr = P.crank[gone ? gg : gg + ddi + P.nx * (ddj + P.ny * ddk)];
-            inb[t] = true;
-            qs[t] = int(cr >> 4);
-            fqs[t] = uint8_t(cr & 15u);
-        } else {
-            const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-            inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
-            qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
-            fqs[t] = P.flags[qs[t]];
-        }
+        const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+        inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+        qs[t] = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+        fqs[t] = P.flags[qs[t]];
         S::load_u(P.u_in, qs[t], P.nsites, uqhs[t], uqls[t]);
     }
 #pragma unroll
@@ -454,78 +672,34 @@ __device__ __attribute__((always_inline)) inline void step_site(
         const int d = d0 + t;
         if (!inb[t]) continue;
         const uint8_t fq = fqs[t];
-        if (!CMP && fq == kVoid) continue;
+        if (fq == kVoid) continue;
         const bool fwd = d < G::NF;
-        int myrank = rank;
+        const int myrank = rank;
         if (fwd) ++rank;
         if (mask & (Mask(1) << d)) continue;
         const R *uqh = uqhs[t];
         const R *uql = uqls[t];
-        // lattice vector X0_q - X0_p
-        R e[DIM];
-        double e64[DIM];
-        if constexpr (DIM == 2) {
-            e[0] = R(G::ex(d)) * a;
-            e[1] = R(G::ey(d)) * hy;
-            e64[0] = G::ex(d) * P.a;
-            e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                e[c] = R(G::off(d, c)) * a;
-                e64[c] = double(G::off(d, c)) * P.a;
-            }
-        }
-        R dv[DIM];
-        R r2 = R(0);
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
-            r2 += dv[c] * dv[c];
-        }
         const int pb = flag_phase(fq);
         const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
         const TTy T = tt[ti];
-        bool brk;
-        double margin = 0.0;
-        double d64[DIM];
-        double r64 = 0.0;
-        bool have64 = false;
-        if constexpr (PREC == 1) {
-            // FP32 test; inside the band (or above rc) the FP64 test decides
-            if (r2 > T.z) {
-                double s2 = 0.0;
-#pragma unroll
-                for (int c = 0; c < DIM; ++c) {
-                    d64[c] = e64[c] + ((double(uqh[c]) - double(uph[c])) +
-                                       (double(uql[c]) - double(upl[c])));
-                    s2 += d64[c] * d64[c];
-                }
-                r64 = sqrt(s2);
-                have64 = true;
-                const double rc = P.types[ti].rc64;
-                brk = r64 > rc;
-                margin = (r64 - rc) / rc;
-            } else {
-                brk = false;
-            }
-        } else {
-            r64 = sqrt(double(r2));
-            have64 = true;
-            brk = r64 > T.z;
-            if (brk) margin = (r64 - T.z) / T.z;
-        }
+        SpringEval<DIM, PREC> o;
+        spring_eval<DIM, PREC>(P, T, ti, d, uph, upl, uqh, uql, o);
+        const bool brk = o.brk;
+        const double margin = o.margin;
+        double *d64 = o.d64;
+        double &r64 = o.r64;
+        const R *dv = o.dv;
+        const double *e64 = o.e64;
         if (brk) {
             if (commit) {
                 newmask |= Mask(1) << d;
                 if (fwd) {
-                    if constexpr (CMP) myrank = __popc(~P.cabs[g] & ((1u << d) - 1u));
                     const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
                     if (idx < P.ev_cap) {
                         lsm_event ev;
                         ev.increment = P.ctl->inc;
                         ev.step = P.ctl->step_base + step_local;
-                        ev.spring_id = int64_t(P.sbase[CMP ? gg : g]) + myrank;
+                        ev.spring_id = int64_t(P.sbase[g]) + myrank;
                         ev.margin = margin;
                         P.events[idx] = ev;
                     }
@@ -533,24 +707,12 @@ __device__ __attribute__((always_inline)) inline void step_site(
             }
             continue;
         }
-        if constexpr (PREC == 1) {
-            const float rinv = __builtin_amdgcn_rsqf(r2);  // r2 is a normal number
-            const float coef = fmaf(-T.y, rinv, T.x);  // k (r - r0) / r
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, dv[c], F[c]);
-        } else {
-            const double coef = T.x * (r64 - T.y) / r64;
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-                F[c] += coef * dv[c];
-                d64[c] = dv[c];
-            }
-        }
+        spring_force_add<DIM, PREC>(T, o, F);
         if constexpr (MODE == kEnd) {
             if (fwd) {
                 // virial (Eq. 7) and potential energy (Eq. 1) in FP64
                 const TypeRec &T64 = P.types[ti];
-                if (!have64) {
+                if (!o.have64) {
                     double s2 = 0.0;
 #pragma unroll
                     for (int c = 0; c < DIM; ++c) {
@@ -637,12 +799,26 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
 // Interior step of a 3D lattice in the compact layout: one thread per
 // particle (raster order, which is the canonical particle order), state,
 // flags and break bits stored per particle, so a wavefront's loads and
-// stores touch only solid sites; the spring arithmetic is the gather
-// kernel's.  P's state pointers point at the compact arrays.
+// stores touch only solid sites.  The 18 neighbours lie in 9 grid rows
+// (x-lines); one 64-bit entry of the row table per row -- the particle
+// index of the row's site at the particle's x, whether that site is solid,
+// and the phases of it and its two x-neighbours -- gives the indices and
+// phases of the neighbours in that row (raster order makes a row's solid
+// sites consecutive particles).  Every load of a particle is issued before
+// any of its stores; the events of forward springs that break are logged
+// after all loads (the test is redone for the margin), before the update.
+// Arithmetic and summation order are the gather kernel's, so state, break
+// bits and events are bitwise the same.
 template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local) {
-    using R = typename State<3, PREC>::R;
+    constexpr int GRP = 6;  // neighbour loads per group (9 or 18, or the next group's loads in
+                            // flight during the current one, measured slower)
+    using CS = CState<PREC>;
+    using R = typename CS::R;
+    using G = Geo<3>;
     using TTy = typename TT<PREC>::type;
+    constexpr int NG = G::ND / GRP;
+    static_assert(G::ND % GRP == 0, "groups must tile the 18 directions");
     __shared__ TTy tt[kMaxTypes];
     __shared__ double mass_s[LSM_MAX_PHASES];
     __shared__ R imass_s[LSM_MAX_PHASES];
@@ -652,8 +828,6 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
         imass_s[threadIdx.x] = R(1.0 / P.mass[threadIdx.x]);
     }
     __syncthreads();
-    // each XCD takes a contiguous run of workgroups (neighbouring planes
-    // share its L2)
     const int b = blockIdx.x;
     const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
     const int p = lb * kBlock + int(threadIdx.x);
@@ -661,17 +835,101 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     const uint32_t pc = P.plist[p];
     const int i = int(pc & 1023u), j = int((pc >> 10) & 2047u), k = int(pc >> 21);
     const int gg = i + P.nx * (j + P.ny * k);
+    const uint32_t ns = uint32_t(P.nsites);
+    R uph[3], upl[3], w[3];
+    CS::load_u(P.u_in, uint32_t(p), ns, uph, upl);
+    CS::load_v(P.v, uint32_t(p), w);
+    const uint32_t mask = reinterpret_cast<const uint32_t *>(P.mask)[p];
+    const uint8_t fp = P.flags[p];
+    // row entries: slot (dj + 1) * 3 + (dk + 1); a row off the grid reads
+    // the particle's own entry (all its springs there are absent)
+    uint64_t row[9];
+#pragma unroll
+    for (int sl = 0; sl < 9; ++sl) {
+        const int dj = sl / 3 - 1, dk = sl % 3 - 1;
+        const bool in = j + dj >= 0 && j + dj < P.ny && k + dk >= 0 && k + dk < P.nz;
+        const uint32_t gq = uint32_t(in ? gg + P.nx * (dj + P.ny * dk) : gg);
+        row[sl] = *reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(P.crow) + gq * 8u);
+    }
+    const uint32_t qmax = uint32_t(P.n_part - 1);
+    // neighbour in direction d: index (clamped, for absent springs) and phase
+    auto nbr = [&](int d, uint32_t &q, int &pb) {
+        const int dx = G::di(d, 0), sl = (G::dj(d) + 1) * 3 + (G::dk(d) + 1);
+        const uint64_t e = row[sl];
+        pb = int((e >> (4 * (dx + 1))) & 15u);
+        if (sl == 4) {
+            q = uint32_t(p + dx);
+        } else {
+            const uint32_t r = uint32_t(e >> 32);
+            q = dx < 0 ? r - 1u : (dx > 0 ? r + uint32_t((e >> 12) & 1u) : r);
+        }
+        q = min(q, qmax);
+    };
+    const int pa = flag_phase(fp);
+    R F[3] = {R(0), R(0), R(0)};
+    uint32_t newmask = mask, fbrk = 0;
+    R uqh[GRP][3], uql[GRP][3];
+    int pbs[GRP];
+#pragma unroll
+    for (int gi = 0; gi < NG; ++gi) {
+#pragma unroll
+        for (int t = 0; t < GRP; ++t) {
+            uint32_t q;
+            nbr(gi * GRP + t, q, pbs[t]);
+            CS::load_u(P.u_in, q, ns, uqh[t], uql[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < GRP; ++t) {
+            const int d = gi * GRP + t;
+            if (mask & (1u << d)) continue;
+            const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pbs[t];
+            const TTy T = tt[ti];
+            SpringEval<3, PREC> o;
+            spring_eval<3, PREC>(P, T, ti, d, uph, upl, uqh[t], uql[t], o);
+            if (o.brk) {
+                newmask |= 1u << d;
+                if (d < G::NF) fbrk |= 1u << d;
+                continue;
+            }
+            spring_force_add<3, PREC>(T, o, F);
+        }
+    }
+    // (before the update, which advances uph / upl in place)
+    while (fbrk) {
+        const int d = __builtin_ctz(fbrk);
+        fbrk &= fbrk - 1u;
+        uint32_t q;
+        int pb;
+        nbr(d, q, pb);
+        R qh[3], ql[3];
+        CS::load_u(P.u_in, q, ns, qh, ql);
+        const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
+        SpringEval<3, PREC> o;
+        spring_eval<3, PREC>(P, tt[ti], ti, d, uph, upl, qh, ql, o);
+        const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+        if (idx < P.ev_cap) {
+            lsm_event ev;
+            ev.increment = P.ctl->inc;
+            ev.step = P.ctl->step_base + step_local;
+            ev.spring_id = int64_t(P.sbase[gg]) + __popc(~P.cabs[p] & ((1u << d) - 1u));
+            ev.margin = o.margin;
+            P.events[idx] = ev;
+        }
+    }
     double red[1] = {0.0};
-    step_site<3, PREC, kMid, true>(P, tt, mass_s, imass_s, p, i, j, k, P.flags[p], red, step_local, gg);
+    integrate_site<3, PREC, kMid>(P, CStore<PREC>{uint32_t(p), ns}, fp, mass_s[pa], imass_s[pa], uph, upl, F, w,
+                                  red);
+    if (newmask != mask) reinterpret_cast<uint32_t *>(P.mask)[p] = newmask;
 }
 
 // Copies between the site-grid state (displacements u_grid, velocities
-// v_grid, break bits m_grid, stride P.nsites) and the compact one (stride
-// cn); the compact break bits also carry the absent-spring bits.
+// v_grid, break bits m_grid, stride P.nsites) and the compact one; the
+// compact break bits also carry the absent-spring bits.
 template <int PREC, bool TO_COMPACT>
 __global__ __launch_bounds__(256) void k_pack_c3(StepParams P, void *u_grid, void *v_grid, uint32_t *m_grid,
-                                                 void *u_c, void *v_c, uint32_t *m_c, int64_t cn) {
+                                                 void *u_c, void *v_c, uint32_t *m_c, uint32_t cn) {
     using S = State<3, PREC>;
+    using CS = CState<PREC>;
     using R = typename S::R;
     const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
     if (p >= P.n_part) return;
@@ -681,12 +939,12 @@ __global__ __launch_bounds__(256) void k_pack_c3(StepParams P, void *u_grid, voi
     if constexpr (TO_COMPACT) {
         S::load_u(u_grid, g, P.nsites, hi, lo);
         S::load_v(v_grid, g, P.nsites, w);
-        S::store_u(u_c, p, cn, hi, lo);
-        S::store_v(v_c, p, cn, w);
+        CS::store_u(u_c, uint32_t(p), cn, hi, lo);
+        CS::store_v(v_c, uint32_t(p), w);
         m_c[p] = m_grid[g] | P.cabs[p];
     } else {
-        S::load_u(u_c, p, cn, hi, lo);
-        S::load_v(v_c, p, cn, w);
+        CS::load_u(u_c, uint32_t(p), cn, hi, lo);
+        CS::load_v(v_c, uint32_t(p), w);
         S::store_u(u_grid, g, P.nsites, hi, lo);
         S::store_v(v_grid, g, P.nsites, w);
         m_grid[g] = m_c[p] & ~P.cabs[p];
@@ -1752,14 +2010,15 @@ hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step
 
 hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t s, int to_compact, void *u_grid,
                           void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn) {
+    const uint32_t ncn = uint32_t(cn);
     const dim3 grid(unsigned((p.n_part + 255) / 256)), block(256);
     if (p.n_part <= 0) return hipSuccess;
     if (to_compact) {
-        if (prec) hipLaunchKernelGGL((k_pack_c3<1, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
-        else hipLaunchKernelGGL((k_pack_c3<0, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+        if (prec) hipLaunchKernelGGL((k_pack_c3<1, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
+        else hipLaunchKernelGGL((k_pack_c3<0, true>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
     } else {
-        if (prec) hipLaunchKernelGGL((k_pack_c3<1, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
-        else hipLaunchKernelGGL((k_pack_c3<0, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, cn);
+        if (prec) hipLaunchKernelGGL((k_pack_c3<1, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
+        else hipLaunchKernelGGL((k_pack_c3<0, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
     }
     return hipGetLastError();
 }
