@@ -148,6 +148,17 @@ def notched_composite(L: int = 96, seed: int = 7, depth_frac: float = 0.2) -> np
     return edge_notch(circular_inclusions(L, seed=seed), int(round(depth_frac * L)))
 
 
+def uniform_phase(L: int, phase: int = SOFT) -> np.ndarray:
+    """A single-phase square image (e.g. all soft)."""
+    return np.full((L, L), phase, dtype=np.uint8)
+
+
+def checkerboard(L: int, cell: int = 1) -> np.ndarray:
+    """STIFF and SOFT squares of side ``cell`` alternating in x and y."""
+    yy, xx = np.mgrid[0:L, 0:L]
+    return np.where(((xx // cell) + (yy // cell)) % 2 == 0, STIFF, SOFT).astype(np.uint8)
+
+
 BATCH_SIZES = (64, 96, 128, 192, 256)
 
 

@@ -175,34 +175,100 @@ def curve_strength(pred: np.ndarray) -> np.ndarray:
     return pred[:, :CURVE_POINTS].max(axis=1)
 
 
+def calibrate_gate(sur: Surrogate, images: np.ndarray, lab: Labels, target_p95: float = 0.05,
+                   max_gate: float = 0.05) -> dict:
+    """Spread gate from a held-out split: the largest threshold (at most
+    max_gate) whose accepted specimens -- spread at or below it -- have a
+    95th-percentile modulus error within target_p95 on that split.  A gate of
+    0 sends every specimen to the model."""
+    pred, spread, _ = sur.predict(images)
+    err = np.abs(pred[:, -1] - lab.modulus) / np.abs(lab.modulus)
+    order = np.argsort(spread, kind="stable")
+    best = 0.0
+    for m in range(1, len(order) + 1):
+        g = float(spread[order[m - 1]])
+        if g > max_gate:
+            break
+        if np.quantile(err[order[:m]], 0.95) <= target_p95:
+            best = g
+    acc = spread <= best
+    return dict(gate=best, val_n=len(images), val_accept_rate=float(acc.mean()),
+                val_accepted_p95=float(np.quantile(err[acc], 0.95)) if acc.any() else 0.0)
+
+
+@dataclass
+class Answers:
+    """The pipeline's answer per specimen: the ensemble's, or the model's
+    where the gate sent the specimen back to it."""
+    modulus: np.ndarray
+    strength: np.ndarray
+    curves: np.ndarray
+    fallback: np.ndarray          # bool per specimen
+    spread: np.ndarray
+    inference_s: float
+    fallback_s: float
+    fallback_labels: Labels | None
+
+
+def answer(sur: Surrogate, images: np.ndarray, gate: float, steps: int = 500, d_eps: float = 0.005,
+           repeats: int = 1) -> Answers:
+    """Gated inference: the ensemble mean where its modulus spread is at or
+    below the gate, the batched model's run of the specimen otherwise."""
+    pred, spread, t_inf = sur.predict(images, repeats=repeats)
+    fb = spread > gate
+    mod = pred[:, -1].copy()
+    cur = pred[:, :CURVE_POINTS].copy()
+    stg = curve_strength(pred)
+    fb_lab, t_fb = None, 0.0
+    if fb.any():
+        fb_lab = label(images[fb], steps=steps, d_eps=d_eps)
+        t_fb = fb_lab.seconds
+        mod[fb] = fb_lab.modulus
+        stg[fb] = fb_lab.strength
+        cur[fb] = fb_lab.curves
+    return Answers(mod, stg, cur, fb, spread, t_inf, t_fb, fb_lab)
+
+
 def evaluate(sur: Surrogate, images: np.ndarray, lab: Labels, gate: float = 0.05,
              steps: int = 500, d_eps: float = 0.005) -> dict:
     """Gated pipeline on a test split, scored against the model's own labels.
 
     Specimens whose ensemble spread exceeds the gate are re-run on the
-    batched model (their answer is the model's, error zero by definition);
-    the others keep the surrogate's prediction.  Throughput counts the
-    surrogate inference (median of five timed passes after an untimed one)
-    plus the fallback runs."""
-    pred, spread, t_inf = sur.predict(images, repeats=5)
-    true_mod = lab.modulus
-    err_mod = np.abs(pred[:, -1] - true_mod) / np.abs(true_mod)
-    err_str = np.abs(curve_strength(pred) - lab.strength) / np.abs(lab.strength)
-    fb = spread > gate
-    t_fb = 0.0
-    if fb.any():
-        fb_lab = label(images[fb], steps=steps, d_eps=d_eps)
-        t_fb = fb_lab.seconds
-    final_err = np.where(fb, 0.0, err_mod)
+    batched model and answered by it; the others keep the surrogate's
+    prediction.  Throughput counts the surrogate inference (median of five
+    timed passes after an untimed one) plus the fallback runs."""
+    a = answer(sur, images, gate, steps, d_eps, repeats=5)
+    pred, _, _ = sur.predict(images)
+    err_sur = np.abs(pred[:, -1] - lab.modulus) / np.abs(lab.modulus)
+    err_str_sur = np.abs(curve_strength(pred) - lab.strength) / np.abs(lab.strength)
+    err = np.abs(a.modulus - lab.modulus) / np.abs(lab.modulus)
+    err_str = np.abs(a.strength - lab.strength) / np.abs(lab.strength)
+    acc = ~a.fallback
     n = len(images)
     return dict(
-        n=n, gate=gate, fallback_rate=float(fb.mean()),
-        surrogate_modulus_err_mean=float(err_mod.mean()),
-        surrogate_modulus_err_p95=float(np.quantile(err_mod, 0.95)),
-        surrogate_strength_err_mean=float(err_str.mean()),
-        pipeline_modulus_err_mean=float(final_err.mean()),
-        pipeline_modulus_err_p95=float(np.quantile(final_err, 0.95)),
-        accepted_modulus_err_max=float(err_mod[~fb].max()) if (~fb).any() else 0.0,
-        inference_s=t_inf, fallback_s=t_fb,
-        specimens_per_hour=n / (t_inf + t_fb) * 3600.0,
+        n=n, gate=gate, fallback_rate=float(a.fallback.mean()),
+        surrogate_modulus_err_mean=float(err_sur.mean()),
+        surrogate_modulus_err_p95=float(np.quantile(err_sur, 0.95)),
+        surrogate_strength_err_mean=float(err_str_sur.mean()),
+        pipeline_modulus_err_mean=float(err.mean()),
+        pipeline_modulus_err_p95=float(np.quantile(err, 0.95)),
+        pipeline_strength_err_mean=float(err_str.mean()),
+        accepted_modulus_err_p95=float(np.quantile(err[acc], 0.95)) if acc.any() else 0.0,
+        accepted_modulus_err_max=float(err[acc].max()) if acc.any() else 0.0,
+        inference_s=a.inference_s, fallback_s=a.fallback_s,
+        specimens_per_hour=n / (a.inference_s + a.fallback_s) * 3600.0,
     )
+
+
+def amortized(res: dict, label_s: float, train_s: float, model_s_per_specimen: float) -> dict:
+    """Whole-pipeline cost including the labelling and training that built
+    the surrogate: specimens/hour over N specimens, and the N from which
+    the pipeline beats the batched model alone."""
+    per = (res["inference_s"] + res["fallback_s"]) / res["n"]
+    fixed = label_s + train_s
+    gain = model_s_per_specimen - per
+    be = fixed / gain if gain > 0 else float("inf")
+    out = {"fixed_s": fixed, "per_specimen_s": per, "break_even_specimens": be}
+    for N in (10 ** 5, 10 ** 6, 10 ** 7):
+        out[f"specimens_per_hour_at_{N}"] = N / (fixed + N * per) * 3600.0
+    return out

@@ -83,3 +83,15 @@ def compare_records(rec_o, rec_g, rtol, dim, upto_inc=None):
         assert rg["n_broken"] == ro["n_broken"]
         n += 1
     return n
+
+
+def first_set_difference(ev_a, ev_b, n_inc):
+    """First increment after which the sets of springs broken so far differ
+    between two runs (n_inc + 1 if they never do); a spring breaks once, so
+    the sets agree through increment n iff every increment's own set does."""
+    for n in range(1, n_inc + 1):
+        a = np.sort(ev_a["id"][ev_a["inc"] == n])
+        b = np.sort(ev_b["id"][ev_b["inc"] == n])
+        if not np.array_equal(a, b):
+            return n
+    return n_inc + 1
