@@ -423,6 +423,18 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y);
  * [batch][outputs]; writes the output gradient (device, may be NULL) and
  * the loss (device float, may be NULL)                                    */
 int lsm_cnn_mse(lsm_cnn *c, const float *target, float *dy, float *loss);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid allocation): lsm_cnn_mse
+ * with its per-workgroup loss partials in a fixed static device array (one
+ * per GPU, 256 KB, held until the process ends) instead of the bound
+ * workspace; calls no allocating routine.  dy (device FP32 [batch][outputs])
+ * and loss (device float) are required and are the only outputs: the
+ * network's own gradient buffer is not touched, so pass dy to
+ * lsm_cnn_backward.  Bitwise the same values as lsm_cnn_mse.  LSM_EINVAL
+ * when batch x outputs exceeds 65536 x 256; LSM_EHIP if the array's address
+ * cannot be obtained.  All calls on one GPU share its array: calls that
+ * overlap in time on the same GPU (other streams or threads) race.        */
+int lsm_cnn_mse_noalloc(lsm_cnn *c, const float *target, float *dy, float *loss);
 /* gradients of all parameters for output gradient dy (device; NULL uses
  * the one from lsm_cnn_mse); overwrites the gradient vector               */
 int lsm_cnn_backward(lsm_cnn *c, const float *dy);

@@ -15,7 +15,7 @@ from . import lsm as _lsm
 CNN_EXPORTS = (
     "lsm_cnn_create", "lsm_cnn_destroy", "lsm_cnn_last_error", "lsm_cnn_param_count",
     "lsm_cnn_layout", "lsm_cnn_workspace_bytes", "lsm_cnn_bind", "lsm_cnn_set_params",
-    "lsm_cnn_get_params", "lsm_cnn_get_grads", "lsm_cnn_forward", "lsm_cnn_mse",
+    "lsm_cnn_get_params", "lsm_cnn_get_grads", "lsm_cnn_forward", "lsm_cnn_mse", "lsm_cnn_mse_noalloc",
     "lsm_cnn_backward", "lsm_cnn_adam_step", "lsm_cnn_conv_forward", "lsm_cnn_read_buffer",
 )
 
@@ -53,6 +53,7 @@ def _load():
         getattr(L, nm).argtypes = [vp, vp]
     L.lsm_cnn_forward.argtypes = [vp, vp, i64, vp]
     L.lsm_cnn_mse.argtypes = [vp, vp, vp, vp]
+    L.lsm_cnn_mse_noalloc.argtypes = [vp, vp, vp, vp]
     L.lsm_cnn_backward.argtypes = [vp, vp]
     L.lsm_cnn_adam_step.argtypes = [vp, fl, fl, fl, fl, i64]
     L.lsm_cnn_conv_forward.argtypes = [vp, C.c_int, vp, vp, i64]
@@ -175,6 +176,13 @@ class Network:
         self._check(self._L.lsm_cnn_mse(self._h, _dptr(target), None, _dptr(self.loss)))
         self._leave(target)
         return self.loss
+
+    def mse_noalloc(self, target, dy, loss):
+        """lsm_cnn_mse_noalloc into caller tensors dy [batch, outputs] and
+        loss [1] (float32, on the network's device)."""
+        self._enter()
+        self._check(self._L.lsm_cnn_mse_noalloc(self._h, _dptr(target), _dptr(dy), _dptr(loss)))
+        self._leave(target, dy, loss)
 
     def backward(self, dy=None):
         self._enter()

@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -979,6 +980,30 @@ struct lsm_cnn {
 
 namespace {
 
+// Allocation-free loss (lsm_cnn_mse_noalloc): the per-workgroup loss
+// partials live in this file-scope device array, one copy per GPU, held
+// until the process ends.  Host code never passes the array's name to a
+// kernel (in host code it is only a stand-in for the symbol): the device
+// address of each GPU's copy is looked up once per device, with that device
+// current, and kept in scratch_ptr.
+constexpr int kMseScratch = 65536;  // partials: batch x outputs <= 65536 x kBlk
+__device__ __align__(256) float scratch[kMseScratch];
+constexpr int kMaxDevices = 64;
+float *scratch_ptr[kMaxDevices] = {};
+std::mutex scratch_mu;
+
+// Device address of this device's scratch array (nullptr on failure).
+float *device_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        scratch_ptr[dev] = static_cast<float *>(ptr);
+    }
+    return scratch_ptr[dev];
+}
+
 int cfail(lsm_cnn *c, int code, const std::string &msg) {
     if (c) c->err = msg;
     return code;
@@ -1246,6 +1271,27 @@ int lsm_cnn_mse(lsm_cnn *c, const float *target, float *dy, float *loss) {
     CHIP(c, hipGetLastError());
     if (dy) CHIP(c, hipMemcpyAsync(dy, c->dy, size_t(n) * 4, hipMemcpyDeviceToDevice, c->stream));
     if (loss) CHIP(c, hipMemcpyAsync(loss, c->loss, 4, hipMemcpyDeviceToDevice, c->stream));
+    return LSM_OK;
+}
+
+int lsm_cnn_mse_noalloc(lsm_cnn *c, const float *target, float *dy, float *loss) {
+    if (!c || !target || !dy || !loss) return LSM_EINVAL;
+    if (!c->bound || c->b_last < 1) return cfail(c, LSM_ESTATE, "forward first");
+    const int64_t n = c->b_last * c->cfg.outputs;
+    const int64_t nb = nblk(n);
+    if (nb > kMseScratch)
+        return cfail(c, LSM_EINVAL, "batch x outputs exceeds the allocation-free limit of " +
+                                        std::to_string(int64_t(kMseScratch) * kBlk));
+    int dev = 0;
+    CHIP(c, hipGetDevice(&dev));
+    float *part = device_scratch(dev);
+    if (!part) return cfail(c, LSM_EHIP, "hipGetSymbolAddress of the scratch array failed");
+    // the same kernels and summation order as lsm_cnn_mse; every partial the
+    // sum reads is written first, so the array needs no clearing
+    hipLaunchKernelGGL(k_mse, dim3(unsigned(nb)), dim3(kBlk), 0, c->stream, c->y, target, dy, part, n,
+                       1.0f / float(n));
+    hipLaunchKernelGGL(k_sum_loss, dim3(1), dim3(64), 0, c->stream, part, int(nb), 1.0f / float(n), loss);
+    CHIP(c, hipGetLastError());
     return LSM_OK;
 }
 
