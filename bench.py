@@ -1,17 +1,27 @@
 """Benchmark: spring-steps/s of the lattice spring model hot path on one GPU.
 
-Workload: 2048 x 2048 brick-and-mortar image -> triangular lattice
-(4,194,304 particles, 12,574,721 springs), FP32 forces with compensated FP32
-displacements, displacement-controlled tension in increments of 0.05 %
-strain, 2000 damped velocity Verlet steps per increment.  One bench "step"
-is one loading increment: strain increment + step-0 force evaluation, 2000
-fused step kernels (spring forces with critical-stretch breaking, force
-accumulation, integration), end-of-increment reductions and the break log.
+Headline workload: the 256^3 random-field voxel lattice (6,693,133
+particles, 56,137,660 face + edge springs), FP64 displacements and forces
+(the paper's arithmetic), displacement-controlled tension in increments of
+0.05 % strain, 2000 damped velocity Verlet steps per increment.  One bench
+"step" is one loading increment: strain increment + step-0 force
+evaluation, 2000 step kernels (spring forces with critical-stretch
+breaking, force accumulation, integration), end-of-increment reductions
+and the break log.
 
 spring-steps/s = springs in the list (broken ones included, they are still
-iterated) x timesteps / wall time.  The roofline object rates the dominant
-kernel (the fused step) by its algorithmic bytes per launch over its
-average duration measured with HIP events on the library's stream.
+iterated) x timesteps / wall time.  The roofline object rates the step
+kernel by the per-timestep bytes of the explicit spring-list model,
+B = N (2 s + 5) + 6 M (s: bytes of a particle's state, 48 in 3D FP64), over
+its average duration per step measured with HIP events on the library's
+stream; `traffic` is what rocprofv3 counted for the same kernel
+(profiles/), or null when the kernel source differs from the one counted.
+
+Further sections (each can be skipped): the same lattice in FP32 with
+compensated displacements; the 2048^2 brick-and-mortar lattice in both
+precisions over increments 41-80 (fracture and the stress peak); 4096
+batched specimens to failure with the oracle on one and on all host cores;
+the 32^2 lattice; the batched-model + surrogate pipeline.
 """
 from __future__ import annotations
 
@@ -19,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -28,18 +39,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = ("spring-steps/s (% HBM roofline); specimens/hour batched+surrogate "
           "@≤5% error")
-COUNTER_FILE = os.path.join(ROOT, "profiles", "c2_step_counters.json")
 # VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s
-# (78.6 TFLOP/s of non-packed FP32 FMA)
+# (78.6 TFLOP/s of non-packed FP32 or FP64 FMA)
 VALU_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
-WORKLOAD_NAMES = {
-    "c2": "c2 brick-and-mortar 2048x2048 triangular lattice, fp32 forces with compensated fp32 "
-          "displacements, 0.05% strain increments x 2000 steps",
-    "c3": "c3 256^3 simple-cubic voxel lattice from a thresholded Gaussian random field (40% solid, "
-          "largest cluster), face + edge springs, fp32 forces with compensated fp32 displacements, "
-          "0.05% strain increments x 2000 steps",
-}
 KERNEL_SRC = os.path.join(ROOT, "paper_2201_04565_amd", "csrc", "lsm_kernels.hip")
+COUNTERS = {"c3": os.path.join(ROOT, "profiles", "c3_step_counters.json"),
+            "c2": os.path.join(ROOT, "profiles", "c2_step_counters.json")}
+# bytes of a particle's state per step (read and written once each): 2D
+# FP32-compensated (u_hi, u_lo, v) 24, FP64 32; 3D 36 / 48
+STATE_BYTES = {(2, "fp32k"): 24, (2, "fp64"): 32, (3, "fp32k"): 36, (3, "fp64"): 48}
+KERNEL_NAMES = {
+    ("c3", "fp64"): "k_step_c3<0> (3D compact layout, fp64)",
+    ("c3", "fp32k"): "k_step_c3<1> (3D compact layout, fp32 forces, compensated fp32 displacements)",
+    ("c2", "fp32k"): "k_sweep2d_x2<1,1> (2D row sweep, two interior steps per launch, fp32 compensated)",
+    ("c2", "fp64"): "k_sweep2d<0,1,1,0> (2D row sweep, fp64)",
+}
 
 
 def kernel_hash() -> str:
@@ -47,16 +61,36 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_counters(launch):
-    """rocprofv3 counters of the C2 step kernel (HBM bytes and VALU
-    instructions per launch) from the committed summary, or None when
-    absent, taken on a different kernel source or another launch shape."""
+def host_cpu():
+    """CPU model and logical core count of this host."""
+    model = platform.processor() or "unknown"
     try:
-        with open(COUNTER_FILE) as f:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count() or 1
+
+
+def survey_bytes(dim, precision, n, m):
+    """Per-timestep bytes of the explicit spring-list model."""
+    return n * (2 * STATE_BYTES[(dim, precision)] + 5) + 6 * m
+
+
+def measured_counters(workload, precision, launch):
+    """rocprofv3 counters of the step kernel (HBM bytes and VALU
+    instructions per interior step) from the committed summary, or None when
+    absent, taken on a different kernel source or another launch."""
+    try:
+        with open(COUNTERS[workload]) as f:
             t = json.load(f)
-    except (OSError, ValueError):
+    except (OSError, ValueError, KeyError):
         return None
-    if t.get("kernel_src_sha256") != kernel_hash():
+    t = t.get(precision) if isinstance(t, dict) else None
+    if not t or t.get("kernel_src_sha256") != kernel_hash():
         return None
     want = {k: launch[k] for k in ("variant", "rows_per_wave", "prefetch")}
     if t.get("launch") != want:
@@ -64,8 +98,64 @@ def measured_counters(launch):
     return t
 
 
+def lattice_run(lsm, torch, wl, img, precision, warmup, timed, spi, workload, log):
+    """Loading increments on one lattice: `warmup` untimed, `timed` timed
+    (wall clock around them, HIP events around every interior-step chunk)."""
+    lat = lsm.Lattice.from_workload(wl, img, precision=precision, device="cuda:0")
+    launch = lat.launch()
+    log(f"{workload} {precision}: {lat.n} particles, {lat.m} springs, launch {launch}")
+    for i in range(warmup):
+        lat.apply_increment(wl["d_eps"])
+        lat.relax(spi)
+        if (i + 1) % 20 == 0:
+            log(f"  warm-up {i + 1}/{warmup}")
+    lat.read_state()
+    lat.set_timing(True)
+    lat.read_timing()  # clear
+    torch.cuda.synchronize()
+    lat.synchronize()
+    t0 = time.perf_counter()
+    for i in range(timed):
+        lat.apply_increment(wl["d_eps"])
+        lat.relax(spi)
+        if (i + 1) % 20 == 0:
+            log(f"  timed {i + 1}/{timed}")
+    lat.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec0 = lat.read_state()
+    kern_ms, kern_steps = lat.read_timing()
+    lat.set_timing(False)
+    dim = 3 if img.ndim == 3 else 2
+    step_s = kern_ms * 1e-3 / max(kern_steps, 1)   # events per interior step
+    B = survey_bytes(dim, precision, lat.n, lat.m)
+    spl = launch["steps_per_launch"]
+    implicit = lat.step_bytes() / spl               # this layout's own bytes per step
+    counters = measured_counters(workload, precision, launch)
+    roof = {"bound": "hbm", "achieved": B / step_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": B / step_s / 1e9 / HBM_PEAK_GBS,
+            "traffic": counters["bytes_per_step"] if counters else None,
+            "bytes_per_step": B, "bytes_model": "N(2s+5)+6M per timestep, s=%d" % STATE_BYTES[(dim, precision)],
+            "implicit_bytes_per_step": implicit,
+            "implicit_frac": implicit / step_s / 1e9 / HBM_PEAK_GBS,
+            "kernel": KERNEL_NAMES.get((workload, precision), launch["variant"])}
+    if counters:
+        roof["traffic_GBs"] = counters["bytes_per_step"] / step_s / 1e9
+        if counters.get("valu_insts_per_step"):
+            # VALU issue rate: wavefront instructions x 64 lanes per step time
+            roof["valu_frac"] = counters["valu_insts_per_step"] * 64 / step_s / 1e12 / VALU_PEAK_T
+    out = dict(value=lat.m * timed * spi / wall, unit="spring-steps/s", ms_per_increment=wall * 1e3 / timed,
+               particles=lat.n, springs=lat.m, steps_per_increment=spi, increments_timed=timed,
+               increments_before=warmup, strain_at_end=rec0["eps"], broken_springs_at_end=rec0["n_broken"],
+               step_kernel_us=step_s * 1e6, launch=launch, roofline=roof)
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, img, steps: int):
-    """The FP64 oracle, single thread, on one increment of the same lattice."""
+    """The FP64 oracle, single thread, on part of one increment of the same
+    lattice (per-step cost does not change along the run)."""
     import oracle
     prm = oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], a=wl.get("a", 1.0),
                         k_face=wl.get("k_face", 1.0), k_diag=wl.get("k_diag", 1.0),
@@ -75,9 +165,11 @@ def cpu_baseline(wl, img, steps: int):
     net.apply_increment(wl["d_eps"])
     net.relax(steps)
     dt = time.perf_counter() - t0
+    model, ncpu = host_cpu()
     return dict(value=net.m * steps / dt, unit="spring-steps/s", cores=1, kind="oracle",
-                sample=f"full {'x'.join(str(d) for d in img.shape[::-1])} lattice, 1 increment x "
-                       f"{steps} steps (+ step-0 evaluation), FP64, single thread, {dt:.1f} s")
+                sample=f"full {'x'.join(str(d) for d in img.shape[::-1])} lattice, 1 increment, "
+                       f"{steps} steps (+ step-0 evaluation), FP64, single thread, {dt:.1f} s",
+                cpu_model=model, host_logical_cpus=ncpu)
 
 
 def batched_c4(args, torch, inputs, lsm):
@@ -138,10 +230,28 @@ def batched_c4(args, torch, inputs, lsm):
     return out
 
 
-def cpu_c4(args, inputs):
-    """Oracle on one host core: one specimen per side for a prefix of
-    increments, extrapolated to the batch's increments (per-step cost is
-    constant because broken springs stay in the list)."""
+def _oracle_specimen(task):
+    """One specimen through `inc` increments on the oracle (one process)."""
+    import oracle
+    from paper_2201_04565_amd import inputs
+    seed, inc = task
+    wl = inputs.WORKLOADS["c4"]
+    img = inputs.batch_specimens(1, seed0=seed)[0]
+    net = oracle.Net.lattice(img, oracle.Params(k=wl["k"], s=wl["s"], mass=wl["mass"], dt=wl["dt"],
+                                                gamma=wl["gamma"]))
+    t0 = time.perf_counter()
+    for _ in range(inc):
+        net.apply_increment(wl["d_eps"])
+        net.relax(wl["steps"])
+    return img.shape[0], time.perf_counter() - t0
+
+
+def cpu_c4(args, inputs, pool):
+    """The oracle on the host: one core (one specimen per side for a prefix
+    of increments, extrapolated to the batch's increments; per-step cost is
+    constant because broken springs stay in the list) and all cores (one
+    specimen per core, the first specimens of the batch, run together in
+    `pool`, worker processes started before the GPU was touched)."""
     import numpy as np
 
     import oracle
@@ -159,9 +269,27 @@ def cpu_c4(args, inputs):
             net.relax(wl["steps"])
         per_step[L] = (time.perf_counter() - t0) / (args.cpu_c4_inc * wl["steps"])
     total = sum(per_step[int(L)] * wl["max_inc"] * wl["steps"] for L in sizes)
-    return dict(value=len(imgs) / total * 3600.0, unit="specimens/hour", cores=1, kind="oracle",
-                sample=f"one specimen per side, {args.cpu_c4_inc} increments each, "
-                       f"extrapolated to {wl['max_inc']} increments per specimen")
+    model, ncpu = host_cpu()
+    out = dict(value=len(imgs) / total * 3600.0, unit="specimens/hour", cores=1, kind="oracle",
+               sample=f"one specimen per side, {args.cpu_c4_inc} increments each, "
+                      f"extrapolated to {wl['max_inc']} increments per specimen",
+               cpu_model=model, host_logical_cpus=ncpu)
+    # all cores: specimens of the batch spread over the worker processes; the
+    # single-core time of the same work over the wall time is the speedup
+    # the host's cores give, applied to the single-core rate
+    P = pool._processes
+    tasks = [(1000 + i, args.cpu_c4_inc) for i in range(3 * P)]
+    t0 = time.perf_counter()
+    res = pool.map(_oracle_specimen, tasks, chunksize=1)
+    wall = time.perf_counter() - t0
+    single = sum(per_step.get(int(L), float(np.mean(list(per_step.values())))) * args.cpu_c4_inc * wl["steps"]
+                 for L, _ in res)
+    speedup = single / wall
+    out["all_cores"] = dict(value=out["value"] * speedup, unit="specimens/hour", cores=P, kind="oracle",
+                            speedup_over_one_core=speedup,
+                            sample=f"{len(tasks)} specimens of the batch (seeds 1000-{999 + len(tasks)}) over "
+                                   f"{P} processes, {args.cpu_c4_inc} increments each, {wall:.1f} s wall")
+    return out
 
 
 def cnn_forward_flops(size=128, channels=(32, 64, 128, 128, 256), hidden=256, outputs=65):
@@ -257,10 +385,12 @@ def cnn_kernels(torch, batch=512, size=128, iters=10):
 
 def surrogate_c5(args):
     """Batched model + surrogate pipeline on 128 x 128 inclusion specimens:
-    labels from the batched model, a 5-member ensemble trained on them, a 5 %
-    spread gate with fallback to the model; specimens/hour of the pipeline
-    and of the batched model alone, and the modulus error against the
-    model's own labels."""
+    labels from the batched model, a 5-member ensemble trained on them, a
+    spread gate calibrated on a validation split (at most 5 %, accepted
+    95th-percentile modulus error within 5 % there) with fallback to the
+    model; specimens/hour of the pipeline and of the batched model alone,
+    the modulus error against the model's own labels, and the cost
+    including the labelling and training that built the surrogate."""
     from paper_2201_04565_amd import surrogate as S
 
     def log(msg):
@@ -268,22 +398,29 @@ def surrogate_c5(args):
 
     t0 = time.perf_counter()
     img_tr = S.specimen_images(args.sur_train, 10 ** 6)
+    img_va = S.specimen_images(args.sur_val, 3 * 10 ** 6)
     img_te = S.specimen_images(args.sur_test, 2 * 10 ** 6)
     log(f"images generated ({time.perf_counter() - t0:.1f} s)")
     lab_tr = S.label(img_tr, log=log)
+    lab_va = S.label(img_va, log=log)
     lab_te = S.label(img_te, log=log)
     sur = S.Surrogate(k=5, batch=512, seed=0)
     sur.fit(img_tr, S.targets(lab_tr), epochs=args.sur_epochs, lr=2e-3, log=log)
-    res = S.evaluate(sur, img_te, lab_te, gate=0.05)
+    cal = S.calibrate_gate(sur, img_va, lab_va, target_p95=0.05, max_gate=0.05)
+    res = S.evaluate(sur, img_te, lab_te, gate=cal["gate"])
+    model_per = lab_te.seconds / len(img_te)
     res.update(
-        workload=f"{args.sur_train} train / {args.sur_test} test 128x128 inclusion specimens, "
-                 f"labels = 64-point sigma_xx curve + modulus (64 x 0.5% x 500 steps, fp32), "
-                 f"5-member BF16 CNN ensemble, {args.sur_epochs} epochs, gate 5% spread",
+        workload=f"{args.sur_train} train / {args.sur_val} validation / {args.sur_test} test 128x128 "
+                 f"inclusion specimens, labels = 64-point sigma_xx curve + modulus (64 x 0.5% x 500 steps, "
+                 f"fp32), 5-member BF16 CNN ensemble, {args.sur_epochs} epochs, gate calibrated on the "
+                 f"validation split",
+        calibration=cal,
         label_specimens_per_hour=len(img_tr) / lab_tr.seconds * 3600.0,
         batched_model_specimens_per_hour=len(img_te) / lab_te.seconds * 3600.0,
         train_s=sur.train_seconds,
         train_TFLOPs=3 * cnn_forward_flops() * 5 * args.sur_epochs * (len(img_tr) // 512) * 512
         / sur.train_seconds / 1e12,
+        amortized=S.amortized(res, lab_tr.seconds + lab_va.seconds, sur.train_seconds, model_per),
         total_s=time.perf_counter() - t0)
     res["pipeline_over_batched_model"] = res["specimens_per_hour"] / res["batched_model_specimens_per_hour"]
     return res
@@ -292,141 +429,86 @@ def surrogate_c5(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("c2", "c3"), default="c2",
-                    help="c2: 2048^2 brick-and-mortar (default); c3: 256^3 random-field voxels")
-    ap.add_argument("--steps", type=int, default=None,
-                    help="timed loading increments (default 198 for c2, 5 for c3)")
-    ap.add_argument("--warmup", type=int, default=2, help="untimed loading increments")
+    ap.add_argument("--workload", choices=("c3", "c2"), default="c3",
+                    help="headline lattice: c3 256^3 random-field voxels (default), c2 2048^2 bricks")
+    ap.add_argument("--dtype", choices=("f64", "f32k"), default="f64",
+                    help="headline arithmetic: f64 (the paper's, default) or fp32 forces with "
+                         "compensated fp32 displacements")
+    ap.add_argument("--steps", type=int, default=10, help="timed loading increments of the headline")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed loading increments before them")
     ap.add_argument("--steps-per-inc", type=int, default=None)
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=30, help="oracle timesteps of the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--kernel", choices=("auto", "sweep", "sweep2", "gather"), default="auto",
-                    help="2D step kernel: auto (the two-step sweep), sweep (one step per launch), "
-                         "sweep2 (two steps), gather (one thread per site)")
-    ap.add_argument("--launch", default="0,1", metavar="ROWS,PREFETCH",
-                    help="sweep launch: rows per wavefront (0: the library's occupancy-model "
-                         "default), prefetch depth")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the launch with lsm_autotune instead of --launch")
+    ap.add_argument("--only-headline", action="store_true", help="skip every further section")
+    ap.add_argument("--no-c3-fp32k", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--c2-from", type=int, default=40, help="c2 section: increments before the timed ones")
+    ap.add_argument("--c2-steps", type=int, default=40, help="c2 section: timed increments")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched C4 measurement")
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--plain-per-size", type=int, default=2)
     ap.add_argument("--cpu-c4-inc", type=int, default=1)
-    ap.add_argument("--no-surrogate", action="store_true",
-                    help="skip the batched-model + surrogate pipeline (on by default at reduced size)")
+    ap.add_argument("--cpu-workers", type=int, default=16, help="processes of the all-core oracle run")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cnn-bench", action="store_true", help="also time the surrogate network kernels")
     ap.add_argument("--no-c1", action="store_true", help="skip the small-lattice (C1) section")
     ap.add_argument("--sur-train", type=int, default=4096,
                     help="training specimens (the full C5 configuration: 50000)")
+    ap.add_argument("--sur-val", type=int, default=1024, help="validation specimens (C5: 5000)")
     ap.add_argument("--sur-test", type=int, default=1024, help="test specimens (C5: 5000)")
     ap.add_argument("--sur-epochs", type=int, default=10, help="epochs (C5: 20)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
-    if args.steps is None:
-        args.steps = 198 if args.workload == "c2" else 5
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (a single "
               "lattice would shard as x-slabs with a halo exchange, a batch by specimen)",
               file=sys.stderr)
         sys.exit(2)
+    if args.only_headline:
+        args.no_c3_fp32k = args.no_c2 = args.no_batch = args.no_c1 = args.no_surrogate = True
+    pool = None
+    if not args.no_batch and not args.no_cpu:
+        # the all-core oracle workers start now, before anything touches the
+        # GPU, and wait idle until the GPU sections are done
+        import multiprocessing as mp
+        pool = mp.get_context("spawn").Pool(max(1, min(args.cpu_workers, os.cpu_count() or 1)))
 
     import torch
 
     from paper_2201_04565_amd import inputs, lsm
 
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    prec = "fp64" if args.dtype == "f64" else "fp32k"
     wl = inputs.WORKLOADS[args.workload]
     spi = args.steps_per_inc or wl["steps"]
-    img = inputs.c2_image() if args.workload == "c2" else inputs.c3_image()
-    lat = lsm.Lattice.from_workload(wl, img, precision="fp32k", device="cuda:0")
-    print(f"[bench] lattice built: {lat.n} particles, {lat.m} springs", file=sys.stderr,
-          flush=True)
-    if args.workload == "c3":
-        pass  # 3D: the gather kernel, one thread per particle
-    elif args.autotune:
-        lat.autotune(100)
-    else:
-        rows, pf = (int(v) for v in args.launch.split(","))
-        lat.set_launch(args.kernel, rows)
-        lat.set_prefetch(pf)
-    launch = lat.launch()
-    print(f"[bench] launch: {launch}", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        lat.apply_increment(wl["d_eps"])
-        lat.relax(spi)
-    lat.read_state()
-    lat.set_timing(True)
-    lat.read_timing()  # clear
-    torch.cuda.synchronize()
-    lat.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        lat.apply_increment(wl["d_eps"])
-        lat.relax(spi)
-        if (i + 1) % 50 == 0:
-            print(f"[bench] {i + 1}/{args.steps} increments", file=sys.stderr, flush=True)
-    lat.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    rec = lat.read_state()
-    kern_ms, kern_launches = lat.read_timing()
-    lat.set_timing(False)
-
-    springs = lat.m
-    timesteps = args.steps * spi
-    value = springs * timesteps / wall
-    avg_step_s = kern_ms * 1e-3 / max(kern_launches, 1)  # event time per interior step
-    spl = launch["steps_per_launch"]
-    launch_s = avg_step_s * spl                            # per launch of the step kernel
-    bytes_per_launch = lat.step_bytes()
-    hbm_gbs = bytes_per_launch / launch_s / 1e9
-    counters = measured_counters(launch) if args.workload == "c2" else None
-    if args.workload == "c3":
-        kname = "k_step<3,1,1> (fp32 compensated, one thread per particle)"
-    else:
-        kname = {2: "k_sweep2d_x2<1,1> (fp32 compensated, two interior steps per launch)",
-                 1: "k_sweep2d<1,1,1,0> (fp32 compensated, one interior step per launch)"}[spl]
-    roofline = {"bound": "hbm", "achieved": hbm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": hbm_gbs / HBM_PEAK_GBS,
-                "traffic": counters.get("bytes_per_launch") if counters else None,
-                "bytes_per_launch": bytes_per_launch, "steps_per_launch": spl, "kernel": kname}
-    if counters and counters.get("valu_insts_per_launch"):
-        # VALU issue rate: wavefront instructions x 64 lanes per launch time
-        alu = counters["valu_insts_per_launch"] * 64 / launch_s / 1e12
-        if alu / VALU_PEAK_T > roofline["frac"]:
-            roofline.update({"bound": "alu", "achieved": alu, "peak": VALU_PEAK_T,
-                             "unit": "T VALU lane-instructions/s", "frac": alu / VALU_PEAK_T,
-                             "hbm_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS})
-        else:
-            roofline["alu_frac"] = alu / VALU_PEAK_T
-
+    img = inputs.c3_image() if args.workload == "c3" else inputs.c2_image()
+    head = lattice_run(lsm, torch, wl, img, prec, args.warmup, args.steps, spi, args.workload, log)
+    names = {"c3": "c3 256^3 simple-cubic voxel lattice from a thresholded Gaussian random field (40% solid, "
+                   "largest cluster), face + edge springs, 0.05% strain increments x 2000 steps",
+             "c2": "c2 brick-and-mortar 2048x2048 triangular lattice, 0.05% strain increments x 2000 steps"}
+    arith = {"fp64": "fp64 positions and forces", "fp32k": "fp32 forces, compensated fp32 displacements"}
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": head["value"],
         "unit": "spring-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": head["ms_per_increment"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if prec == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD_NAMES[args.workload],
-            "particles": lat.n,
-            "springs": springs,
-            "steps_per_increment": spi,
-            "strain_at_end": rec["eps"],
-            "broken_springs_at_end": rec["n_broken"],
-            "step_kernel_us": avg_step_s * 1e6,
-            "step_kernel_launch_us": launch_s * 1e6,
-            "launch": launch,
-            "hbm_fraction_of_wall": bytes_per_launch * timesteps / spl / wall / 1e9 / HBM_PEAK_GBS,
+            "workload": f"{names[args.workload]}, {arith[prec]}",
+            **{k: head[k] for k in ("particles", "springs", "steps_per_increment", "strain_at_end",
+                                    "broken_springs_at_end", "step_kernel_us", "launch")},
         },
-        "roofline": roofline,
+        "roofline": head["roofline"],
     }
     if args.copy_ref:
         # plain copy kernel of known size: reads and writes copy_ref MiB once
@@ -434,29 +516,41 @@ def main():
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
-            torch.mul(src, 1.0, out=dst)  # one elementwise kernel: reads and writes MIB MiB
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         out["copy_ref_mib"] = args.copy_ref
+        del src, dst
+    if args.workload == "c3" and prec == "fp64" and not args.no_c3_fp32k:
+        out["c3_fp32k"] = lattice_run(lsm, torch, wl, img, "fp32k", args.warmup, args.steps, spi, "c3", log)
+    if not args.no_c2:
+        w2 = inputs.WORKLOADS["c2"]
+        img2 = inputs.c2_image()
+        out["c2"] = {"workload": names["c2"] + f", increments {args.c2_from + 1}-{args.c2_from + args.c2_steps}",
+                     "mall_caveat": "the state fits the 256 MB Infinity Cache, so the HBM fraction may count "
+                                    "cache-served bytes"}
+        for p2 in ("fp32k", "fp64"):
+            out["c2"][p2] = lattice_run(lsm, torch, w2, img2, p2, args.c2_from, args.c2_steps, w2["steps"],
+                                        "c2", log)
     if not args.no_batch:
-        del lat
-        torch.cuda.empty_cache()
-        print("[bench] batched specimens", file=sys.stderr, flush=True)
+        log("batched specimens")
         out["batched"] = batched_c4(args, torch, inputs, lsm)
         if not args.no_cpu:
-            out["batched"]["cpu_baseline"] = cpu_c4(args, inputs)
-    if args.workload == "c2" and not args.no_c1:
-        print("[bench] c1 small lattice", file=sys.stderr, flush=True)
+            out["batched"]["cpu_baseline"] = cpu_c4(args, inputs, pool)
+    if not args.no_c1:
+        log("c1 small lattice")
         out["c1"] = small_c1(args, inputs, lsm)
     if args.cnn_bench:
-        print("[bench] surrogate network kernels", file=sys.stderr, flush=True)
+        log("surrogate network kernels")
         out["cnn"] = cnn_kernels(torch)
-    if not args.no_surrogate and args.workload == "c2":
-        print("[bench] surrogate pipeline", file=sys.stderr, flush=True)
+    if not args.no_surrogate:
+        log("surrogate pipeline")
         out["surrogate"] = surrogate_c5(args)
     if not args.no_cpu:
-        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps if args.workload == "c2"
-                                           else max(args.cpu_steps // 30, 2))
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(wl, img, args.cpu_steps)
+    if pool is not None:
+        pool.close()
+        pool.join()
     print(json.dumps(out))
 
 
