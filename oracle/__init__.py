@@ -56,6 +56,7 @@ def lib():
                                   vp, C.c_int]
         L.orc_set_dynamics.argtypes = [vp, dbl, dbl, C.c_int]
         L.orc_set_strain_rate.argtypes = [vp, dbl]
+        L.orc_set_spring_law.argtypes = [vp, C.c_int, dbl]
         L.orc_apply_increment.argtypes = [vp, dbl]
         L.orc_relax.argtypes = [vp, i64]
         L.orc_record_state.argtypes = [vp, P(Record)]
@@ -159,6 +160,12 @@ class Net:
     # --- dynamics ------------------------------------------------------
     def set_dynamics(self, dt, gamma, predictor=0):
         lib().orc_set_dynamics(self._h, float(dt), float(gamma), int(predictor))
+
+    def set_spring_law(self, law, c=0.0):
+        """0 linear (Eq. 1-2), 1 recoverable in compression, 2 cubic with
+        coefficient c; see the spring-law comment of the C source."""
+        if lib().orc_set_spring_law(self._h, int(law), float(c)) != 0:
+            raise ValueError("bad spring law")
 
     def set_strain_rate(self, rate):
         """Constant strain-rate loading (per unit time) from the next step."""

@@ -76,6 +76,10 @@ typedef struct orc_net {
     double *k, *r0, *rc;
     uint8_t *broken;
     double omega; /* reference volume of Eq. 7 */
+    /* spring law (0 linear, 1 recoverable in compression, 2 cubic) and the
+       cubic coefficient */
+    int law;
+    double law_c;
     /* dynamics */
     double dt, gamma;
     int predictor; /* 0 affine, 1 grips only */
@@ -323,15 +327,46 @@ orc_net *orc_lattice(int kind, const uint8_t *img, int64_t nx, int64_t ny, int64
 
 /* ------------------------------------------------------------- dynamics */
 
+/* Spring laws.  The linear truncated spring of Eq. 1-2 is law 0.  The
+ * paper's closing section names extensions of it; two are built:
+ *   law 1, recoverable stiffness: a broken spring still resists compression,
+ *     with its intact stiffness, while shorter than its rest length
+ *     (U = k (r - r0)^2 / 2 for r < r0, nothing otherwise);
+ *   law 2, cubic (non-linear) elasticity: U = k d^2 / 2 + k c d^4 / (4 r0^2)
+ *     with d = r - r0, so the force magnitude is k d (1 + c d^2 / r0^2).
+ * The break rule (an intact spring longer than rc breaks) is the same for
+ * all laws. */
+static int spring_acts(const orc_net *N, int64_t s, double r)
+{
+    if (!N->broken[s]) return 1;
+    return N->law == 1 && r < N->r0[s];
+}
+
+static double spring_coef(const orc_net *N, int64_t s, double r)
+{
+    double dl = r - N->r0[s];
+    if (N->law == 2) return N->k[s] * dl * (1.0 + N->law_c * dl * dl / (N->r0[s] * N->r0[s])) / r;
+    return N->k[s] * dl / r;
+}
+
+static double spring_energy(const orc_net *N, int64_t s, double r)
+{
+    double dl = r - N->r0[s];
+    double u = 0.5 * N->k[s] * dl * dl;
+    if (N->law == 2) u += 0.25 * N->k[s] * N->law_c * dl * dl * dl * dl / (N->r0[s] * N->r0[s]);
+    return u;
+}
+
 /* Eq. 2 with the break rule: loops the spring list in id order, skipping
- * broken springs.  A spring longer than rc is (if commit) marked broken and
- * logged, and gives no force in this evaluation either way. */
+ * broken springs (unless the law lets them act).  An intact spring longer
+ * than rc is (if commit) marked broken and logged, and gives no force in
+ * this evaluation either way. */
 static int forces(orc_net *N, double *F, int commit)
 {
     const int dim = N->dim;
     memset(F, 0, (size_t)N->n * dim * sizeof(double));
     for (int64_t s = 0; s < N->m; ++s) {
-        if (N->broken[s]) continue;
+        if (N->broken[s] && N->law != 1) continue;
         int64_t p = N->sp[s], q = N->sq[s];
         double d[3] = {0.0, 0.0, 0.0};
         double r2 = 0.0;
@@ -340,15 +375,16 @@ static int forces(orc_net *N, double *F, int commit)
             r2 += d[e] * d[e];
         }
         double r = sqrt(r2);
-        if (r > N->rc[s]) {
+        if (!N->broken[s] && r > N->rc[s]) {
             if (commit) {
                 N->broken[s] = 1;
                 if (log_event(N, s, (r - N->rc[s]) / N->rc[s]) != ORC_OK) return ORC_ENOMEM;
             }
             continue;
         }
-        /* force on p from q is +k (r - r0) d / r with d = x_q - x_p */
-        double coef = N->k[s] * (r - N->r0[s]) / r;
+        if (!spring_acts(N, s, r)) continue;
+        /* force on p from q is +coef d with d = x_q - x_p (Eq. 2 for law 0) */
+        double coef = spring_coef(N, s, r);
         for (int e = 0; e < dim; ++e) {
             F[p * dim + e] += coef * d[e];
             F[q * dim + e] -= coef * d[e];
@@ -369,6 +405,15 @@ static void accelerations(orc_net *N)
                 N->a[p * dim + e] = (N->F[p * dim + e] - N->gamma * N->v[p * dim + e]) / N->mass[p];
         }
     }
+}
+
+/* Spring law of the network (see spring_acts); 0 linear by default. */
+int orc_set_spring_law(orc_net *N, int law, double c)
+{
+    if (law < 0 || law > 2 || !isfinite(c)) return ORC_EINVAL;
+    N->law = law;
+    N->law_c = c;
+    return ORC_OK;
 }
 
 void orc_set_dynamics(orc_net *N, double dt, double gamma, int predictor)
@@ -475,7 +520,10 @@ int orc_record_state(orc_net *N, orc_record *R)
     double pe = 0.0, ke = 0.0;
     int64_t nb = 0;
     for (int64_t s = 0; s < N->m; ++s) {
-        if (N->broken[s]) { nb++; continue; }
+        if (N->broken[s]) {
+            nb++;
+            if (N->law != 1) continue;
+        }
         int64_t p = N->sp[s], q = N->sq[s];
         double d[3] = {0.0, 0.0, 0.0}, r2 = 0.0;
         for (int e = 0; e < dim; ++e) {
@@ -483,11 +531,12 @@ int orc_record_state(orc_net *N, orc_record *R)
             r2 += d[e] * d[e];
         }
         double r = sqrt(r2);
-        if (r > N->rc[s]) continue; /* Heaviside factor of Eq. 1 */
-        double coef = N->k[s] * (r - N->r0[s]) / r;
+        if (!N->broken[s] && r > N->rc[s]) continue; /* Heaviside factor of Eq. 1 */
+        if (!spring_acts(N, s, r)) continue;
+        double coef = spring_coef(N, s, r);
         for (int aa = 0; aa < dim; ++aa)
             for (int bb = 0; bb < dim; ++bb) S[aa * 3 + bb] += d[aa] * (coef * d[bb]);
-        pe += 0.5 * N->k[s] * (r - N->r0[s]) * (r - N->r0[s]);
+        pe += spring_energy(N, s, r);
     }
     for (int64_t p = 0; p < N->n; ++p) {
         for (int aa = 0; aa < dim; ++aa) {
@@ -578,7 +627,7 @@ double orc_potential_energy(const orc_net *N)
     const int dim = N->dim;
     double pe = 0.0;
     for (int64_t s = 0; s < N->m; ++s) {
-        if (N->broken[s]) continue;
+        if (N->broken[s] && N->law != 1) continue;
         int64_t p = N->sp[s], q = N->sq[s];
         double r2 = 0.0;
         for (int e = 0; e < dim; ++e) {
@@ -586,8 +635,9 @@ double orc_potential_energy(const orc_net *N)
             r2 += d * d;
         }
         double r = sqrt(r2);
-        if (r > N->rc[s]) continue;
-        pe += 0.5 * N->k[s] * (r - N->r0[s]) * (r - N->r0[s]);
+        if (!N->broken[s] && r > N->rc[s]) continue;
+        if (!spring_acts(N, s, r)) continue;
+        pe += spring_energy(N, s, r);
     }
     return pe;
 }
