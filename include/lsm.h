@@ -105,8 +105,25 @@ typedef struct {
     int32_t precision;
     int32_t predictor;
     int32_t void_value;
-    int32_t reserved;
+    int32_t spring_law;   /* LSM_SPRING_* (0: the linear spring of Eq. 1-2) */
+    double law_c;         /* cubic coefficient c of LSM_SPRING_CUBIC */
 } lsm_config;
+
+/* Spring laws.  The paper's closing section keeps broken springs in the
+ * list so that their stiffness may recover under compression, and names
+ * non-linear elasticity among the extensions of the linear spring:
+ *   LSM_SPRING_LINEAR: U = k (r - r0)^2 / 2 (Eq. 1), broken springs inert;
+ *   LSM_SPRING_RECOVER: as linear, and a broken spring shorter than its rest
+ *     length acts with its intact stiffness (contact of crack faces);
+ *   LSM_SPRING_CUBIC: U = k d^2 / 2 + k c d^4 / (4 r0^2), d = r - r0, force
+ *     magnitude k d (1 + c d^2 / r0^2) (c > 0 stiffening, c < 0 softening).
+ * The break rule is the same for all.  Lattices with a law other than
+ * LSM_SPRING_LINEAR run the gather kernel (LSM_KERNEL_AUTO resolves to it;
+ * asking for another kernel is LSM_EINVAL); batches take the linear law
+ * only.                                                                   */
+#define LSM_SPRING_LINEAR 0
+#define LSM_SPRING_RECOVER 1
+#define LSM_SPRING_CUBIC 2
 
 /* State record at the end of a relaxation.
  *  eps: applied engineering strain (sum of increments).
@@ -254,6 +271,28 @@ int lsm_set_velocities(lsm_handle *h, const double *v);
  * (increment, step); 0 leaves the state untouched (such springs still give
  * no force).  Synchronises.                                               */
 int lsm_eval_forces(lsm_handle *h, double *f, int commit_breaks);
+
+/* Local fields of the current state (Section 3.1: the virial stress of
+ * Eq. 7 over a neighbourhood domain and the Lagrangian strain of the field
+ * figure, Eq. 8), FP64, written asynchronously on the bound stream to
+ * caller-owned DEVICE arrays stress and strain, each [n_particles][dim][dim]
+ * in particle order (both required).
+ *   stress: sigma = (1 / (|D| V)) sum_{k in D} s^k with
+ *     s^k_ab = 1/2 sum over k's intact springs (x_l - x_k)_a f^{kl}_b
+ *              - m_k v_a v_b  (f^{kl}: Eq. 2 force on k from l; tension
+ *     positive), V the site area (sqrt3/2 a^2) or volume (a^3), and D = {k}
+ *     for radius 0 or k and every particle it shares a spring with (broken
+ *     or not) for radius 1;
+ *   strain: (J^T J - I) / 2 (the Green-Lagrange reading of Eq. 8) with J the
+ *     least-squares map (sum d d0^T)(sum d0 d0^T)^-1 of the vectors to the
+ *     first nearest neighbours (2D: the six lattice neighbours, 3D: the six
+ *     face neighbours; broken springs included) from the reference to the
+ *     current configuration; NaN where those vectors do not span the space.
+ * With radius 1 the strain array also serves as the temporary of the
+ * per-particle sums.  LSM_EINVAL for other radii or null arrays; LSM_ESTATE
+ * between lsm_apply_strain_increment and lsm_relax (velocities are then
+ * half-step values).                                                      */
+int lsm_local_fields(lsm_handle *h, int radius, double *stress, double *strain);
 
 /* Bitwise checkpoint of the dynamic state (displacements, velocities,
  * broken flags, clock, events).  lsm_save_state with buf == NULL returns

@@ -88,6 +88,7 @@ struct lsm_handle {
     uint8_t *d_cflag = nullptr;
     uint32_t *d_cmask = nullptr, *d_cabs = nullptr;
     uint64_t *d_crow = nullptr;
+    int32_t *d_site_of = nullptr, *d_part_of = nullptr;  // particle -> site, site -> particle (-1: void)
     void *d_U[2] = {nullptr, nullptr};
     void *d_V = nullptr, *d_A = nullptr;
     double *d_f64 = nullptr, *d_partials = nullptr;
@@ -266,6 +267,8 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     p.plist = h->plist.empty() ? nullptr : h->d_plist;
     p.c_blocks = h->c_blocks;
     p.red_blocks = p.plist ? p.c_blocks : p.nblocks;
+    p.law = h->cfg.spring_law;
+    p.law_c = h->cfg.law_c;
     return p;
 }
 
@@ -277,19 +280,21 @@ bool small_fits(const lsm_handle *h) {
     return h->dim == 2 && h->nsites > 0 && lsm::small_lds_bytes(h->nsites, h->prec) <= lsm::kSmallLdsBytes;
 }
 // (not under constant-rate loading, which moves the grips before every step)
+bool linear_law(const lsm_handle *h) { return h->cfg.spring_law == LSM_SPRING_LINEAR; }
 bool use_small(const lsm_handle *h) {
-    return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h) && h->rate == 0.0;
+    return (h->variant == LSM_KERNEL_SMALL || h->variant == LSM_KERNEL_AUTO) && small_fits(h) && h->rate == 0.0 &&
+           linear_law(h);
 }
 // 3D interior steps in the compact layout: the default for 3D lattices
 // (not under constant-rate loading, whose grip kernel moves site-grid state)
 bool use_compact(const lsm_handle *h) {
-    return h->dim == 3 && !h->crow.empty() && h->rate == 0.0 &&
+    return h->dim == 3 && !h->crow.empty() && h->rate == 0.0 && linear_law(h) &&
            (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT);
 }
 bool use_sweep(const lsm_handle *h) {
     return h->dim == 2 && ((h->variant == LSM_KERNEL_AUTO && !small_fits(h)) || h->variant == LSM_KERNEL_SWEEP ||
                            h->variant == LSM_KERNEL_SWEEP2) &&
-           h->nsites <= lsm::kSweepMaxSites;
+           h->nsites <= lsm::kSweepMaxSites && linear_law(h);
 }
 // interior steps in pairs per launch: the default for 2D FP32-compensated lattices
 // (not under constant-rate loading: the grips move between the two steps)
@@ -542,6 +547,9 @@ int lsm_create(const lsm_config *cfg, lsm_handle **out) {
     }
     if (c.lattice == LSM_LATTICE_SC3D && (!finite_nonneg(c.k_face) || !finite_nonneg(c.k_diag)))
         return LSM_EINVAL;
+    if (c.spring_law != LSM_SPRING_LINEAR && c.spring_law != LSM_SPRING_RECOVER && c.spring_law != LSM_SPRING_CUBIC)
+        return LSM_EINVAL;
+    if (!std::isfinite(c.law_c)) return LSM_EINVAL;
     lsm_handle *h = new (std::nothrow) lsm_handle();
     if (!h) return LSM_ENOMEM;
     h->cfg = c;
@@ -691,7 +699,7 @@ int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
     return LSM_OK;
 }
 
-constexpr int kRegions = 23;
+constexpr int kRegions = 25;
 
 static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
     size_t o = 0;
@@ -723,6 +731,8 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         h->cflag.size() * 4,                          // 20 compact break + absent bits
         h->cabs.size() * 4,                           // 21 absent-spring bits
         h->crow.size() * 8,                           // 22 row table per site
+        size_t(h->n) * 4,                             // 23 site of each particle
+        ns * 4,                                       // 24 particle of each site
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -774,6 +784,8 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_cmask = reinterpret_cast<uint32_t *>(w + off[20]);
     h->d_cabs = reinterpret_cast<uint32_t *>(w + off[21]);
     h->d_crow = reinterpret_cast<uint64_t *>(w + off[22]);
+    h->d_site_of = reinterpret_cast<int32_t *>(w + off[23]);
+    h->d_part_of = reinterpret_cast<int32_t *>(w + off[24]);
     h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     {
@@ -798,6 +810,15 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     HIPCHK(h, hipMemcpyAsync(h->d_sbase, h->sbase.data(), h->sbase.size() * 4, hipMemcpyHostToDevice, h->stream));
     if (!h->plist.empty())
         HIPCHK(h, hipMemcpyAsync(h->d_plist, h->plist.data(), h->plist.size() * 4, hipMemcpyHostToDevice, h->stream));
+    if (h->n > 0) {
+        std::vector<int32_t> part_of(size_t(h->nsites), -1);
+        for (int64_t c = 0; c < h->n; ++c) part_of[size_t(h->site_of[size_t(c)])] = int32_t(c);
+        HIPCHK(h, hipMemcpyAsync(h->d_site_of, h->site_of.data(), size_t(h->n) * 4, hipMemcpyHostToDevice,
+                                 h->stream));
+        HIPCHK(h, hipMemcpyAsync(h->d_part_of, part_of.data(), part_of.size() * 4, hipMemcpyHostToDevice,
+                                 h->stream));
+        HIPCHK(h, hipStreamSynchronize(h->stream));  // part_of is a local vector
+    }
     if (!h->crow.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_cflag, h->cflag.data(), h->cflag.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_cabs, h->cabs.data(), h->cabs.size() * 4, hipMemcpyHostToDevice, h->stream));
@@ -1180,6 +1201,18 @@ int lsm_eval_forces(lsm_handle *h, double *f, int commit_breaks) {
     return LSM_OK;
 }
 
+int lsm_local_fields(lsm_handle *h, int radius, double *stress, double *strain) {
+    int rc = check_bound(h);
+    if (rc) return rc;
+    if (!stress || !strain || (radius != 0 && radius != 1)) return fail(h, LSM_EINVAL, "bad local-field arguments");
+    if (h->half) return fail(h, LSM_ESTATE, "local fields need full-step velocities (after lsm_relax)");
+    StepParams p = make_params(h, h->cur, h->cur);
+    const double vsite = h->dim == 2 ? kHalfSqrt3 * h->cfg.a * h->cfg.a : h->cfg.a * h->cfg.a * h->cfg.a;
+    HIPCHK(h, lsm::launch_local_fields(p, h->dim, h->prec, h->stream, h->d_site_of, h->d_part_of, radius, vsite,
+                                       stress, strain));
+    return LSM_OK;
+}
+
 // ---- checkpoint: header, u (current buffer), v, acc, mask, ctl, record, events
 struct StateHeader {
     uint32_t magic, version;
@@ -1317,6 +1350,8 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
         return fail(h, LSM_EINVAL, "unknown kernel variant");
     if (variant == LSM_KERNEL_COMPACT && h->dim != 3)
         return fail(h, LSM_EINVAL, "the compact layout is 3D only");
+    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && !linear_law(h))
+        return fail(h, LSM_EINVAL, "spring laws other than the linear one run the gather kernel only");
     if (variant == LSM_KERNEL_COMPACT && h->built && h->crow.empty())
         return fail(h, LSM_EINVAL, "lattice too large for the compact layout");
     if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");
@@ -1790,7 +1825,7 @@ int lsm_batch_create(const lsm_config *cfg, int64_t n, const uint8_t *const *img
                      lsm_batch **out) {
     if (!cfg || !out || n < 1 || !imgs || !dims) return LSM_EINVAL;
     *out = nullptr;
-    if (cfg->lattice != LSM_LATTICE_TRI2D) return LSM_EINVAL;
+    if (cfg->lattice != LSM_LATTICE_TRI2D || cfg->spring_law != LSM_SPRING_LINEAR) return LSM_EINVAL;
     // validate the configuration through the single-lattice constructor
     lsm_handle *probe = nullptr;
     int rc = lsm_create(cfg, &probe);

@@ -116,6 +116,10 @@ struct StepParams {
     // neighbour is void or off the grid
     const uint64_t *crow;
     const uint32_t *cabs;
+    // spring law (LSM_SPRING_*) and the cubic coefficient; only the gather
+    // kernel (and the local fields) take a law other than the linear one
+    int32_t law;
+    double law_c;
 };
 
 // Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.
@@ -150,6 +154,16 @@ hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t
 hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t stream, int step_local);
 hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t stream, int to_compact, void *u_grid,
                           void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn);
+// Local fields of the state in u_in / v / mask (particle order, FP64
+// [n][dim][dim]): virial stress over the radius-0 or radius-1 domain per
+// site volume vsite, and the Lagrangian strain (NaN where undefined).
+hipError_t launch_local_fields(const StepParams &p, int dim, int prec, hipStream_t stream, const int32_t *site_of,
+                               const int32_t *part_of, int radius, double vsite, double *stress, double *strain);
+// Local fields of the state in u_in / v / mask (particle order, FP64
+// [n][dim][dim]): virial stress over the radius-0 or radius-1 domain per
+// site volume vsite, and the Lagrangian strain (NaN where undefined).
+hipError_t launch_local_fields(const StepParams &p, int dim, int prec, hipStream_t stream, const int32_t *site_of,
+                               const int32_t *part_of, int radius, double vsite, double *stress, double *strain);
 // Constant-rate loading: places the grips of u_in at the strain of step
 // step_local of the increment (rate fields of the loop control) and records
 // that strain; launched before every step kernel while a rate is set.

@@ -598,23 +598,38 @@ __device__ __attribute__((always_inline)) inline void spring_eval(
     }
 }
 
-// Eq. 2 force of an intact spring added to the force on p.
+// Eq. 2 force of an intact spring added to the force on p.  cubic != 0
+// scales it by 1 + c d^2 / r0^2 (d = r - r0), the cubic spring law.
 template <int DIM, int PREC>
 __device__ __attribute__((always_inline)) inline void spring_force_add(const typename TT<PREC>::type &T,
                                                                        SpringEval<DIM, PREC> &o,
-                                                                       typename State<DIM, PREC>::R *F) {
+                                                                       typename State<DIM, PREC>::R *F,
+                                                                       double cubic = 0.0) {
     if constexpr (PREC == 1) {
         const float rinv = __builtin_amdgcn_rsqf(o.r2);  // r2 is a normal number
-        const float coef = fmaf(-T.y, rinv, T.x);        // k (r - r0) / r
+        float coef = fmaf(-T.y, rinv, T.x);              // k (r - r0) / r
+        if (cubic != 0.0) {
+            const float dr = (o.r2 * rinv - T.w) / T.w;   // (r - r0) / r0
+            coef *= fmaf(float(cubic) * dr, dr, 1.0f);
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) F[c] = fmaf(coef, o.dv[c], F[c]);
     } else if constexpr (DIM == 3) {
         // k (r - r0) / r = k - k r0 / r from 1 / r
-        const double coef = fma(-(T.x * T.y), rsqrt_pos(double(o.r2)), T.x);
+        const double rinv = rsqrt_pos(double(o.r2));
+        double coef = fma(-(T.x * T.y), rinv, T.x);
+        if (cubic != 0.0) {
+            const double dr = (double(o.r2) * rinv - T.y) / T.y;
+            coef *= fma(cubic * dr, dr, 1.0);
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) F[c] += coef * o.dv[c];
     } else {
-        const double coef = T.x * (o.r64 - T.y) / o.r64;
+        double coef = T.x * (o.r64 - T.y) / o.r64;
+        if (cubic != 0.0) {
+            const double dr = (o.r64 - T.y) / T.y;
+            coef *= fma(cubic * dr, dr, 1.0);
+        }
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             F[c] += coef * o.dv[c];
@@ -676,7 +691,9 @@ __device__ __attribute__((always_inline)) inline void step_site(
         const bool fwd = d < G::NF;
         const int myrank = rank;
         if (fwd) ++rank;
-        if (mask & (Mask(1) << d)) continue;
+        // a broken spring acts only under the recoverable law, in compression
+        const bool was_broken = mask & (Mask(1) << d);
+        if (was_broken && P.law != LSM_SPRING_RECOVER) continue;
         const R *uqh = uqhs[t];
         const R *uql = uqls[t];
         const int pb = flag_phase(fq);
@@ -684,6 +701,11 @@ __device__ __attribute__((always_inline)) inline void step_site(
         const TTy T = tt[ti];
         SpringEval<DIM, PREC> o;
         spring_eval<DIM, PREC>(P, T, ti, d, uph, upl, uqh, uql, o);
+        if (was_broken) {
+            const double r0 = P.types[ti].r0_64;
+            if (!(double(o.r2) < r0 * r0)) continue;
+            o.brk = false;
+        }
         const bool brk = o.brk;
         const double margin = o.margin;
         double *d64 = o.d64;
@@ -707,7 +729,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
             }
             continue;
         }
-        spring_force_add<DIM, PREC>(T, o, F);
+        spring_force_add<DIM, PREC>(T, o, F, P.law == LSM_SPRING_CUBIC ? P.law_c : 0.0);
         if constexpr (MODE == kEnd) {
             if (fwd) {
                 // virial (Eq. 7) and potential energy (Eq. 1) in FP64
@@ -722,12 +744,19 @@ __device__ __attribute__((always_inline)) inline void step_site(
                     }
                     r64 = sqrt(s2);
                 }
-                const double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
+                double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
+                const double dl = r64 - T64.r0_64;
+                double pe = 0.5 * T64.k64 * dl * dl;
+                if (P.law == LSM_SPRING_CUBIC) {
+                    const double dr = dl / T64.r0_64;
+                    coef64 *= 1.0 + P.law_c * dr * dr;
+                    pe += 0.25 * T64.k64 * P.law_c * dl * dl * dr * dr;
+                }
 #pragma unroll
                 for (int aa = 0; aa < DIM; ++aa)
 #pragma unroll
                     for (int bb = 0; bb < DIM; ++bb) red[aa * 3 + bb] += d64[aa] * (coef64 * d64[bb]);
-                red[18] += 0.5 * T64.k64 * (r64 - T64.r0_64) * (r64 - T64.r0_64);
+                red[18] += pe;
             }
         }
     }
@@ -920,6 +949,203 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     integrate_site<3, PREC, kMid>(P, CStore<PREC>{uint32_t(p), ns}, fp, mass_s[pa], imass_s[pa], uph, upl, F, w,
                                   red);
     if (newmask != mask) reinterpret_cast<uint32_t *>(P.mask)[p] = newmask;
+}
+
+// ------------------------------------------------------- local fields
+// Local stress and strain of the current state (Section 3.1: the virial
+// stress of Eq. 7 over a neighbourhood and the Lagrangian strain of the
+// field figure).  One thread per particle p (site site_of[p]); FP64 from
+// the (hi, lo) displacements.
+//
+// Virial contribution s^p_ab = 1/2 sum over p's intact springs of
+// (x_q - x_p)_a f_b (f the Eq. 2 force on p from q) - m v_a v_b, written to
+// out[p] (dim x dim).
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k_virial(StepParams P, const int32_t *site_of, double *out) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    using G = Geo<DIM>;
+    using Mask = typename G::Mask;
+    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p >= P.n_part) return;
+    const int g = site_of[p];
+    const int i = g % P.nx, j = (g / P.nx) % P.ny, k = g / (P.nx * P.ny);
+    const uint8_t fp = P.flags[g];
+    const int pa = flag_phase(fp);
+    const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
+    R uph[DIM], upl[DIM], w[DIM];
+    S::load_u(P.u_in, g, P.nsites, uph, upl);
+    S::load_v(P.v, g, P.nsites, w);
+    double sv[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) sv[a][b] = 0.0;
+    for (int d = 0; d < G::ND; ++d) {
+        const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
+        const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+        if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
+        const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
+        const uint8_t fq = P.flags[q];
+        const bool was_broken = mask & (Mask(1) << d);
+        if (fq == kVoid || (was_broken && P.law != LSM_SPRING_RECOVER)) continue;
+        R uqh[DIM], uql[DIM];
+        S::load_u(P.u_in, q, P.nsites, uqh, uql);
+        double dd[DIM], r2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            double e;
+            if constexpr (DIM == 2) e = (c == 0 ? G::ex(d) : G::ey(d) * kHalfSqrt3) * P.a;
+            else e = double(G::off(d, c)) * P.a;
+            dd[c] = e + ((double(uqh[c]) - double(uph[c])) + (double(uql[c]) - double(upl[c])));
+            r2 += dd[c] * dd[c];
+        }
+        const TypeRec &T = P.types[G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES +
+                                   flag_phase(fq)];
+        const double r = sqrt(r2);
+        if (was_broken && !(r < T.r0_64)) continue;  // recoverable law: compression only
+        double coef = T.k64 * (r - T.r0_64) / r;
+        if (P.law == LSM_SPRING_CUBIC) {
+            const double dr = (r - T.r0_64) / T.r0_64;
+            coef *= 1.0 + P.law_c * dr * dr;
+        }
+        const double half_coef = 0.5 * coef;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) sv[a][b] += dd[a] * (half_coef * dd[b]);
+    }
+    const double m = P.mass[pa];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) out[(int64_t(p) * DIM + a) * DIM + b] = sv[a][b] - m * double(w[a]) * double(w[b]);
+}
+
+// Virial stress over p's domain: p alone (radius 0) or p and the particles
+// it shares a spring with, broken or not (radius 1), per site volume.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_virial_domain(StepParams P, const int32_t *site_of, const int32_t *part_of,
+                                                       const double *s, double *out, int radius, double vsite) {
+    using G = Geo<DIM>;
+    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p >= P.n_part) return;
+    double acc[DIM * DIM];
+#pragma unroll
+    for (int e = 0; e < DIM * DIM; ++e) acc[e] = s[int64_t(p) * DIM * DIM + e];
+    int count = 1;
+    if (radius > 0) {
+        const int g = site_of[p];
+        const int i = g % P.nx, j = (g / P.nx) % P.ny, k = g / (P.nx * P.ny);
+        for (int d = 0; d < G::ND; ++d) {
+            const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
+            const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+            if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
+            const int q = part_of[g + ddi + P.nx * (ddj + P.ny * ddk)];
+            if (q < 0) continue;
+#pragma unroll
+            for (int e = 0; e < DIM * DIM; ++e) acc[e] += s[int64_t(q) * DIM * DIM + e];
+            ++count;
+        }
+    }
+    const double inv = 1.0 / (double(count) * vsite);
+#pragma unroll
+    for (int e = 0; e < DIM * DIM; ++e) out[int64_t(p) * DIM * DIM + e] = acc[e] * inv;
+}
+
+// Lagrangian strain: J = (sum d d0^T)(sum d0 d0^T)^-1 over p's first
+// nearest neighbours (2D: the six lattice neighbours; 3D: the six face
+// neighbours), broken springs included; eps = (J^T J - I) / 2, NaN where
+// the reference vectors do not span the space.
+template <int DIM, int PREC>
+__global__ __launch_bounds__(256) void k_strain(StepParams P, const int32_t *site_of, double *out) {
+    using S = State<DIM, PREC>;
+    using R = typename S::R;
+    using G = Geo<DIM>;
+    const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
+    if (p >= P.n_part) return;
+    const int g = site_of[p];
+    const int i = g % P.nx, j = (g / P.nx) % P.ny, k = g / (P.nx * P.ny);
+    R uph[DIM], upl[DIM];
+    S::load_u(P.u_in, g, P.nsites, uph, upl);
+    double A[DIM][DIM], B[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) A[a][b] = B[a][b] = 0.0;
+    for (int d = 0; d < G::ND; ++d) {
+        if (G::geom(d) != 0) continue;  // first nearest neighbours only
+        const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
+        const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
+        if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
+        const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
+        if (P.flags[q] == kVoid) continue;
+        R uqh[DIM], uql[DIM];
+        S::load_u(P.u_in, q, P.nsites, uqh, uql);
+        double d0[DIM], dd[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            if constexpr (DIM == 2) d0[c] = (c == 0 ? G::ex(d) : G::ey(d) * kHalfSqrt3) * P.a;
+            else d0[c] = double(G::off(d, c)) * P.a;
+            dd[c] = d0[c] + ((double(uqh[c]) - double(uph[c])) + (double(uql[c]) - double(upl[c])));
+        }
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
+            for (int b = 0; b < DIM; ++b) {
+                A[a][b] += d0[a] * d0[b];
+                B[a][b] += dd[a] * d0[b];
+            }
+    }
+    // inverse of A by its adjugate
+    double Ai[DIM][DIM], det, amax = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) amax = fmax(amax, fabs(A[a][b]));
+    if constexpr (DIM == 2) {
+        det = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        Ai[0][0] = A[1][1]; Ai[0][1] = -A[0][1]; Ai[1][0] = -A[1][0]; Ai[1][1] = A[0][0];
+    } else {
+        Ai[0][0] = A[1][1] * A[2][2] - A[1][2] * A[2][1];
+        Ai[0][1] = A[0][2] * A[2][1] - A[0][1] * A[2][2];
+        Ai[0][2] = A[0][1] * A[1][2] - A[0][2] * A[1][1];
+        Ai[1][0] = A[1][2] * A[2][0] - A[1][0] * A[2][2];
+        Ai[1][1] = A[0][0] * A[2][2] - A[0][2] * A[2][0];
+        Ai[1][2] = A[0][2] * A[1][0] - A[0][0] * A[1][2];
+        Ai[2][0] = A[1][0] * A[2][1] - A[1][1] * A[2][0];
+        Ai[2][1] = A[0][1] * A[2][0] - A[0][0] * A[2][1];
+        Ai[2][2] = A[0][0] * A[1][1] - A[0][1] * A[1][0];
+        det = A[0][0] * Ai[0][0] + A[0][1] * Ai[1][0] + A[0][2] * Ai[2][0];
+    }
+    double* o = out + int64_t(p) * DIM * DIM;
+    double tiny = 1e-12;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) tiny *= amax;
+    if (!(fabs(det) > tiny)) {
+#pragma unroll
+        for (int e = 0; e < DIM * DIM; ++e) o[e] = __longlong_as_double(0x7FF8000000000000LL);
+        return;
+    }
+    double J[DIM][DIM];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) t += B[a][c] * Ai[c][b];
+            J[a][b] = t / det;
+        }
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < DIM; ++c) t += J[c][a] * J[c][b];
+            o[a * DIM + b] = 0.5 * (t - (a == b ? 1.0 : 0.0));
+        }
 }
 
 // Copies between the site-grid state (displacements u_grid, velocities
@@ -2019,6 +2245,29 @@ hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t s, int to_c
     } else {
         if (prec) hipLaunchKernelGGL((k_pack_c3<1, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
         else hipLaunchKernelGGL((k_pack_c3<0, false>), grid, block, 0, s, p, u_grid, v_grid, m_grid, u_c, v_c, m_c, ncn);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_local_fields(const StepParams &p, int dim, int prec, hipStream_t s, const int32_t *site_of,
+                               const int32_t *part_of, int radius, double vsite, double *stress, double *strain) {
+    if (p.n_part <= 0) return hipSuccess;
+    const dim3 grid(unsigned((p.n_part + 255) / 256)), block(256);
+    // radius 1: the contributions go to `strain` first, which the strain
+    // kernel then overwrites
+    double *tmp = radius > 0 ? strain : stress;
+    if (dim == 2) {
+        if (prec) hipLaunchKernelGGL((k_virial<2, 1>), grid, block, 0, s, p, site_of, tmp);
+        else hipLaunchKernelGGL((k_virial<2, 0>), grid, block, 0, s, p, site_of, tmp);
+        hipLaunchKernelGGL((k_virial_domain<2>), grid, block, 0, s, p, site_of, part_of, tmp, stress, radius, vsite);
+        if (prec) hipLaunchKernelGGL((k_strain<2, 1>), grid, block, 0, s, p, site_of, strain);
+        else hipLaunchKernelGGL((k_strain<2, 0>), grid, block, 0, s, p, site_of, strain);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_virial<3, 1>), grid, block, 0, s, p, site_of, tmp);
+        else hipLaunchKernelGGL((k_virial<3, 0>), grid, block, 0, s, p, site_of, tmp);
+        hipLaunchKernelGGL((k_virial_domain<3>), grid, block, 0, s, p, site_of, part_of, tmp, stress, radius, vsite);
+        if (prec) hipLaunchKernelGGL((k_strain<3, 1>), grid, block, 0, s, p, site_of, strain);
+        else hipLaunchKernelGGL((k_strain<3, 0>), grid, block, 0, s, p, site_of, strain);
     }
     return hipGetLastError();
 }

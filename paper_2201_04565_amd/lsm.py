@@ -30,7 +30,7 @@ EXPORTS = (
     "lsm_get_velocities", "lsm_set_positions", "lsm_set_velocities", "lsm_eval_forces",
     "lsm_save_state", "lsm_load_state", "lsm_set_timing", "lsm_read_timing", "lsm_step_bytes",
     "lsm_set_launch", "lsm_set_prefetch", "lsm_autotune", "lsm_get_launch", "lsm_last_error",
-    "lsm_strerror", "lsm_set_strain_rate", "lsm_relax_trace",
+    "lsm_strerror", "lsm_set_strain_rate", "lsm_relax_trace", "lsm_local_fields",
 )
 
 
@@ -39,7 +39,8 @@ class Config(C.Structure):
                 ("k", C.c_double * 64), ("break_stretch", C.c_double * 64),
                 ("k_face", C.c_double), ("k_diag", C.c_double), ("mass", C.c_double * 8),
                 ("dt", C.c_double), ("damping", C.c_double), ("precision", C.c_int32),
-                ("predictor", C.c_int32), ("void_value", C.c_int32), ("reserved", C.c_int32)]
+                ("predictor", C.c_int32), ("void_value", C.c_int32), ("spring_law", C.c_int32),
+                ("law_c", C.c_double)]
 
 
 class Record(C.Structure):
@@ -99,6 +100,7 @@ def load_library():
                "lsm_set_positions", "lsm_set_velocities"):
         getattr(L, nm).argtypes = [vp, vp]
     L.lsm_eval_forces.argtypes = [vp, vp, C.c_int]
+    L.lsm_local_fields.argtypes = [vp, C.c_int, vp, vp]
     L.lsm_save_state.argtypes = [vp, vp, P(C.c_size_t)]
     L.lsm_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lsm_set_timing.argtypes = [vp, C.c_int]
@@ -116,8 +118,12 @@ def load_library():
     return L
 
 
+SPRING_LAWS = {"linear": 0, "recover": 1, "cubic": 2}
+
+
 def make_config(*, lattice, k, s, mass, a=1.0, k_face=1.0, k_diag=1.0, dt=0.01, gamma=0.1,
-                precision="fp64", predictor="affine", void_value=-1) -> Config:
+                precision="fp64", predictor="affine", void_value=-1, spring_law="linear",
+                law_c=0.0) -> Config:
     P = len(mass)
     if not 1 <= P <= MAX_PHASES:
         raise ValueError("1..8 phases supported")
@@ -141,6 +147,8 @@ def make_config(*, lattice, k, s, mass, a=1.0, k_face=1.0, k_diag=1.0, dt=0.01, 
     cfg.precision = {"fp64": FP64, "fp32k": FP32_KAHAN}[precision]
     cfg.predictor = {"affine": PRED_AFFINE, "grips": PRED_GRIPS_ONLY}[predictor]
     cfg.void_value = void_value
+    cfg.spring_law = SPRING_LAWS[spring_law]
+    cfg.law_c = law_c
     return cfg
 
 
@@ -158,7 +166,7 @@ class Lattice:
 
     def __init__(self, image: np.ndarray, *, k, s, mass, a=1.0, k_face=1.0, k_diag=1.0,
                  dt=0.01, gamma=0.1, precision="fp64", predictor="affine", void_value=-1,
-                 device="cuda:0", stream=None):
+                 spring_law="linear", law_c=0.0, device="cuda:0", stream=None):
         import torch
 
         L = load_library()
@@ -168,7 +176,8 @@ class Lattice:
         self.dim = 2 if lattice == TRI2D else 3
         cfg = make_config(lattice=lattice, k=k, s=s, mass=mass, a=a, k_face=k_face,
                           k_diag=k_diag, dt=dt, gamma=gamma, precision=precision,
-                          predictor=predictor, void_value=void_value)
+                          predictor=predictor, void_value=void_value, spring_law=spring_law,
+                          law_c=law_c)
         self.precision = precision
         h = C.c_void_p()
         self._check(L.lsm_create(C.byref(cfg), C.byref(h)), None)
@@ -312,6 +321,20 @@ class Lattice:
         self._check(self._L.lsm_eval_forces(self._h, _ptr(out), int(bool(commit))))
         return out
 
+    def local_fields(self, radius=0):
+        """(stress, strain) per particle, numpy [n, dim, dim] (lsm_local_fields
+        into device tensors on the lattice's stream, then copied)."""
+        import torch
+        d = self.n * self.dim * self.dim
+        stress = torch.empty(max(d, 1), dtype=torch.float64, device=self.device)
+        strain = torch.empty(max(d, 1), dtype=torch.float64, device=self.device)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self._L.lsm_local_fields(self._h, int(radius), C.c_void_p(stress.data_ptr()),
+                                             C.c_void_p(strain.data_ptr())))
+        self.synchronize()
+        shape = (self.n, self.dim, self.dim)
+        return stress[:d].cpu().numpy().reshape(shape), strain[:d].cpu().numpy().reshape(shape)
+
     def save_state(self) -> bytes:
         n = C.c_size_t()
         self._check(self._L.lsm_save_state(self._h, None, C.byref(n)))
@@ -373,7 +396,8 @@ class HostModel:
     counts, canonical spring list and reference positions."""
 
     def __init__(self, image: np.ndarray, *, k, s, mass, a=1.0, k_face=1.0, k_diag=1.0,
-                 dt=0.01, gamma=0.1, precision="fp64", predictor="affine", void_value=-1):
+                 dt=0.01, gamma=0.1, precision="fp64", predictor="affine", void_value=-1,
+                 spring_law="linear", law_c=0.0):
         L = load_library()
         self._L = L
         img = np.ascontiguousarray(image, dtype=np.uint8)
@@ -381,7 +405,8 @@ class HostModel:
         self.dim = 2 if lattice == TRI2D else 3
         cfg = make_config(lattice=lattice, k=k, s=s, mass=mass, a=a, k_face=k_face,
                           k_diag=k_diag, dt=dt, gamma=gamma, precision=precision,
-                          predictor=predictor, void_value=void_value)
+                          predictor=predictor, void_value=void_value, spring_law=spring_law,
+                          law_c=law_c)
         h = C.c_void_p()
         rc = L.lsm_create(C.byref(cfg), C.byref(h))
         if rc != LSM_OK:

@@ -14,7 +14,7 @@ import pytest
 
 from oracle import Net, Params
 from paper_2201_04565_amd import inputs
-from tests.parity import compare_events, compare_records
+from tests.parity import compare_events, compare_records, first_set_difference
 
 pytestmark = pytest.mark.gpu
 
@@ -92,8 +92,14 @@ def test_brick_crop_with_fracture(lsm, precision):
     ev_o, ev_g = o.events(), g.read_broken()
     assert len(ev_o) > 0
     div_inc, k = compare_events(ev_o, ev_g, tie)
-    say(f"  {len(ev_o)} oracle events, {k} identical; divergence from increment {div_inc}")
-    compare_records(ro, rg, rtol, 2, upto_inc=div_inc)
+    # past the first near-tie the order of breaks inside an increment may
+    # differ; the records still agree while the broken sets do
+    diff_inc = first_set_difference(ev_o, ev_g, 6)
+    n = compare_records(ro, rg, rtol, 2, upto_inc=max(div_inc, diff_inc))
+    say(f"  {len(ev_o)} oracle events, {k} identical in order (divergence from increment {div_inc}); "
+        f"broken sets equal through increment {diff_inc - 1}; {n} records compared")
+    assert k >= (2000 if precision == "fp64" else 100)
+    assert n >= 4
 
 
 def test_c2_prefix_fp32k(lsm):
@@ -115,8 +121,12 @@ def test_3d_grf_with_fracture(lsm, precision):
     rtol, tie = TOL[precision]
     ev_o, ev_g = o.events(), g.read_broken()
     div_inc, k = compare_events(ev_o, ev_g, tie)
-    say(f"  {len(ev_o)} oracle events, {k} identical; divergence from increment {div_inc}")
-    compare_records(ro, rg, rtol, 3, upto_inc=div_inc)
+    diff_inc = first_set_difference(ev_o, ev_g, 4)
+    n = compare_records(ro, rg, rtol, 3, upto_inc=max(div_inc, diff_inc))
+    say(f"  {len(ev_o)} oracle events, {k} identical in order (divergence from increment {div_inc}); "
+        f"broken sets equal through increment {diff_inc - 1}; {n} records compared")
+    assert k >= (900 if precision == "fp64" else 1)
+    assert n >= (4 if precision == "fp64" else 1)
 
 
 def test_relax_continuation_and_grips_only(lsm):
