@@ -82,6 +82,7 @@ struct lsm_handle {
     // particle the absent-spring directions and the flag byte
     std::vector<uint64_t> crow;
     std::vector<uint32_t> cabs;
+    bool row32 = false;               // single-phase: 32-bit row entries (before << 1 | solid) on the device
     std::vector<uint8_t> cflag;
     int64_t cn = 0;                   // particle stride of the compact arrays
     void *d_cu[2] = {nullptr, nullptr}, *d_cv = nullptr;
@@ -379,7 +380,7 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         for (int s = 0; s < chunk && le == hipSuccess; ++s) {
             q.u_in = h->d_cu[s & 1];
             q.u_out = h->d_cu[(s & 1) ^ 1];
-            le = lsm::launch_step_c3(q, h->prec, h->stream, local + s);
+            le = lsm::launch_step_c3(q, h->prec, h->stream, local + s, h->row32 ? 1 : 0);
         }
         if (le != hipSuccess) return le;
         return lsm::launch_pack_c3(p, h->prec, h->stream, 0, h->d_U[c ^ (chunk & 1)], h->d_V,
@@ -616,6 +617,7 @@ static void build_compact_3d(lsm_handle *h) {
         h->cflag[size_t(c)] = h->flags[size_t(g)];
     }
     h->cn = (h->n + 63) / 64 * 64;
+    h->row32 = h->cfg.nphase == 1;
 }
 
 int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t ny, int64_t nz) {
@@ -730,7 +732,7 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         h->cflag.size(),                              // 19 compact flags
         h->cflag.size() * 4,                          // 20 compact break + absent bits
         h->cabs.size() * 4,                           // 21 absent-spring bits
-        h->crow.size() * 8,                           // 22 row table per site
+        h->crow.size() * (h->row32 ? 4 : 8),          // 22 row table per site
         size_t(h->n) * 4,                             // 23 site of each particle
         ns * 4,                                       // 24 particle of each site
     };
@@ -822,8 +824,16 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     if (!h->crow.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_cflag, h->cflag.data(), h->cflag.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_cabs, h->cabs.data(), h->cabs.size() * 4, hipMemcpyHostToDevice, h->stream));
-        HIPCHK(h, hipMemcpyAsync(h->d_crow, h->crow.data(), h->crow.size() * 8, hipMemcpyHostToDevice,
-                                 h->stream));
+        if (h->row32) {
+            std::vector<uint32_t> r32(h->crow.size());
+            for (size_t g = 0; g < r32.size(); ++g)
+                r32[g] = uint32_t((h->crow[g] >> 32) << 1) | uint32_t((h->crow[g] >> 12) & 1u);
+            HIPCHK(h, hipMemcpyAsync(h->d_crow, r32.data(), r32.size() * 4, hipMemcpyHostToDevice, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));  // r32 is a local vector
+        } else {
+            HIPCHK(h, hipMemcpyAsync(h->d_crow, h->crow.data(), h->crow.size() * 8, hipMemcpyHostToDevice,
+                                     h->stream));
+        }
     }
     HIPCHK(h, hipStreamSynchronize(h->stream));
     h->cur = 0;

@@ -112,8 +112,9 @@ struct StepParams {
     // bits 32-63 the number of solid sites before it in raster order (= the
     // particle index of a solid site), bit 12 whether it is solid, bits 0-3,
     // 4-7, 8-11 the phases of the sites at x - 1, x, x + 1 of its row (0 if
-    // void or off the grid); per particle the directions (bits 0-17) whose
-    // neighbour is void or off the grid
+    // void or off the grid) -- or, for single-phase lattices, 32-bit entries
+    // (solid sites before it << 1 | solid); per particle the directions
+    // (bits 0-17) whose neighbour is void or off the grid
     const uint64_t *crow;
     const uint32_t *cabs;
     // spring law (LSM_SPRING_*) and the cubic coefficient; only the gather
@@ -151,14 +152,11 @@ hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t
 // 3D compact layout: one interior step (P's state pointers, flags and break
 // bits point at the compact arrays, P.nsites is their particle stride), and
 // the copies between the site-grid and compact states (cn: compact stride).
-hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t stream, int step_local);
+// row32: the row table holds 32-bit entries (particles before << 1 | solid)
+// of a single-phase lattice
+hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t stream, int step_local, int row32);
 hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t stream, int to_compact, void *u_grid,
                           void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn);
-// Local fields of the state in u_in / v / mask (particle order, FP64
-// [n][dim][dim]): virial stress over the radius-0 or radius-1 domain per
-// site volume vsite, and the Lagrangian strain (NaN where undefined).
-hipError_t launch_local_fields(const StepParams &p, int dim, int prec, hipStream_t stream, const int32_t *site_of,
-                               const int32_t *part_of, int radius, double vsite, double *stress, double *strain);
 // Local fields of the state in u_in / v / mask (particle order, FP64
 // [n][dim][dim]): virial stress over the radius-0 or radius-1 domain per
 // site volume vsite, and the Lagrangian strain (NaN where undefined).

@@ -825,20 +825,43 @@ __global__ __launch_bounds__(kBlock) void k_step(StepParams P, int step_local) {
     }
 }
 
+// wave_shl:1 -> lane l reads lane l + 1; wave_shr:1 -> lane l reads lane l - 1
+// (the edge lane reads zero; edge lanes are never owned).
+__device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
+__device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
+__device__ inline float lane_next(float x) { return __int_as_float(lane_next(__float_as_int(x))); }
+__device__ inline float lane_prev(float x) { return __int_as_float(lane_prev(__float_as_int(x))); }
+__device__ inline double lane_next(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_next(int(b & 0xFFFFFFFFll)), hi = lane_next(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ inline double lane_prev(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_prev(int(b & 0xFFFFFFFFll)), hi = lane_prev(int(b >> 32));
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Calls f(std::integral_constant<int, t>) for t = T .. N - 1 in order, so
+// each unrolled row can use t in template arguments.
 // Interior step of a 3D lattice in the compact layout: one thread per
 // particle (raster order, which is the canonical particle order), state,
 // flags and break bits stored per particle, so a wavefront's loads and
 // stores touch only solid sites.  The 18 neighbours lie in 9 grid rows
-// (x-lines); one 64-bit entry of the row table per row -- the particle
-// index of the row's site at the particle's x, whether that site is solid,
-// and the phases of it and its two x-neighbours -- gives the indices and
-// phases of the neighbours in that row (raster order makes a row's solid
-// sites consecutive particles).  Every load of a particle is issued before
+// (x-lines); one entry of the row table per row -- the particle index of
+// the row's site at the particle's x, whether that site is solid, and the
+// phases of it and its two x-neighbours -- gives the indices and phases of
+// the neighbours in that row (raster order makes a row's solid sites
+// consecutive particles); the own row's neighbours p - 1 and p + 1 are the
+// adjacent lanes.  (Taking the other rows' x +- 1 neighbours from the
+// adjacent lanes' same-x neighbours as well, with a row-grouped summation
+// order, measured slower: 323 against 285 us per C3 FP64 step.)  Every
+// load of a particle is issued before
 // any of its stores; the events of forward springs that break are logged
 // after all loads (the test is redone for the margin), before the update.
 // Arithmetic and summation order are the gather kernel's, so state, break
 // bits and events are bitwise the same.
-template <int PREC>
+template <int PREC, bool ROW32>
 __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local) {
     constexpr int GRP = 6;  // neighbour loads per group (9 or 18, or the next group's loads in
                             // flight during the current one, measured slower)
@@ -860,6 +883,7 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     const int b = blockIdx.x;
     const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
     const int p = lb * kBlock + int(threadIdx.x);
+    const int lane = int(threadIdx.x) & 63;
     if (p >= P.n_part) return;
     const uint32_t pc = P.plist[p];
     const int i = int(pc & 1023u), j = int((pc >> 10) & 2047u), k = int(pc >> 21);
@@ -871,15 +895,24 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     const uint32_t mask = reinterpret_cast<const uint32_t *>(P.mask)[p];
     const uint8_t fp = P.flags[p];
     // row entries: slot (dj + 1) * 3 + (dk + 1); a row off the grid reads
-    // the particle's own entry (all its springs there are absent)
+    // the particle's own entry (all its springs there are absent).  ROW32:
+    // single-phase lattices keep (particles before << 1) | solid in 32 bits.
     uint64_t row[9];
 #pragma unroll
     for (int sl = 0; sl < 9; ++sl) {
+        if (sl == 4) continue;  // own row: p - 1 and p + 1
         const int dj = sl / 3 - 1, dk = sl % 3 - 1;
         const bool in = j + dj >= 0 && j + dj < P.ny && k + dk >= 0 && k + dk < P.nz;
         const uint32_t gq = uint32_t(in ? gg + P.nx * (dj + P.ny * dk) : gg);
-        row[sl] = *reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(P.crow) + gq * 8u);
+        if constexpr (ROW32) {
+            const uint32_t e = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(P.crow) + gq * 4u);
+            row[sl] = (uint64_t(e >> 1) << 32) | (uint64_t(e & 1u) << 12);
+        } else {
+            row[sl] = *reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(P.crow) + gq * 8u);
+        }
     }
+    if constexpr (ROW32) row[4] = 0;
+    else row[4] = *reinterpret_cast<const uint64_t *>(reinterpret_cast<const char *>(P.crow) + uint32_t(gg) * 8u);
     const uint32_t qmax = uint32_t(P.n_part - 1);
     // neighbour in direction d: index (clamped, for absent springs) and phase
     auto nbr = [&](int d, uint32_t &q, int &pb) {
@@ -894,6 +927,17 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
         }
         q = min(q, qmax);
     };
+    // the x-neighbours p - 1 and p + 1 are the adjacent lanes (particles are
+    // consecutive across a wavefront): their displacements come by DPP, and
+    // only the edge lanes load them
+    auto xnbr = [&](int dx, R *qh, R *ql) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            qh[c] = dx > 0 ? lane_next(uph[c]) : lane_prev(uph[c]);
+            ql[c] = dx > 0 ? lane_next(upl[c]) : lane_prev(upl[c]);
+        }
+        if (lane == (dx > 0 ? 63 : 0)) CS::load_u(P.u_in, min(uint32_t(p + dx), qmax), ns, qh, ql);
+    };
     const int pa = flag_phase(fp);
     R F[3] = {R(0), R(0), R(0)};
     uint32_t newmask = mask, fbrk = 0;
@@ -903,9 +947,11 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     for (int gi = 0; gi < NG; ++gi) {
 #pragma unroll
         for (int t = 0; t < GRP; ++t) {
+            const int d = gi * GRP + t;
             uint32_t q;
-            nbr(gi * GRP + t, q, pbs[t]);
-            CS::load_u(P.u_in, q, ns, uqh[t], uql[t]);
+            nbr(d, q, pbs[t]);
+            if (G::dj(d) == 0 && G::dk(d) == 0) xnbr(G::di(d, 0), uqh[t], uql[t]);
+            else CS::load_u(P.u_in, q, ns, uqh[t], uql[t]);
         }
 #pragma unroll
         for (int t = 0; t < GRP; ++t) {
@@ -1391,25 +1437,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(StepParams P, DevRecord *re
 // two lower neighbours (previous row, carried in registers).  The force sum
 // has a fixed order per site, so results do not depend on the launch shape.
 
-// wave_shl:1 -> lane l reads lane l + 1; wave_shr:1 -> lane l reads lane l - 1
-// (the edge lane reads zero; edge lanes are never owned).
-__device__ inline int lane_next(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true); }
-__device__ inline int lane_prev(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true); }
-__device__ inline float lane_next(float x) { return __int_as_float(lane_next(__float_as_int(x))); }
-__device__ inline float lane_prev(float x) { return __int_as_float(lane_prev(__float_as_int(x))); }
-__device__ inline double lane_next(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = lane_next(int(b & 0xFFFFFFFFll)), hi = lane_next(int(b >> 32));
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-__device__ inline double lane_prev(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = lane_prev(int(b & 0xFFFFFFFFll)), hi = lane_prev(int(b >> 32));
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-// Calls f(std::integral_constant<int, t>) for t = T .. N - 1 in order, so
-// each unrolled row can use t in template arguments.
 template <int T, int N, class F>
 __device__ __attribute__((always_inline)) inline void unroll_rows(F &&f) {
     if constexpr (T < N) {
@@ -2227,10 +2254,15 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
     return prec ? launch_step_t<3, 1>(p, mode, s, step_local) : launch_step_t<3, 0>(p, mode, s, step_local);
 }
 
-hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local) {
+hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local, int row32) {
     const dim3 grid(p.c_blocks), block(kBlock);
-    if (prec) hipLaunchKernelGGL((k_step_c3<1>), grid, block, 0, s, p, step_local);
-    else hipLaunchKernelGGL((k_step_c3<0>), grid, block, 0, s, p, step_local);
+    if (row32) {
+        if (prec) hipLaunchKernelGGL((k_step_c3<1, true>), grid, block, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_step_c3<0, true>), grid, block, 0, s, p, step_local);
+    } else {
+        if (prec) hipLaunchKernelGGL((k_step_c3<1, false>), grid, block, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_step_c3<0, false>), grid, block, 0, s, p, step_local);
+    }
     return hipGetLastError();
 }
 
