@@ -75,9 +75,16 @@ extern "C" {
                                found through a per-site prefix count), copied in and out
                                around every chunk of interior steps; same results as
                                LSM_KERNEL_GATHER, whose kernel runs the start and end
-                               steps.  LSM_EINVAL for 2D lattices and for lattices of
+                               steps.  Single-phase lattices stage each workgroup's
+                               neighbour records in LDS (where every window holds fewer
+                               than 2^15 particles; else, and for several phases, it runs
+                               as LSM_KERNEL_COMPACT_DIRECT, which lsm_get_launch then
+                               reports).  LSM_EINVAL for 2D lattices and for lattices of
                                2^28 particles or more.  Not under constant-rate loading
                                (the gather kernel runs those steps) */
+#define LSM_KERNEL_COMPACT_DIRECT 6 /* LSM_KERNEL_COMPACT with every neighbour record read
+                               from global memory (no LDS staging); same results and
+                               rules */
 
 /* Model and integration parameters.
  *  k[P*P], break_stretch[P*P]: row-major, symmetric spring constant and

@@ -83,12 +83,19 @@ struct lsm_handle {
     std::vector<uint64_t> crow;
     std::vector<uint32_t> cabs;
     bool row32 = false;               // single-phase: 32-bit row entries (before << 1 | solid) on the device
+    // LDS windows of the interior step (single-phase lattices whose windows
+    // hold fewer than 2^15 particles): per workgroup bases and lengths, per
+    // particle eight 16-bit row entries
+    std::vector<uint32_t> cwin;
+    std::vector<uint16_t> crel;
     std::vector<uint8_t> cflag;
     int64_t cn = 0;                   // particle stride of the compact arrays
     void *d_cu[2] = {nullptr, nullptr}, *d_cv = nullptr;
     uint8_t *d_cflag = nullptr;
     uint32_t *d_cmask = nullptr, *d_cabs = nullptr;
     uint64_t *d_crow = nullptr;
+    uint32_t *d_cwin = nullptr;
+    void *d_crel = nullptr;
     int32_t *d_site_of = nullptr, *d_part_of = nullptr;  // particle -> site, site -> particle (-1: void)
     void *d_U[2] = {nullptr, nullptr};
     void *d_V = nullptr, *d_A = nullptr;
@@ -290,7 +297,12 @@ bool use_small(const lsm_handle *h) {
 // (not under constant-rate loading, whose grip kernel moves site-grid state)
 bool use_compact(const lsm_handle *h) {
     return h->dim == 3 && !h->crow.empty() && h->rate == 0.0 && linear_law(h) &&
-           (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT);
+           (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT ||
+            h->variant == LSM_KERNEL_COMPACT_DIRECT);
+}
+// ... with the neighbours staged in LDS windows (where the lattice has them)
+bool use_window(const lsm_handle *h) {
+    return use_compact(h) && !h->cwin.empty() && h->variant != LSM_KERNEL_COMPACT_DIRECT;
 }
 bool use_sweep(const lsm_handle *h) {
     return h->dim == 2 && ((h->variant == LSM_KERNEL_AUTO && !small_fits(h)) || h->variant == LSM_KERNEL_SWEEP ||
@@ -370,6 +382,9 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         StepParams p = make_params(h, c, c ^ 1);
         p.crow = h->d_crow;
         p.cabs = h->d_cabs;
+        p.cwin = h->d_cwin;
+        p.crel = h->d_crel;
+        const int kind = use_window(h) ? 2 : (h->row32 ? 1 : 0);
         le = lsm::launch_pack_c3(p, h->prec, h->stream, 1, h->d_U[c], h->d_V, static_cast<uint32_t *>(h->d_mask),
                                  h->d_cu[0], h->d_cv, h->d_cmask, h->cn);
         StepParams q = p;
@@ -380,7 +395,7 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         for (int s = 0; s < chunk && le == hipSuccess; ++s) {
             q.u_in = h->d_cu[s & 1];
             q.u_out = h->d_cu[(s & 1) ^ 1];
-            le = lsm::launch_step_c3(q, h->prec, h->stream, local + s, h->row32 ? 1 : 0);
+            le = lsm::launch_step_c3(q, h->prec, h->stream, local + s, kind);
         }
         if (le != hipSuccess) return le;
         return lsm::launch_pack_c3(p, h->prec, h->stream, 0, h->d_U[c ^ (chunk & 1)], h->d_V,
@@ -573,6 +588,75 @@ void lsm_destroy(lsm_handle *h) {
     delete h;
 }
 
+// LDS windows of the compact 3D interior step (single-phase lattices).  The
+// particles of workgroup lb (lsm::kBlock consecutive ones, sites g0 .. g1)
+// have all their neighbours in plane offset dk among the sites
+// g0 - nx - 1 + dk nx ny .. g1 + nx + 1 + dk nx ny: a contiguous run of
+// particles, the window, whose first particle and length are kept per
+// workgroup.  Per particle and off-row grid row (j + dj, k + dk): the offset
+// in window dk of the row's site at the particle's x and its solid bit, in
+// 16 bits.  Left empty (the interior step then reads every neighbour from
+// global memory) when a window holds 2^15 particles or more; every entry of
+// an intact spring is checked against the neighbour's particle index.
+static void build_windows_3d(lsm_handle *h) {
+    h->cwin.clear();
+    h->crel.clear();
+    const int64_t nx = h->nx, ny = h->ny, nz = h->nz, ns = h->nsites, n = h->n;
+    const int64_t B = lsm::kBlock, nb = h->c_blocks;
+    if (n < 1 || nb * B < n) return;
+    auto before = [&](int64_t g) { return int64_t(h->crow[size_t(g)] >> 32); };  // g in [0, ns]
+    std::vector<uint32_t> win(size_t(nb) * 8, 0);
+    for (int64_t lb = 0; lb * B < n; ++lb) {
+        const int64_t g0 = h->site_of[size_t(lb * B)], g1 = h->site_of[size_t(std::min(n, lb * B + B) - 1)];
+        for (int w = 0; w < 3; ++w) {
+            const int64_t lo = std::max<int64_t>(0, g0 - nx - 1 + (w - 1) * nx * ny);
+            const int64_t hi = std::min<int64_t>(ns - 1, g1 + nx + 1 + (w - 1) * nx * ny);
+            const int64_t base = before(std::min(lo, ns)), len = hi >= lo ? before(hi + 1) - base : 0;
+            if (len >= (int64_t(1) << 15)) return;
+            win[size_t(lb * 8 + w)] = uint32_t(base);
+            win[size_t(lb * 8 + 3 + w)] = uint32_t(len);
+        }
+    }
+    std::vector<uint16_t> rel(size_t(n) * 8, 0);
+    for (int64_t c = 0; c < n; ++c) {
+        const int64_t lb = c / B, g = h->site_of[size_t(c)];
+        const int64_t i = g % nx, j = (g / nx) % ny, k = g / (nx * ny);
+        int e = 0;
+        for (int sl = 0; sl < 9; ++sl) {
+            if (sl == 4) continue;
+            const int dj = sl / 3 - 1, dk = sl % 3 - 1;
+            uint16_t v = 2;  // a row off the grid: offset 1, void (its springs are absent)
+            if (j + dj >= 0 && j + dj < ny && k + dk >= 0 && k + dk < nz) {
+                const int64_t gq = g + nx * (dj + ny * dk);
+                const int64_t off = before(gq) - int64_t(win[size_t(lb * 8 + dk + 1)]);
+                if (off < 0 || off >= (int64_t(1) << 15)) return;
+                v = uint16_t((off << 1) | (h->flags[size_t(gq)] != lsm::kVoid ? 1 : 0));
+            }
+            rel[size_t(c * 8 + e++)] = v;
+        }
+        // the neighbour the step kernel takes for every intact spring
+        const uint32_t absent = h->cabs[size_t(c)];
+        for (int d = 0; d < 18; ++d) {
+            if (absent & (1u << d)) continue;
+            const int sgn = d < 9 ? 1 : -1;
+            const int dx = sgn * kFwd3[d % 9][0], dj = sgn * kFwd3[d % 9][1], dk = sgn * kFwd3[d % 9][2];
+            const int sl = (dj + 1) * 3 + (dk + 1);
+            const int64_t base = win[size_t(lb * 8 + dk + 1)];
+            int64_t t;
+            if (sl == 4) {
+                t = c - base + dx;
+            } else {
+                const int64_t ent = rel[size_t(c * 8 + (sl < 4 ? sl : sl - 1))];
+                t = (ent >> 1) + (dx < 0 ? -1 : (dx > 0 ? (ent & 1) : 0));
+            }
+            const int64_t gq = g + dx + nx * (dj + ny * dk);
+            if (t < 0 || t >= int64_t(win[size_t(lb * 8 + 3 + dk + 1)]) || base + t != before(gq)) return;
+        }
+    }
+    h->cwin.swap(win);
+    h->crel.swap(rel);
+}
+
 // Tables of the compact 3D layout: the row table (per site: particles
 // before it, solid bit, phases at x - 1, x, x + 1), absent-spring bits and
 // flags per particle.  Particle indices must fit 32 bits and the kernels
@@ -618,6 +702,7 @@ static void build_compact_3d(lsm_handle *h) {
     }
     h->cn = (h->n + 63) / 64 * 64;
     h->row32 = h->cfg.nphase == 1;
+    if (h->row32) build_windows_3d(h);
 }
 
 int lsm_build_lattice(lsm_handle *h, const uint8_t *phase, int64_t nx, int64_t ny, int64_t nz) {
@@ -701,7 +786,7 @@ int lsm_counts(const lsm_handle *h, int64_t *n_particles, int64_t *n_springs) {
     return LSM_OK;
 }
 
-constexpr int kRegions = 25;
+constexpr int kRegions = 27;
 
 static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
     size_t o = 0;
@@ -735,6 +820,8 @@ static size_t layout(const lsm_handle *h, size_t *off /* kRegions offsets */) {
         h->crow.size() * (h->row32 ? 4 : 8),          // 22 row table per site
         size_t(h->n) * 4,                             // 23 site of each particle
         ns * 4,                                       // 24 particle of each site
+        h->cwin.size() * 4,                           // 25 LDS windows per workgroup
+        h->crel.size() * 2,                           // 26 window row entries per particle
     };
     for (int i = 0; i < kRegions; ++i) {
         off[i] = o;
@@ -788,6 +875,8 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     h->d_crow = reinterpret_cast<uint64_t *>(w + off[22]);
     h->d_site_of = reinterpret_cast<int32_t *>(w + off[23]);
     h->d_part_of = reinterpret_cast<int32_t *>(w + off[24]);
+    h->d_cwin = reinterpret_cast<uint32_t *>(w + off[25]);
+    h->d_crel = w + off[26];
     h->vm = 0;
     HIPCHK(h, hipMemsetAsync(w, 0, need, h->stream));
     {
@@ -824,6 +913,12 @@ int lsm_bind(lsm_handle *h, void *dptr, size_t bytes, void *hip_stream) {
     if (!h->crow.empty()) {
         HIPCHK(h, hipMemcpyAsync(h->d_cflag, h->cflag.data(), h->cflag.size(), hipMemcpyHostToDevice, h->stream));
         HIPCHK(h, hipMemcpyAsync(h->d_cabs, h->cabs.data(), h->cabs.size() * 4, hipMemcpyHostToDevice, h->stream));
+        if (!h->cwin.empty()) {
+            HIPCHK(h, hipMemcpyAsync(h->d_cwin, h->cwin.data(), h->cwin.size() * 4, hipMemcpyHostToDevice,
+                                     h->stream));
+            HIPCHK(h, hipMemcpyAsync(h->d_crel, h->crel.data(), h->crel.size() * 2, hipMemcpyHostToDevice,
+                                     h->stream));
+        }
         if (h->row32) {
             std::vector<uint32_t> r32(h->crow.size());
             for (size_t g = 0; g < r32.size(); ++g)
@@ -1356,13 +1451,15 @@ int lsm_set_prefetch(lsm_handle *h, int rows_ahead) {
 int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     if (!h) return LSM_EINVAL;
     if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_SWEEP &&
-        variant != LSM_KERNEL_SWEEP2 && variant != LSM_KERNEL_SMALL && variant != LSM_KERNEL_COMPACT)
+        variant != LSM_KERNEL_SWEEP2 && variant != LSM_KERNEL_SMALL && variant != LSM_KERNEL_COMPACT &&
+        variant != LSM_KERNEL_COMPACT_DIRECT)
         return fail(h, LSM_EINVAL, "unknown kernel variant");
-    if (variant == LSM_KERNEL_COMPACT && h->dim != 3)
+    const bool compact = variant == LSM_KERNEL_COMPACT || variant == LSM_KERNEL_COMPACT_DIRECT;
+    if (compact && h->dim != 3)
         return fail(h, LSM_EINVAL, "the compact layout is 3D only");
     if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && !linear_law(h))
         return fail(h, LSM_EINVAL, "spring laws other than the linear one run the gather kernel only");
-    if (variant == LSM_KERNEL_COMPACT && h->built && h->crow.empty())
+    if (compact && h->built && h->crow.empty())
         return fail(h, LSM_EINVAL, "lattice too large for the compact layout");
     if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");
     if (variant == LSM_KERNEL_SMALL && h->built && !small_fits(h))
@@ -1504,7 +1601,8 @@ int lsm_get_launch(const lsm_handle *h, lsm_tuning *out) {
     const int variant = use_sweep2(h)    ? LSM_KERNEL_SWEEP2
                         : use_sweep(h)   ? LSM_KERNEL_SWEEP
                         : use_small(h)   ? LSM_KERNEL_SMALL
-                        : use_compact(h) ? LSM_KERNEL_COMPACT
+                        : use_window(h)  ? LSM_KERNEL_COMPACT
+                        : use_compact(h) ? LSM_KERNEL_COMPACT_DIRECT
                                          : LSM_KERNEL_GATHER;
     *out = lsm_tuning{variant, rows_of(h), h->sw_pf, use_sweep2(h) ? 2 : 1, 0.0};
     return LSM_OK;
@@ -1515,9 +1613,10 @@ int lsm_step_bytes(const lsm_handle *h, int64_t *bytes) {
     if (!h->built) return LSM_ESTATE;
     // per particle and launch: displacement and velocity read and written,
     // flag byte, break mask read (and rewritten by the two-step sweep), and
-    // the packed coordinates in particle-list mode
+    // the packed coordinates in particle-list mode -- or, with LDS windows,
+    // the eight 16-bit row entries
     *bytes = h->n * int64_t(2 * (h->ub + h->vb) + 1 + h->mb + (use_sweep2(h) ? h->mb : 0) +
-                            (h->plist.empty() ? 0 : 4));
+                            (use_window(h) ? 16 : (h->plist.empty() ? 0 : 4)));
     return LSM_OK;
 }
 

@@ -559,7 +559,14 @@ __device__ __attribute__((always_inline)) inline void spring_eval(
     o.r2 = R(0);
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        o.dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
+        if constexpr (DIM == 3) {
+            // 3D: no term for a zero lattice offset, and no low words in
+            // FP64 (they are zero); the same values up to the sign of a zero
+            const R du = PREC == 1 ? (uqh[c] - uph[c]) + (uql[c] - upl[c]) : uqh[c] - uph[c];
+            o.dv[c] = G::off(d, c) == 0 ? du : e[c] + du;
+        } else {
+            o.dv[c] = e[c] + ((uqh[c] - uph[c]) + (uql[c] - upl[c]));
+        }
         o.r2 += o.dv[c] * o.dv[c];
     }
     o.margin = 0.0;
@@ -995,6 +1002,195 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
     integrate_site<3, PREC, kMid>(P, CStore<PREC>{uint32_t(p), ns}, fp, mass_s[pa], imass_s[pa], uph, upl, F, w,
                                   red);
     if (newmask != mask) reinterpret_cast<uint32_t *>(P.mask)[p] = newmask;
+}
+
+// Interior step of a single-phase 3D lattice in the compact layout, with
+// the displacements a workgroup reads staged in LDS.  The workgroup's 256
+// consecutive particles lie between grid sites g0 and g1; all their
+// neighbours in plane offset dk lie between sites g0 - nx - 1 and
+// g1 + nx + 1 of that plane, a contiguous run of particles (raster order),
+// the window of dk.  The three windows are copied one after the other into
+// an LDS pool of POOL records with coalesced loads before any spring is
+// evaluated.  A per-particle entry per off-row grid row -- the offset in
+// that plane's window of the row's site at the particle's x, and whether
+// that site is solid -- gives the neighbours in the row (x - 1: entry - 1,
+// x: entry, x + 1: entry + solid bit); the own row's neighbours are p - 1
+// and p + 1.  A workgroup whose windows exceed the pool reads every
+// neighbour from global memory.  Arithmetic and summation order
+// are those of the gather kernel, so state, break bits and events are
+// bitwise the same.
+template <int PREC, int POOL>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step_c3w(StepParams P,
+                                                                                         int step_local) {
+    constexpr int GRP = PREC ? 3 : 6;  // FP32-compensated: fewer registers, four waves per SIMD
+    using CS = CState<PREC>;
+    using R = typename CS::R;
+    using G = Geo<3>;
+    using TTy = typename TT<PREC>::type;
+    using VA = typename std::conditional<PREC == 1, float4, double2>::type;  // 16-byte record part
+    using VB = typename std::conditional<PREC == 1, float2, double>::type;   // 8-byte record part
+    constexpr int NG = G::ND / GRP;
+    constexpr int NIT = (POOL + kBlock - 1) / kBlock;
+    static_assert(G::ND % GRP == 0, "groups must tile the 18 directions");
+    __shared__ VA wa[POOL];
+    __shared__ VB wb[POOL];
+    const int b = blockIdx.x;
+    const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
+    if (lb * kBlock >= P.n_part) return;  // the whole workgroup
+    const int p = lb * kBlock + int(threadIdx.x);
+    const bool act = p < P.n_part;
+    const uint32_t pp = uint32_t(act ? p : P.n_part - 1);
+    const uint32_t ns = uint32_t(P.nsites);
+    const char *ub = static_cast<const char *>(P.u_in);
+    // windows: first particle, records staged, pool offset (uniform)
+    const uint32_t wb0 = P.cwin[lb * 8 + 0], wb1 = P.cwin[lb * 8 + 1], wb2 = P.cwin[lb * 8 + 2];
+    const uint32_t wl0 = P.cwin[lb * 8 + 3], wl1 = P.cwin[lb * 8 + 4], wl2 = P.cwin[lb * 8 + 5];
+    const uint32_t nst = wl0 + wl1 + wl2;  // >= 1: the own particles are in window 1
+    const bool fit = nst <= uint32_t(POOL);
+    // own state first, so its loads are in flight during the window copy
+    R w[3];
+    CS::load_v(P.v, pp, w);
+    const uint32_t mask = reinterpret_cast<const uint32_t *>(P.mask)[pp];
+    const uint8_t fp = P.flags[pp];
+    const uint4 er = reinterpret_cast<const uint4 *>(P.crel)[pp];
+    // window copy in batches of three workgroup rounds: the batch's loads
+    // (index clamped to the last record), then its stores.  (Loads straight
+    // into LDS, all in flight at once, measured slower: 249 against 228 us
+    // per C3 FP64 step.)
+    struct Rec {
+        VA a;
+        VB b;
+    };
+    auto fetch = [&](int it) {
+        const uint32_t x = min(threadIdx.x + uint32_t(it * kBlock), nst - 1u);
+        const uint32_t q = x + (x < wl0 ? wb0 : (x < wl0 + wl1 ? wb1 - wl0 : wb2 - wl0 - wl1));
+        return Rec{*reinterpret_cast<const VA *>(ub + q * 16u), *reinterpret_cast<const VB *>(ub + (ns * 16u + q * 8u))};
+    };
+    auto put = [&](int it, const Rec &r) {
+        const uint32_t x = threadIdx.x + uint32_t(it * kBlock);
+        if (x < nst) {
+            wa[x] = r.a;
+            wb[x] = r.b;
+        }
+    };
+#pragma unroll
+    for (int it = 0; it < NIT; it += 3) {
+        if (!fit || uint32_t(it * kBlock) >= nst) break;
+        const Rec r0 = fetch(it);
+        const Rec r1 = fetch(it + 1 < NIT ? it + 1 : it);
+        const Rec r2 = fetch(it + 2 < NIT ? it + 2 : it);
+        put(it, r0);
+        if (it + 1 < NIT) put(it + 1, r1);
+        if (it + 2 < NIT) put(it + 2, r2);
+    }
+    __syncthreads();
+    if (!act) return;
+    const uint32_t qmax = uint32_t(P.n_part - 1);
+    const uint32_t wbase[3] = {wb0, wb1, wb2};
+    const uint32_t soff[3] = {0u, wl0, wl0 + wl1};
+    // spring types of the two geometry classes (phase 0 with itself)
+    const TTy T0 = TT<PREC>::make(P.types[0]), T1 = TT<PREC>::make(P.types[LSM_MAX_PHASES * LSM_MAX_PHASES]);
+    const double mass = P.mass[0];
+    const R imass = R(1.0 / mass);
+    auto lds = [&](uint32_t x, R *qh, R *ql) {
+        const VA a = wa[x];
+        const VB c = wb[x];
+        if constexpr (PREC == 1) {
+            qh[0] = a.x; qh[1] = a.y; qh[2] = a.z; ql[0] = a.w; ql[1] = c.x; ql[2] = c.y;
+        } else {
+            qh[0] = a.x; qh[1] = a.y; qh[2] = c;
+            ql[0] = 0.0; ql[1] = 0.0; ql[2] = 0.0;
+        }
+    };
+    // record t of window wi: from the pool (an offset beyond the window
+    // belongs to an absent spring and reads a clamped slot), or from global
+    // memory when the windows exceed the pool
+    auto ld = [&](auto fit_c, int wi, uint32_t t, R *qh, R *ql) {
+        if constexpr (decltype(fit_c)::value) lds(min(soff[wi] + t, uint32_t(POOL - 1)), qh, ql);
+        else CS::load_u(P.u_in, min(wbase[wi] + t, qmax), ns, qh, ql);
+    };
+    const uint32_t t0 = uint32_t(p) - wb1;
+    // entries of the off-row rows, slot (dj + 1) * 3 + (dk + 1) without the own row
+    const uint32_t ent[8] = {er.x & 0xFFFFu, er.x >> 16, er.y & 0xFFFFu, er.y >> 16,
+                             er.z & 0xFFFFu, er.z >> 16, er.w & 0xFFFFu, er.w >> 16};
+    // neighbour in direction d: window and offset in it
+    auto nbr = [&](int d, int &wi, uint32_t &t) {
+        const int dx = G::di(d, 0), sl = (G::dj(d) + 1) * 3 + (G::dk(d) + 1);
+        wi = G::dk(d) + 1;
+        if (sl == 4) {
+            t = t0 + uint32_t(dx);
+        } else {
+            const uint32_t e = ent[sl < 4 ? sl : sl - 1];
+            const uint32_t r = e >> 1;
+            t = dx < 0 ? r - 1u : (dx > 0 ? r + (e & 1u) : r);
+        }
+    };
+    auto body = [&](auto fit_c) {
+        R uph[3], upl[3];
+        ld(fit_c, 1, t0, uph, upl);
+        R F[3] = {R(0), R(0), R(0)};
+        uint32_t newmask = mask, fbrk = 0;
+        R uqh[GRP][3], uql[GRP][3];
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) {
+#pragma unroll
+            for (int t = 0; t < GRP; ++t) {
+                int wi;
+                uint32_t tq;
+                nbr(gi * GRP + t, wi, tq);
+                ld(fit_c, wi, tq, uqh[t], uql[t]);
+            }
+#pragma unroll
+            for (int t = 0; t < GRP; ++t) {
+                const int d = gi * GRP + t;
+                if (mask & (1u << d)) continue;
+                const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
+                const TTy T = G::geom(d) ? T1 : T0;
+                SpringEval<3, PREC> o;
+                spring_eval<3, PREC>(P, T, ti, d, uph, upl, uqh[t], uql[t], o);
+                if (o.brk) {
+                    newmask |= 1u << d;
+                    if (d < G::NF) fbrk |= 1u << d;
+                    continue;
+                }
+                spring_force_add<3, PREC>(T, o, F);
+            }
+        }
+        // events of forward springs that break (before the update, which
+        // advances uph / upl in place)
+        if (fbrk) {
+            const uint32_t pc = P.plist[p];
+            const int i = int(pc & 1023u), j = int((pc >> 10) & 2047u), k = int(pc >> 21);
+            const int gg = i + P.nx * (j + P.ny * k);
+            // (directions unrolled: the row entries and windows stay in registers)
+#pragma unroll
+            for (int d = 0; d < G::NF; ++d) {
+                if (!(fbrk & (1u << d))) continue;
+                int wi;
+                uint32_t tq;
+                nbr(d, wi, tq);
+                R qh[3], ql[3];
+                ld(fit_c, wi, tq, qh, ql);
+                const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
+                SpringEval<3, PREC> o;
+                spring_eval<3, PREC>(P, G::geom(d) ? T1 : T0, ti, d, uph, upl, qh, ql, o);
+                const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                if (idx < P.ev_cap) {
+                    lsm_event ev;
+                    ev.increment = P.ctl->inc;
+                    ev.step = P.ctl->step_base + step_local;
+                    ev.spring_id = int64_t(P.sbase[gg]) + __popc(~P.cabs[p] & ((1u << d) - 1u));
+                    ev.margin = o.margin;
+                    P.events[idx] = ev;
+                }
+            }
+        }
+        double red[1] = {0.0};
+        integrate_site<3, PREC, kMid>(P, CStore<PREC>{uint32_t(p), ns}, fp, mass, imass, uph, upl, F, w, red);
+        if (newmask != mask) reinterpret_cast<uint32_t *>(P.mask)[p] = newmask;
+    };
+    if (fit) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 // ------------------------------------------------------- local fields
@@ -2254,9 +2450,12 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
     return prec ? launch_step_t<3, 1>(p, mode, s, step_local) : launch_step_t<3, 0>(p, mode, s, step_local);
 }
 
-hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local, int row32) {
+hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local, int kind) {
     const dim3 grid(p.c_blocks), block(kBlock);
-    if (row32) {
+    if (kind == 2) {
+        if (prec) hipLaunchKernelGGL((k_step_c3w<1, kC3PoolF32>), grid, block, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_step_c3w<0, kC3PoolF64>), grid, block, 0, s, p, step_local);
+    } else if (kind == 1) {
         if (prec) hipLaunchKernelGGL((k_step_c3<1, true>), grid, block, 0, s, p, step_local);
         else hipLaunchKernelGGL((k_step_c3<0, true>), grid, block, 0, s, p, step_local);
     } else {

@@ -21,6 +21,7 @@ TRI2D, SC3D = 0, 1
 FP64, FP32_KAHAN = 0, 1
 PRED_AFFINE, PRED_GRIPS_ONLY = 0, 1
 KERNEL_AUTO, KERNEL_GATHER, KERNEL_SWEEP, KERNEL_SWEEP2, KERNEL_SMALL, KERNEL_COMPACT = 0, 1, 2, 3, 4, 5
+KERNEL_COMPACT_DIRECT = 6
 MAX_PHASES = 8
 
 EXPORTS = (
@@ -362,7 +363,8 @@ class Lattice:
 
     def set_launch(self, variant="auto", rows_per_wave=0):
         v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
-             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT}[variant]
+             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT,
+             "compact_direct": KERNEL_COMPACT_DIRECT}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def set_prefetch(self, rows_ahead):
@@ -375,7 +377,8 @@ class Lattice:
         n = C.c_int()
         self._check(self._L.lsm_autotune(self._h, int(steps_per_trial), buf, 64, C.byref(n)))
         names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2",
-                 KERNEL_SMALL: "small", KERNEL_COMPACT: "compact"}
+                 KERNEL_SMALL: "small", KERNEL_COMPACT: "compact",
+                 KERNEL_COMPACT_DIRECT: "compact_direct"}
         return [(names.get(t.variant, "auto"), t.rows_per_wave, t.prefetch, t.us_per_step)
                 for t in buf[:n.value]]
 
@@ -383,7 +386,8 @@ class Lattice:
         t = Tuning()
         self._check(self._L.lsm_get_launch(self._h, C.byref(t)))
         names = {KERNEL_AUTO: "auto", KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep",
-                 KERNEL_SWEEP2: "sweep2", KERNEL_SMALL: "small", KERNEL_COMPACT: "compact"}
+                 KERNEL_SWEEP2: "sweep2", KERNEL_SMALL: "small", KERNEL_COMPACT: "compact",
+                 KERNEL_COMPACT_DIRECT: "compact_direct"}
         return dict(variant=names[t.variant], rows_per_wave=t.rows_per_wave, prefetch=t.prefetch,
                     steps_per_launch=t.steps_per_launch)
 
@@ -441,13 +445,22 @@ class HostModel:
     def set_launch(self, variant="auto", rows_per_wave=0):
         """Kernel variant whose bytes step_bytes reports (no device call)."""
         v = {"auto": KERNEL_AUTO, "gather": KERNEL_GATHER, "sweep": KERNEL_SWEEP,
-             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT}[variant]
+             "sweep2": KERNEL_SWEEP2, "small": KERNEL_SMALL, "compact": KERNEL_COMPACT,
+             "compact_direct": KERNEL_COMPACT_DIRECT}[variant]
         self._check(self._L.lsm_set_launch(self._h, v, int(rows_per_wave)))
 
     def step_bytes(self) -> int:
         b = C.c_int64()
         self._check(self._L.lsm_step_bytes(self._h, C.byref(b)))
         return b.value
+
+    def launch_variant(self) -> str:
+        """The kernel that would run the interior steps (no device call)."""
+        t = Tuning()
+        self._check(self._L.lsm_get_launch(self._h, C.byref(t)))
+        names = {KERNEL_GATHER: "gather", KERNEL_SWEEP: "sweep", KERNEL_SWEEP2: "sweep2",
+                 KERNEL_SMALL: "small", KERNEL_COMPACT: "compact", KERNEL_COMPACT_DIRECT: "compact_direct"}
+        return names[t.variant]
 
 
 BATCH_EXPORTS = (

@@ -88,12 +88,18 @@ def test_c2_full_size_counts():
 def test_3d_step_bytes_count_the_particle_list():
     # 3D fp32k: u (24 B) and v (12 B) read and written, flag, 4-byte break
     # mask, and the packed coordinates of the one-thread-per-particle launch
+    # -- or the eight 16-bit row entries of the LDS-window kernel
     img = inputs.gaussian_random_field_3d(24, seed=3)
     wl = inputs.WORKLOADS["c3"]
     g = _model(img, wl, precision="fp32k")
     assert g.n == int((img != inputs.VOID).sum()) > 0
+    assert g.launch_variant() == "compact"
+    assert g.step_bytes() == g.n * (2 * (24 + 12) + 1 + 4 + 16)
+    g.set_launch("compact_direct")
     assert g.step_bytes() == g.n * (2 * (24 + 12) + 1 + 4 + 4)
     g64 = _model(img, wl, precision="fp64")
+    assert g64.step_bytes() == g64.n * (2 * (24 + 24) + 1 + 4 + 16)
+    g64.set_launch("gather")
     assert g64.step_bytes() == g64.n * (2 * (24 + 24) + 1 + 4 + 4)
 
 
@@ -116,6 +122,33 @@ def test_compact_kernel_variant_rules():
     _model(img3, inputs.WORKLOADS["c3"], precision="fp32k").set_launch("compact")
     with pytest.raises(lsm.LsmError):
         _model(inputs.c1_image(), inputs.WORKLOADS["c1"]).set_launch("compact")
+    with pytest.raises(lsm.LsmError):
+        _model(inputs.c1_image(), inputs.WORKLOADS["c1"]).set_launch("compact_direct")
+
+
+def test_compact_kernel_stages_windows_where_they_fit():
+    # single-phase lattices stage their neighbours in LDS windows; two
+    # phases, or a window of 2^15 particles or more, read them directly
+    wl3 = inputs.WORKLOADS["c3"]
+    g = _model(inputs.gaussian_random_field_3d(20, seed=2), wl3)
+    assert g.launch_variant() == "compact"
+    g.set_launch("compact_direct")
+    assert g.launch_variant() == "compact_direct"
+    g.set_launch("compact")
+    assert g.launch_variant() == "compact"
+    rng = np.random.default_rng(1)
+    two = dict(wl3, k=[[1.0, float("nan")], [float("nan"), 0.3]], s=[[0.03, float("nan")], [float("nan"), 0.08]],
+               mass=[1.0, 2.0])
+    assert _model(rng.integers(0, 2, size=(6, 7, 8)).astype(np.uint8), two).launch_variant() == "compact_direct"
+    # a sparse plane (one particle every 128 sites) under a full one: the
+    # first workgroup's 256 particles span 32,768 sites of plane 0, so its
+    # window in plane 1 holds more than 2^15 particles
+    img = np.zeros((2, 40, 1024), np.uint8)
+    img[0].reshape(-1)[np.arange(0, 40 * 1024) % 128 != 0] = inputs.VOID
+    assert _model(img, wl3).launch_variant() == "compact_direct"
+    img[0] = inputs.VOID
+    img[0, :, :64] = 0
+    assert _model(img, wl3).launch_variant() == "compact"
 
 
 def test_table2_paper_mode_types():
