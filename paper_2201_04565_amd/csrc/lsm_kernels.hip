@@ -533,27 +533,29 @@ struct SpringEval {
     double r64;
 };
 
+// (alat: the lattice constant P.a, passed by kernels that keep it in a
+// register across their unrolled spring loops)
 template <int DIM, int PREC>
 __device__ __attribute__((always_inline)) inline void spring_eval(
-    const StepParams &P, const typename TT<PREC>::type &T, int ti, int d, const typename State<DIM, PREC>::R *uph,
-    const typename State<DIM, PREC>::R *upl, const typename State<DIM, PREC>::R *uqh,
-    const typename State<DIM, PREC>::R *uql, SpringEval<DIM, PREC> &o) {
+    const StepParams &P, double alat, const typename TT<PREC>::type &T, int ti, int d,
+    const typename State<DIM, PREC>::R *uph, const typename State<DIM, PREC>::R *upl,
+    const typename State<DIM, PREC>::R *uqh, const typename State<DIM, PREC>::R *uql, SpringEval<DIM, PREC> &o) {
     using R = typename State<DIM, PREC>::R;
     using G = Geo<DIM>;
-    const R a = R(P.a);
-    const R hy = R(kHalfSqrt3 * P.a);
+    const R a = R(alat);
+    const R hy = R(kHalfSqrt3 * alat);
     // lattice vector X0_q - X0_p
     R e[DIM];
     if constexpr (DIM == 2) {
         e[0] = R(G::ex(d)) * a;
         e[1] = R(G::ey(d)) * hy;
-        o.e64[0] = G::ex(d) * P.a;
-        o.e64[1] = G::ey(d) * (kHalfSqrt3 * P.a);
+        o.e64[0] = G::ex(d) * alat;
+        o.e64[1] = G::ey(d) * (kHalfSqrt3 * alat);
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             e[c] = R(G::off(d, c)) * a;
-            o.e64[c] = double(G::off(d, c)) * P.a;
+            o.e64[c] = double(G::off(d, c)) * alat;
         }
     }
     o.r2 = R(0);
@@ -605,6 +607,14 @@ __device__ __attribute__((always_inline)) inline void spring_eval(
     }
 }
 
+template <int DIM, int PREC>
+__device__ __attribute__((always_inline)) inline void spring_eval(
+    const StepParams &P, const typename TT<PREC>::type &T, int ti, int d, const typename State<DIM, PREC>::R *uph,
+    const typename State<DIM, PREC>::R *upl, const typename State<DIM, PREC>::R *uqh,
+    const typename State<DIM, PREC>::R *uql, SpringEval<DIM, PREC> &o) {
+    spring_eval<DIM, PREC>(P, P.a, T, ti, d, uph, upl, uqh, uql, o);
+}
+
 // Eq. 2 force of an intact spring added to the force on p.  cubic != 0
 // scales it by 1 + c d^2 / r0^2 (d = r - r0), the cubic spring law.
 template <int DIM, int PREC>
@@ -643,6 +653,16 @@ __device__ __attribute__((always_inline)) inline void spring_force_add(const typ
             o.d64[c] = o.dv[c];
         }
     }
+}
+
+// The 3D FP64 linear force of spring_force_add with -(k r0) precomputed
+// (nkr0 = -(T.x * T.y), the same product): the same result.
+__device__ __attribute__((always_inline)) inline void spring_force_add_f64(const D4 &T, double nkr0,
+                                                                          const SpringEval<3, 0> &o, double *F) {
+    const double rinv = rsqrt_pos(o.r2);
+    const double coef = fma(nkr0, rinv, T.x);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) F[c] += coef * o.dv[c];
 }
 
 // ------------------------------------------------------------ step kernel
@@ -1090,6 +1110,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t soff[3] = {0u, wl0, wl0 + wl1};
     // spring types of the two geometry classes (phase 0 with itself)
     const TTy T0 = TT<PREC>::make(P.types[0]), T1 = TT<PREC>::make(P.types[LSM_MAX_PHASES * LSM_MAX_PHASES]);
+    const double nk0 = -(double(T0.x) * double(T0.y)), nk1 = -(double(T1.x) * double(T1.y));  // FP64 only
+    const double alat = P.a;
     const double mass = P.mass[0];
     const R imass = R(1.0 / mass);
     auto lds = [&](uint32_t x, R *qh, R *ql) {
@@ -1147,13 +1169,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
                 const TTy T = G::geom(d) ? T1 : T0;
                 SpringEval<3, PREC> o;
-                spring_eval<3, PREC>(P, T, ti, d, uph, upl, uqh[t], uql[t], o);
+                spring_eval<3, PREC>(P, alat, T, ti, d, uph, upl, uqh[t], uql[t], o);
                 if (o.brk) {
                     newmask |= 1u << d;
                     if (d < G::NF) fbrk |= 1u << d;
                     continue;
                 }
-                spring_force_add<3, PREC>(T, o, F);
+                if constexpr (PREC == 0) spring_force_add_f64(T, G::geom(d) ? nk1 : nk0, o, F);
+                else spring_force_add<3, PREC>(T, o, F);
             }
         }
         // events of forward springs that break (before the update, which
@@ -1173,7 +1196,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
                 ld(fit_c, wi, tq, qh, ql);
                 const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
                 SpringEval<3, PREC> o;
-                spring_eval<3, PREC>(P, G::geom(d) ? T1 : T0, ti, d, uph, upl, qh, ql, o);
+                spring_eval<3, PREC>(P, alat, G::geom(d) ? T1 : T0, ti, d, uph, upl, qh, ql, o);
                 const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
                 if (idx < P.ev_cap) {
                     lsm_event ev;
