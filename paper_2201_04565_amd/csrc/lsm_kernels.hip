@@ -1073,10 +1073,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint32_t mask = reinterpret_cast<const uint32_t *>(P.mask)[pp];
     const uint8_t fp = P.flags[pp];
     const uint4 er = reinterpret_cast<const uint4 *>(P.crel)[pp];
-    // window copy in batches of three workgroup rounds: the batch's loads
-    // (index clamped to the last record), then its stores.  (Loads straight
-    // into LDS, all in flight at once, measured slower: 249 against 228 us
-    // per C3 FP64 step.)
+    // window copy: the loads of every round the windows need (index clamped
+    // to the last record), then the stores.  (Batches of three or four
+    // rounds measured 1-3 % slower; loads straight into LDS, 249 against
+    // 228 us per C3 FP64 step.)
     struct Rec {
         VA a;
         VB b;
@@ -1093,15 +1093,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
             wb[x] = r.b;
         }
     };
+    if (fit) {
+        const int nr = int((nst + kBlock - 1) / kBlock);  // rounds needed (uniform)
+        Rec r[NIT];
 #pragma unroll
-    for (int it = 0; it < NIT; it += 3) {
-        if (!fit || uint32_t(it * kBlock) >= nst) break;
-        const Rec r0 = fetch(it);
-        const Rec r1 = fetch(it + 1 < NIT ? it + 1 : it);
-        const Rec r2 = fetch(it + 2 < NIT ? it + 2 : it);
-        put(it, r0);
-        if (it + 1 < NIT) put(it + 1, r1);
-        if (it + 2 < NIT) put(it + 2, r2);
+        for (int it = 0; it < NIT; ++it)
+            if (it < nr) r[it] = fetch(it);
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (it < nr) put(it, r[it]);
     }
     __syncthreads();
     if (!act) return;
