@@ -88,6 +88,7 @@ struct lsm_handle {
     // particle eight 16-bit row entries
     std::vector<uint32_t> cwin;
     std::vector<uint16_t> crel;
+    int c_wblocks = 0;                // workgroups of the window kernel (a multiple of 8)
     std::vector<uint8_t> cflag;
     int64_t cn = 0;                   // particle stride of the compact arrays
     void *d_cu[2] = {nullptr, nullptr}, *d_cv = nullptr;
@@ -274,6 +275,7 @@ StepParams make_params(const lsm_handle *h, int in_buf, int out_buf) {
     p.n_part = int32_t(h->n);
     p.plist = h->plist.empty() ? nullptr : h->d_plist;
     p.c_blocks = h->c_blocks;
+    p.c_wblocks = h->c_wblocks;
     p.red_blocks = p.plist ? p.c_blocks : p.nblocks;
     p.law = h->cfg.spring_law;
     p.law_c = h->cfg.law_c;
@@ -589,7 +591,7 @@ void lsm_destroy(lsm_handle *h) {
 }
 
 // LDS windows of the compact 3D interior step (single-phase lattices).  The
-// particles of workgroup lb (lsm::kBlock consecutive ones, sites g0 .. g1)
+// particles of workgroup lb (lsm::kC3WinBlock consecutive ones, sites g0 .. g1)
 // have all their neighbours in plane offset dk among the sites
 // g0 - nx - 1 + dk nx ny .. g1 + nx + 1 + dk nx ny: a contiguous run of
 // particles, the window, whose first particle and length are kept per
@@ -602,8 +604,8 @@ static void build_windows_3d(lsm_handle *h) {
     h->cwin.clear();
     h->crel.clear();
     const int64_t nx = h->nx, ny = h->ny, nz = h->nz, ns = h->nsites, n = h->n;
-    const int64_t B = lsm::kBlock, nb = h->c_blocks;
-    if (n < 1 || nb * B < n) return;
+    const int64_t B = lsm::kC3WinBlock, nb = ((n + B - 1) / B + 7) / 8 * 8;
+    if (n < 1) return;
     auto before = [&](int64_t g) { return int64_t(h->crow[size_t(g)] >> 32); };  // g in [0, ns]
     std::vector<uint32_t> win(size_t(nb) * 8, 0);
     for (int64_t lb = 0; lb * B < n; ++lb) {
@@ -655,6 +657,7 @@ static void build_windows_3d(lsm_handle *h) {
     }
     h->cwin.swap(win);
     h->crel.swap(rel);
+    h->c_wblocks = int(nb);
 }
 
 // Tables of the compact 3D layout: the row table (per site: particles

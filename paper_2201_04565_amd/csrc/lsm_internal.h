@@ -117,13 +117,15 @@ struct StepParams {
     // (bits 0-17) whose neighbour is void or off the grid
     const uint64_t *crow;
     const uint32_t *cabs;
-    // LDS-window variant (single-phase lattices): per workgroup of kBlock
-    // particles, cwin[8 lb ..] = first particle of the windows of plane
+    // LDS-window variant (single-phase lattices): per workgroup of
+    // kC3WinBlock particles (c_wblocks workgroups, a multiple of 8),
+    // cwin[8 lb ..] = first particle of the windows of plane
     // offsets -1, 0, +1, then their lengths; per particle crel = eight
     // 16-bit entries (offset in the plane's window << 1 | solid) of the
     // off-row grid rows, slots (dj + 1) * 3 + (dk + 1) without the own row
     const uint32_t *cwin;
     const void *crel;
+    int32_t c_wblocks;
     // spring law (LSM_SPRING_*) and the cubic coefficient; only the gather
     // kernel (and the local fields) take a law other than the linear one
     int32_t law;
@@ -163,10 +165,13 @@ hipError_t launch_kick_drift(const StepParams &p, int dim, int prec, hipStream_t
 // solid) of a single-phase lattice; 2: LDS windows (cwin / crel) of a
 // single-phase lattice
 hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t stream, int step_local, int kind);
-// records of the three plane windows staged in LDS by the window variant
-// (39 KB: four workgroups per CU)
-constexpr int kC3PoolF64 = 1664;
-constexpr int kC3PoolF32 = 1664;
+// particles per workgroup of the window variant (eight wavefronts: 4.3
+// window records per particle on the C3 lattice against 5.6 for 256), and
+// the records of the three plane windows it stages in LDS (66 KB: two
+// workgroups per CU)
+constexpr int kC3WinBlock = 512;
+constexpr int kC3PoolF64 = 2816;
+constexpr int kC3PoolF32 = 2816;
 hipError_t launch_pack_c3(const StepParams &p, int prec, hipStream_t stream, int to_compact, void *u_grid,
                           void *v_grid, uint32_t *m_grid, void *u_c, void *v_c, uint32_t *m_c, int64_t cn);
 // Local fields of the state in u_in / v / mask (particle order, FP64

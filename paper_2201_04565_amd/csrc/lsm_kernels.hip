@@ -1025,8 +1025,8 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
 }
 
 // Interior step of a single-phase 3D lattice in the compact layout, with
-// the displacements a workgroup reads staged in LDS.  The workgroup's 256
-// consecutive particles lie between grid sites g0 and g1; all their
+// the displacements a workgroup reads staged in LDS.  The workgroup's
+// kC3WinBlock consecutive particles lie between grid sites g0 and g1; all their
 // neighbours in plane offset dk lie between sites g0 - nx - 1 and
 // g1 + nx + 1 of that plane, a contiguous run of particles (raster order),
 // the window of dk.  The three windows are copied one after the other into
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
 // are those of the gather kernel, so state, break bits and events are
 // bitwise the same.
 template <int PREC, int POOL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step_c3w(StepParams P,
+__global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step_c3w(StepParams P,
                                                                                          int step_local) {
     constexpr int GRP = PREC ? 3 : 6;  // FP32-compensated: fewer registers, four waves per SIMD
     using CS = CState<PREC>;
@@ -1050,14 +1050,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     using VA = typename std::conditional<PREC == 1, float4, double2>::type;  // 16-byte record part
     using VB = typename std::conditional<PREC == 1, float2, double>::type;   // 8-byte record part
     constexpr int NG = G::ND / GRP;
-    constexpr int NIT = (POOL + kBlock - 1) / kBlock;
+    constexpr int NIT = (POOL + kC3WinBlock - 1) / kC3WinBlock;
     static_assert(G::ND % GRP == 0, "groups must tile the 18 directions");
     __shared__ VA wa[POOL];
     __shared__ VB wb[POOL];
     const int b = blockIdx.x;
-    const int lb = (b & 7) * (P.c_blocks >> 3) + (b >> 3);
-    if (lb * kBlock >= P.n_part) return;  // the whole workgroup
-    const int p = lb * kBlock + int(threadIdx.x);
+    const int lb = (b & 7) * (P.c_wblocks >> 3) + (b >> 3);
+    if (lb * kC3WinBlock >= P.n_part) return;  // the whole workgroup
+    const int p = lb * kC3WinBlock + int(threadIdx.x);
     const bool act = p < P.n_part;
     const uint32_t pp = uint32_t(act ? p : P.n_part - 1);
     const uint32_t ns = uint32_t(P.nsites);
@@ -1082,19 +1082,19 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         VB b;
     };
     auto fetch = [&](int it) {
-        const uint32_t x = min(threadIdx.x + uint32_t(it * kBlock), nst - 1u);
+        const uint32_t x = min(threadIdx.x + uint32_t(it * kC3WinBlock), nst - 1u);
         const uint32_t q = x + (x < wl0 ? wb0 : (x < wl0 + wl1 ? wb1 - wl0 : wb2 - wl0 - wl1));
         return Rec{*reinterpret_cast<const VA *>(ub + q * 16u), *reinterpret_cast<const VB *>(ub + (ns * 16u + q * 8u))};
     };
     auto put = [&](int it, const Rec &r) {
-        const uint32_t x = threadIdx.x + uint32_t(it * kBlock);
+        const uint32_t x = threadIdx.x + uint32_t(it * kC3WinBlock);
         if (x < nst) {
             wa[x] = r.a;
             wb[x] = r.b;
         }
     };
     if (fit) {
-        const int nr = int((nst + kBlock - 1) / kBlock);  // rounds needed (uniform)
+        const int nr = int((nst + kC3WinBlock - 1) / kC3WinBlock);  // rounds needed (uniform)
         Rec r[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it)
@@ -2476,8 +2476,9 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
 hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local, int kind) {
     const dim3 grid(p.c_blocks), block(kBlock);
     if (kind == 2) {
-        if (prec) hipLaunchKernelGGL((k_step_c3w<1, kC3PoolF32>), grid, block, 0, s, p, step_local);
-        else hipLaunchKernelGGL((k_step_c3w<0, kC3PoolF64>), grid, block, 0, s, p, step_local);
+        const dim3 wgrid(p.c_wblocks), wblock(kC3WinBlock);
+        if (prec) hipLaunchKernelGGL((k_step_c3w<1, kC3PoolF32>), wgrid, wblock, 0, s, p, step_local);
+        else hipLaunchKernelGGL((k_step_c3w<0, kC3PoolF64>), wgrid, wblock, 0, s, p, step_local);
     } else if (kind == 1) {
         if (prec) hipLaunchKernelGGL((k_step_c3<1, true>), grid, block, 0, s, p, step_local);
         else hipLaunchKernelGGL((k_step_c3<0, true>), grid, block, 0, s, p, step_local);
