@@ -627,7 +627,7 @@ static void build_windows_3d(lsm_handle *h) {
         for (int sl = 0; sl < 9; ++sl) {
             if (sl == 4) continue;
             const int dj = sl / 3 - 1, dk = sl % 3 - 1;
-            uint16_t v = 2;  // a row off the grid: offset 1, void (its springs are absent)
+            uint16_t v = 0;  // a row off the grid: offset 0, void (its springs are absent)
             if (j + dj >= 0 && j + dj < ny && k + dk >= 0 && k + dk < nz) {
                 const int64_t gq = g + nx * (dj + ny * dk);
                 const int64_t off = before(gq) - int64_t(win[size_t(lb * 8 + dk + 1)]);
@@ -636,10 +636,14 @@ static void build_windows_3d(lsm_handle *h) {
             }
             rel[size_t(c * 8 + e++)] = v;
         }
-        // the neighbour the step kernel takes for every intact spring
+        // the neighbour the step kernel takes for every intact spring, and
+        // the pool slot it reads for every direction (slot 1 + offset in the
+        // pooled windows, which must lie in 0 .. pool + 1 when they fit)
         const uint32_t absent = h->cabs[size_t(c)];
+        const int64_t wl[3] = {win[size_t(lb * 8 + 3)], win[size_t(lb * 8 + 4)], win[size_t(lb * 8 + 5)]};
+        const int64_t pool = std::min(lsm::kC3PoolF64, lsm::kC3PoolF32);
+        const bool fits = wl[0] + wl[1] + wl[2] <= pool;
         for (int d = 0; d < 18; ++d) {
-            if (absent & (1u << d)) continue;
             const int sgn = d < 9 ? 1 : -1;
             const int dx = sgn * kFwd3[d % 9][0], dj = sgn * kFwd3[d % 9][1], dk = sgn * kFwd3[d % 9][2];
             const int sl = (dj + 1) * 3 + (dk + 1);
@@ -651,8 +655,11 @@ static void build_windows_3d(lsm_handle *h) {
                 const int64_t ent = rel[size_t(c * 8 + (sl < 4 ? sl : sl - 1))];
                 t = (ent >> 1) + (dx < 0 ? -1 : (dx > 0 ? (ent & 1) : 0));
             }
+            const int64_t slot = 1 + (dk >= 0 ? wl[0] : 0) + (dk > 0 ? wl[1] : 0) + t;
+            if (fits && (slot < 0 || slot > pool + 1)) return;
+            if (absent & (1u << d)) continue;
             const int64_t gq = g + dx + nx * (dj + ny * dk);
-            if (t < 0 || t >= int64_t(win[size_t(lb * 8 + 3 + dk + 1)]) || base + t != before(gq)) return;
+            if (t < 0 || t >= wl[dk + 1] || base + t != before(gq)) return;
         }
     }
     h->cwin.swap(win);

@@ -1052,8 +1052,10 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
     constexpr int NG = G::ND / GRP;
     constexpr int NIT = (POOL + kC3WinBlock - 1) / kC3WinBlock;
     static_assert(G::ND % GRP == 0, "groups must tile the 18 directions");
-    __shared__ VA wa[POOL];
-    __shared__ VB wb[POOL];
+    // pool slot x + 1 holds staged record x: every offset the row entries
+    // give, -1 .. window length, lands inside (slots 0 .. POOL + 1)
+    __shared__ VA wa[POOL + 2];
+    __shared__ VB wb[POOL + 2];
     const int b = blockIdx.x;
     const int lb = (b & 7) * (P.c_wblocks >> 3) + (b >> 3);
     if (lb * kC3WinBlock >= P.n_part) return;  // the whole workgroup
@@ -1089,8 +1091,8 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
     auto put = [&](int it, const Rec &r) {
         const uint32_t x = threadIdx.x + uint32_t(it * kC3WinBlock);
         if (x < nst) {
-            wa[x] = r.a;
-            wb[x] = r.b;
+            wa[x + 1] = r.a;
+            wb[x + 1] = r.b;
         }
     };
     if (fit) {
@@ -1107,7 +1109,7 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
     if (!act) return;
     const uint32_t qmax = uint32_t(P.n_part - 1);
     const uint32_t wbase[3] = {wb0, wb1, wb2};
-    const uint32_t soff[3] = {0u, wl0, wl0 + wl1};
+    const uint32_t soff[3] = {1u, 1u + wl0, 1u + wl0 + wl1};  // slot of each window's first record
     // spring types of the two geometry classes (phase 0 with itself)
     const TTy T0 = TT<PREC>::make(P.types[0]), T1 = TT<PREC>::make(P.types[LSM_MAX_PHASES * LSM_MAX_PHASES]);
     const double nk0 = -(double(T0.x) * double(T0.y)), nk1 = -(double(T1.x) * double(T1.y));  // FP64 only
@@ -1124,11 +1126,12 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
             ql[0] = 0.0; ql[1] = 0.0; ql[2] = 0.0;
         }
     };
-    // record t of window wi: from the pool (an offset beyond the window
-    // belongs to an absent spring and reads a clamped slot), or from global
-    // memory when the windows exceed the pool
+    // record t of window wi: from the pool (an offset outside the window,
+    // -1 or the window length, belongs to an absent spring and reads a
+    // slot of another window or a spare one), or from global memory when
+    // the windows exceed the pool
     auto ld = [&](auto fit_c, int wi, uint32_t t, R *qh, R *ql) {
-        if constexpr (decltype(fit_c)::value) lds(min(soff[wi] + t, uint32_t(POOL - 1)), qh, ql);
+        if constexpr (decltype(fit_c)::value) lds(soff[wi] + t, qh, ql);
         else CS::load_u(P.u_in, min(wbase[wi] + t, qmax), ns, qh, ql);
     };
     const uint32_t t0 = uint32_t(p) - wb1;
