@@ -494,145 +494,148 @@ inline dim3 conv_grid(int64_t npix, int cout) {
 // dw[co, n] = sum_p dout[p, co] * in[shift(p, tap(n)), ci(n)], n = tap * Cin
 // + ci (the [Cout][9][Cin] weight layout flattened), split over pixel
 // ranges: partial[split][co][n] (FP32), summed later in a fixed order.
-// Workgroup tile: 64 co x 64 n (a tile spans two taps when Cin = 32), 64
-// pixels of reduction per LDS stage, four wavefronts of 32 x 32.  Both
-// tiles are staged in their natural [pixel][channel] order with 16-byte
-// stores and read back as MFMA operands with the transposing LDS read
-// (ds_read_b64_tr_b16): within a group of 16 lanes, lane L addressing
-// T[k0 + L / 4][m0 + 4 (L mod 4)] makes lane i receive T[k0 + k][m0 + i],
-// k = 0..3 -- four consecutive reduction elements of row m0 + i, half of
-// an MFMA fragment.  The workgroups of the first n tile also sum dout over
-// their pixels: the bias gradient.
+// Workgroup tile: 64 output channels x 288 columns (a multiple of 288 =
+// 9 x 32 for every Cin), so dout is read once per 288 columns and the input
+// patches once per 64 output channels; 64 pixels of reduction per LDS
+// stage.  Per stage lane l of every wavefront stages pixel l: dout channels
+// 16 w .. 16 w + 15 and input chunks 9 w .. 9 w + 8 (eight columns each; Cin
+// is a power of two >= 32, so a chunk never straddles a tap), with one
+// division of the pixel index per stage.  Both tiles are stored in their
+// natural [pixel][channel] order with 16-byte stores and read back as MFMA
+// operands with the transposing LDS read (ds_read_b64_tr_b16): within a
+// group of 16 lanes, lane L addressing T[k0 + L / 4][m0 + 4 (L mod 4)] makes
+// lane i receive T[k0 + k][m0 + i], k = 0..3 -- four consecutive reduction
+// elements of row m0 + i, half of an MFMA fragment.  Wavefront w computes
+// 32 channels x 144 columns (2 x 9 tiles of 16 x 16).  The workgroups of
+// the first column tile also sum dout over their pixels: the bias gradient.
+// (64 x 64 tiles, which re-read dout for every 64 columns, took 276 us per
+// layer on average against 147.)
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4s lds_v4s;
 
-constexpr int kWgStride = 72;  // u16 per staged pixel row (64 + 8): 144 B, 16-byte aligned
+constexpr int kWwN = 288;          // columns per workgroup
+constexpr int kWwXS = kWwN + 8;    // u16 per staged input pixel row: 592 B, 16-byte aligned
+constexpr int kWwDS = 64 + 8;      // u16 per staged dout pixel row
 
-__device__ inline bf16x8 tr_frag(const u16 *tile, int k0, int m0, int lane16) {
-    const u16 *p0 = tile + (k0 + (lane16 >> 2)) * kWgStride + m0 + 4 * (lane16 & 3);
+template <int S>
+__device__ inline bf16x8 tr_frag_s(const u16 *tile, int k0, int m0, int lane16) {
+    const u16 *p0 = tile + (k0 + (lane16 >> 2)) * S + m0 + 4 * (lane16 & 3);
     union {
         v4s h[2];
         bf16x8 v;
     } u;
     u.h[0] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p0));
-    u.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p0 + 4 * kWgStride));
+    u.h[1] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s *)(p0 + 4 * S));
     return u.v;
 }
 
-__global__ __launch_bounds__(kBlk) void k_conv_wgrad_mfma(const u16 *in, const u16 *dout, float *partial,
+__global__ __launch_bounds__(kBlk) void k_conv_wgrad_wide(const u16 *in, const u16 *dout, float *partial,
                                                          float *bias_partial, int B, int H, int W, int Cin,
-                                                         int Cout, int64_t pix_per_split) {
-    __shared__ __align__(16) u16 sd[64 * kWgStride];  // [pixel][co]
-    __shared__ __align__(16) u16 sx[64 * kWgStride];  // [pixel][n]
-    __shared__ float sb[4][64];                       // bias sums per wavefront
+                                                         int Cout, int pix_per_split) {
+    __shared__ __align__(16) u16 sd[64 * kWwDS];  // [pixel][co]
+    __shared__ __align__(16) u16 sx[64 * kWwXS];  // [pixel][n]
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int N = 9 * Cin;
-    const int co_t = blockIdx.x * 64, n_t = blockIdx.y * 64;
+    const int co_t = blockIdx.x * 64, n_t = blockIdx.y * kWwN;
     const int split = blockIdx.z;
-    const int64_t npix = int64_t(B) * H * W;
-    const int64_t pbeg = int64_t(split) * pix_per_split;
-    const int64_t pend = pbeg + pix_per_split < npix ? pbeg + pix_per_split : npix;
+    const int npix = B * H * W;
+    const int pbeg = split * pix_per_split;
+    const int pend = min(pbeg + pix_per_split, npix);
     const int r16 = lane & 15, kq = lane >> 4;
-    const int wco = (wv >> 1) * 32, wn = (wv & 1) * 32;
+    const int wco = (wv >> 1) * 32, wn = (wv & 1) * 144;
     const bool do_bias = blockIdx.y == 0;
-    // loader: thread t stages pixels t / 8 and t / 8 + 32 of a stage,
-    // channels 8 (t mod 8) .. + 7 of both tiles; its eight n share one tap
-    const int lp = threadIdx.x >> 3, lc = (threadIdx.x & 7) * 8;
-    const int ln = n_t + lc;
-    const bool nok = ln < N;
-    const int ltap = nok ? ln / Cin : 0;
-    const int lci = nok ? ln - ltap * Cin : 0;
-    const int ldy = ltap / 3 - 1, ldx = ltap % 3 - 1;
-    const bool cok = co_t + lc < Cout;
-    f32x4 acc[2][2];
+    const int cshift = __builtin_ctz(unsigned(Cin));
+    f32x4 acc[2][9];
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum[8];
+        for (int c = 0; c < 9; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[16];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) bsum[e] = 0.0f;
-    uint4 rd[2], rx[2];
-    auto gload = [&](int64_t q0) {
+    for (int e = 0; e < 16; ++e) bsum[e] = 0.0f;
+    uint4 rd[2], rx[9];
+    auto gload = [&](int q0) {
+        const int p = q0 + lane;
+        const bool pin = p < pend;
+        const int pp = pin ? p : 0;
+        const int x = pp % W, t = pp / W, y = t % H, n = t / H;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int64_t p = q0 + lp + 32 * h;
-            const bool pin = p < pend;
-            const int64_t pp = pin ? p : 0;
-            const int x = int(pp % W), y = int((pp / W) % H);
-            const int64_t n = pp / (int64_t(H) * W);
-            const int sy = y + ldy, sx2 = x + ldx;
-            const bool dok = pin && cok;
-            const bool xok = pin && nok && sy >= 0 && sy < H && sx2 >= 0 && sx2 < W;
+            const int co = co_t + 16 * wv + 8 * h;
+            const bool dok = pin && co < Cout;
             // unconditional loads from valid addresses, masked afterwards
-            const uint4 vd = *reinterpret_cast<const uint4 *>(dout + (dok ? pp * Cout + co_t + lc : 0));
-            const uint4 vx = *reinterpret_cast<const uint4 *>(in + (xok ? ((n * H + sy) * W + sx2) * Cin + lci : 0));
-            rd[h] = dok ? vd : make_uint4(0, 0, 0, 0);
-            rx[h] = xok ? vx : make_uint4(0, 0, 0, 0);
+            const uint4 v = *reinterpret_cast<const uint4 *>(dout + (dok ? int64_t(pp) * Cout + co : 0));
+            rd[h] = dok ? v : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            const int nn = n_t + 8 * (9 * wv + j);
+            const int tap = nn >> cshift, ci = nn & (Cin - 1);
+            const int sy = y + tap / 3 - 1, sx2 = x + tap % 3 - 1;
+            const bool xok = pin && sy >= 0 && sy < H && sx2 >= 0 && sx2 < W;
+            const uint4 v =
+                *reinterpret_cast<const uint4 *>(in + (xok ? (int64_t((n * H + sy) * W + sx2) << cshift) + ci : 0));
+            rx[j] = xok ? v : make_uint4(0, 0, 0, 0);
         }
     };
     if (pbeg < pend) gload(pbeg);
-    for (int64_t q0 = pbeg; q0 < pend; q0 += 64) {
+    for (int q0 = pbeg; q0 < pend; q0 += 64) {
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            *reinterpret_cast<uint4 *>(sd + (lp + 32 * h) * kWgStride + lc) = rd[h];
-            *reinterpret_cast<uint4 *>(sx + (lp + 32 * h) * kWgStride + lc) = rx[h];
+            *reinterpret_cast<uint4 *>(sd + lane * kWwDS + 16 * wv + 8 * h) = rd[h];
             if (do_bias) {
                 const u16 *e8 = reinterpret_cast<const u16 *>(&rd[h]);
 #pragma unroll
-                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(e8[e]);
+                for (int e = 0; e < 8; ++e) bsum[8 * h + e] += bf2f(e8[e]);
             }
         }
+#pragma unroll
+        for (int j = 0; j < 9; ++j) *reinterpret_cast<uint4 *>(sx + lane * kWwXS + 8 * (9 * wv + j)) = rx[j];
         __syncthreads();
         if (q0 + 64 < pend) gload(q0 + 64);  // next stage in flight during the MFMAs
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-            bf16x8 a[2], b[2];
+            bf16x8 a[2];
 #pragma unroll
-            for (int r = 0; r < 2; ++r) a[r] = tr_frag(sd, ks * 32 + 8 * kq, wco + r * 16, r16);
+            for (int r = 0; r < 2; ++r) a[r] = tr_frag_s<kWwDS>(sd, ks * 32 + 8 * kq, wco + r * 16, r16);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) b[c] = tr_frag(sx, ks * 32 + 8 * kq, wn + c * 16, r16);
+            for (int c = 0; c < 9; ++c) {
+                const bf16x8 bb = tr_frag_s<kWwXS>(sx, ks * 32 + 8 * kq, wn + c * 16, r16);
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], b[c], acc[r][c], 0, 0, 0);
+                for (int r = 0; r < 2; ++r)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb, acc[r][c], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
-    // D: rows = co (4 * kq + i), column = n (r16)
+    // D: rows = co (4 kq + i), column = n (r16)
 #pragma unroll
     for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+        for (int c = 0; c < 9; ++c) {
             const int n = n_t + wn + c * 16 + r16;
-            if (n >= N) continue;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int co = co_t + wco + r * 16 + 4 * kq + i;
-                if (co >= Cout) continue;
-                partial[(int64_t(split) * Cout + co) * N + n] = acc[r][c][i];
+                if (co < Cout && n < N) partial[(int64_t(split) * Cout + co) * N + n] = acc[r][c][i];
             }
         }
     if (do_bias) {  // uniform per workgroup
-        // lanes with equal lane % 8 hold the same 8 channels: butterfly over
-        // the other lane bits, then the four wavefronts in order
+        // lane l summed pixel l of every stage: butterfly over the 64 lanes
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 16; ++e) {
             float v = bsum[e];
 #pragma unroll
-            for (int o = 8; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
             bsum[e] = v;
         }
-        if (lane < 8) {
+        if (lane == 0) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) sb[wv][lane * 8 + e] = bsum[e];
-        }
-        __syncthreads();
-        if (threadIdx.x < 64 && co_t + int(threadIdx.x) < Cout) {
-            const float t = ((sb[0][threadIdx.x] + sb[1][threadIdx.x]) + sb[2][threadIdx.x]) + sb[3][threadIdx.x];
-            bias_partial[int64_t(split) * Cout + co_t + threadIdx.x] = t;
+            for (int e = 0; e < 16; ++e) {
+                const int co = co_t + 16 * wv + e;
+                if (co < Cout) bias_partial[int64_t(split) * Cout + co] = bsum[e];
+            }
         }
     }
 }
@@ -1022,6 +1025,14 @@ constexpr int64_t kSplitPix = 8192;  // pixels per weight-gradient split
 
 int64_t splits_for(int64_t npix) { return (npix + kSplitPix - 1) / kSplitPix; }
 
+// Weight-gradient splits of the layers with >= 32 input channels: about
+// 512 workgroups over the (64 x 288) tiles, a multiple of 64 pixels each.
+int64_t wgrad_pix_per_split(int64_t npix, int64_t cout, int64_t cin) {
+    const int64_t tiles = ((cout + 63) / 64) * (9 * cin / kWwN);
+    const int64_t sp = std::max<int64_t>(1, (512 + tiles - 1) / tiles);
+    return std::max<int64_t>(64, ((npix + sp - 1) / sp + 63) / 64 * 64);
+}
+
 size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
     const int64_t B = c->cfg.batch;
     const int64_t P = c->nparam;
@@ -1112,6 +1123,11 @@ int lsm_cnn_create(const lsm_cnn_config *cfg, lsm_cnn **out) {
         const int64_t npix = int64_t(k.batch) * c->Hs[l] * c->Hs[l];
         const int64_t sp = splits_for(npix);
         pn = std::max(pn, size_t(sp * (c->w_n[l] + c->C[l + 1] * 10)));
+        if (l > 0) {
+            const int64_t pps = wgrad_pix_per_split(npix, c->C[l + 1], c->C[l]);
+            const int64_t sw = (npix + pps - 1) / pps;
+            pn = std::max(pn, size_t(sw * (c->w_n[l] + c->C[l + 1])));
+        }
     }
     // slack for the first layer's summed [co][10] block after its partials
     c->part_n = pn + size_t(c->C[1]) * 10 + 64;
@@ -1322,15 +1338,17 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
         const int64_t nw = c->w_n[l], cout = c->C[l + 1], cin = c->C[l];
         if (l > 0) {
             // weight gradient: MFMA over pixel splits, then a fixed-order sum
-            const dim3 grid(unsigned((cout + 63) / 64), unsigned((9 * cin + 63) / 64), unsigned(sp));
-            float *bias_part = c->part + sp * nw;  // [split][co] after the weight partials
-            hipLaunchKernelGGL(k_conv_wgrad_mfma, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l], c->part,
-                               bias_part, B, H, H, int(cin), int(cout), int64_t(kSplitPix));
+            const int64_t pps = wgrad_pix_per_split(npix, cout, cin);
+            const int64_t sw = (npix + pps - 1) / pps;
+            const dim3 grid(unsigned((cout + 63) / 64), unsigned(9 * cin / kWwN), unsigned(sw));
+            float *bias_part = c->part + sw * nw;  // [split][co] after the weight partials
+            hipLaunchKernelGGL(k_conv_wgrad_wide, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l], c->part,
+                               bias_part, B, H, H, int(cin), int(cout), int(pps));
             CHIP(c, hipGetLastError());
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
-                               int(sp));
+                               int(sw));
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout)), dim3(kBlk), 0, c->stream, bias_part,
-                               c->g + c->b_off[l], cout, int(sp));
+                               c->g + c->b_off[l], cout, int(sw));
             CHIP(c, hipGetLastError());
             // input gradient: implicit GEMM with the flipped weights; its
             // epilogue applies the pooling and ReLU of the layer below (the
