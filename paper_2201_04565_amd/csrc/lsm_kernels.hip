@@ -315,6 +315,20 @@ __device__ inline void tile_coords(const StepParams &P, int &i, int &j, int &k, 
     ok = ok && i < P.nx && j < P.ny;
 }
 
+// Slot of this lane's event in the break log: one atomic per wavefront for
+// the lanes logging at this point (their ballot), slots in lane order
+// within it.  The log's order across wavefronts depends on scheduling; the
+// host sorts it on read.
+__device__ inline uint32_t event_slot(Ctl *ctl) {
+    const uint64_t act = __ballot(1);
+    const int lane = int(__lane_id());
+    const int leader = __ffsll(static_cast<unsigned long long>(act)) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&ctl->n_events, uint32_t(__popcll(act)));
+    base = uint32_t(__shfl(int(base), leader, 64));
+    return base + uint32_t(__popcll(act & ((uint64_t(1) << lane) - 1u)));
+}
+
 // Acceleration (F - gamma v) / m of a free particle (v: the half-step velocity).
 template <int DIM, int PREC>
 __device__ inline void site_acc(const typename State<DIM, PREC>::R *F, const typename State<DIM, PREC>::R *w,
@@ -743,7 +757,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
             if (commit) {
                 newmask |= Mask(1) << d;
                 if (fwd) {
-                    const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                    const uint32_t idx = event_slot(P.ctl);
                     if (idx < P.ev_cap) {
                         lsm_event ev;
                         ev.increment = P.ctl->inc;
@@ -1008,7 +1022,7 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
         const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + pb;
         SpringEval<3, PREC> o;
         spring_eval<3, PREC>(P, tt[ti], ti, d, uph, upl, qh, ql, o);
-        const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+        const uint32_t idx = event_slot(P.ctl);
         if (idx < P.ev_cap) {
             lsm_event ev;
             ev.increment = P.ctl->inc;
@@ -1200,7 +1214,7 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
                 const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
                 SpringEval<3, PREC> o;
                 spring_eval<3, PREC>(P, alat, G::geom(d) ? T1 : T0, ti, d, uph, upl, qh, ql, o);
-                const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                const uint32_t idx = event_slot(P.ctl);
                 if (idx < P.ev_cap) {
                     lsm_event ev;
                     ev.increment = P.ctl->inc;
@@ -1997,7 +2011,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
                             if (brks[d]) {
-                                const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+                                const uint32_t idx = event_slot(P.ctl);
                                 if (idx < P.ev_cap) {
                                     lsm_event ev;
                                     ev.increment = P.ctl->inc;
@@ -2090,7 +2104,7 @@ __device__ inline void log_breaks(const StepParams &P, int g, const RowSprings<t
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         if (brks[d]) {
-            const uint32_t idx = atomicAdd(&P.ctl->n_events, 1u);
+            const uint32_t idx = event_slot(P.ctl);
             if (idx < P.ev_cap) {
                 lsm_event ev;
                 ev.increment = P.ctl->inc;
