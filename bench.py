@@ -153,6 +153,97 @@ def lattice_run(lsm, torch, wl, img, precision, warmup, timed, spi, workload, lo
     return out
 
 
+def extensions(torch, inputs, lsm, log):
+    """The paper's protocol, local fields and the spring laws, each timed on
+    a full-size lattice: constant strain-rate loading of the C2 bricks
+    (grips moved before every step, one interior step per launch), the local
+    stress and strain fields of the C3 lattice, and the cubic spring law on
+    C3 (gather kernel).  HIP events on the library's stream."""
+    import ctypes as C
+
+    out = {}
+    # f1: grips at a constant strain rate, a record every 500 steps
+    w2 = inputs.WORKLOADS["c2"]
+    lat = lsm.Lattice.from_workload(w2, inputs.c2_image(), precision="fp32k", device="cuda:0")
+    lat.relax_trace(1e-6, 100, 100)  # graphs captured, grips running
+    lat.set_timing(True)
+    lat.read_timing()
+    t0 = time.perf_counter()
+    recs = lat.relax_trace(1e-6, 2000, 500)
+    wall = time.perf_counter() - t0
+    ms, steps = lat.read_timing()
+    lat.set_timing(False)
+    step_s = ms * 1e-3 / max(steps, 1)
+    B = survey_bytes(2, "fp32k", lat.n, lat.m)
+    own = lat.step_bytes() / lat.launch()["steps_per_launch"]
+    out["rate"] = dict(workload="c2 bricks 2048^2, fp32 compensated, strain rate 1e-6 per unit time, "
+                                "2000 steps, a record every 500",
+                       launch=lat.launch(), us_per_step=step_s * 1e6, spring_steps_per_s=lat.m / step_s,
+                       wall_s=wall, records=len(recs), strain_at_end=recs[-1]["eps"],
+                       roofline={"bound": "hbm", "achieved": B / step_s / 1e9, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": B / step_s / 1e9 / HBM_PEAK_GBS,
+                                 "bytes_per_step": B, "implicit_bytes_per_step": own,
+                                 "implicit_frac": own / step_s / 1e9 / HBM_PEAK_GBS})
+    log(f"rate: {out['rate']['us_per_step']:.1f} us per step")
+    del lat
+    torch.cuda.empty_cache()
+    # f2: local fields of the C3 lattice after one increment
+    w3 = inputs.WORKLOADS["c3"]
+    img3 = inputs.c3_image()
+    lat = lsm.Lattice.from_workload(w3, img3, precision="fp64", device="cuda:0")
+    lat.apply_increment(w3["d_eps"])
+    lat.relax(200)
+    lat.read_state()
+    n = lat.n
+    stress = torch.empty(n * 9, dtype=torch.float64, device="cuda:0")
+    strain = torch.empty(n * 9, dtype=torch.float64, device="cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fields = {}
+    for radius in (0, 1):
+        for rep_ in range(2):  # the second pass is timed
+            e0.record(lat.stream)
+            for _ in range(5):
+                lat._check(lat._L.lsm_local_fields(lat._h, radius, C.c_void_p(stress.data_ptr()),
+                                                   C.c_void_p(strain.data_ptr())))
+            e1.record(lat.stream)
+            e1.synchronize()
+        t = e0.elapsed_time(e1) / 5 * 1e-3
+        # state read once (u, v 24 B each, mask 4, flag 1, site index 4), the
+        # per-particle virial written and read once (72 B each), stress and
+        # strain written once (72 B each)
+        fb = n * (24 + 24 + 4 + 1 + 4 + 72 + 72 + 72 + 72)
+        fields[f"radius{radius}"] = dict(ms_per_call=t * 1e3, particles_per_s=n / t,
+                                         roofline={"bound": "hbm", "achieved": fb / t / 1e9, "peak": HBM_PEAK_GBS,
+                                                   "unit": "GB/s", "frac": fb / t / 1e9 / HBM_PEAK_GBS,
+                                                   "bytes_per_call": fb})
+    out["fields"] = dict(workload="c3 random-field voxels 256^3, fp64, local virial stress over the radius-0 / "
+                                  "radius-1 domain and Lagrangian strain of every particle", particles=n, **fields)
+    log(f"fields: {fields['radius1']['ms_per_call']:.2f} ms per call (radius 1)")
+    del lat, stress, strain
+    torch.cuda.empty_cache()
+    # f3: the cubic spring law (the gather kernel)
+    lat = lsm.Lattice.from_workload(w3, img3, precision="fp64", device="cuda:0", spring_law="cubic", law_c=1.0)
+    lat.apply_increment(w3["d_eps"])
+    lat.relax(200)
+    lat.read_state()
+    lat.set_timing(True)
+    lat.read_timing()
+    lat.relax(1000)
+    ms, steps = lat.read_timing()
+    lat.set_timing(False)
+    step_s = ms * 1e-3 / max(steps, 1)
+    B = survey_bytes(3, "fp64", lat.n, lat.m)
+    out["cubic_law"] = dict(workload="c3 random-field voxels 256^3, fp64, cubic spring law (c = 1), 1000 steps",
+                            launch=lat.launch(), us_per_step=step_s * 1e6, spring_steps_per_s=lat.m / step_s,
+                            roofline={"bound": "hbm", "achieved": B / step_s / 1e9, "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": B / step_s / 1e9 / HBM_PEAK_GBS,
+                                      "bytes_per_step": B})
+    log(f"cubic law: {out['cubic_law']['us_per_step']:.1f} us per step")
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, img, steps: int):
     """The FP64 oracle, single thread, on part of one increment of the same
     lattice (per-step cost does not change along the run)."""
@@ -452,6 +543,8 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--cnn-bench", action="store_true", help="also time the surrogate network kernels")
     ap.add_argument("--no-c1", action="store_true", help="skip the small-lattice (C1) section")
+    ap.add_argument("--no-ext", action="store_true",
+                    help="skip the strain-rate, local-field and spring-law section")
     ap.add_argument("--sur-train", type=int, default=4096,
                     help="training specimens (the full C5 configuration: 50000)")
     ap.add_argument("--sur-val", type=int, default=1024, help="validation specimens (C5: 5000)")
@@ -466,7 +559,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     if args.only_headline:
-        args.no_c3_fp32k = args.no_c2 = args.no_batch = args.no_c1 = args.no_surrogate = True
+        args.no_c3_fp32k = args.no_c2 = args.no_batch = args.no_c1 = args.no_surrogate = args.no_ext = True
     pool = None
     if not args.no_batch and not args.no_cpu:
         # the all-core oracle workers start now, before anything touches the
@@ -539,6 +632,9 @@ def main():
     if not args.no_c1:
         log("c1 small lattice")
         out["c1"] = small_c1(args, inputs, lsm)
+    if not args.no_ext:
+        log("strain-rate loading, local fields, cubic spring law")
+        out["extensions"] = extensions(torch, inputs, lsm, log)
     if args.cnn_bench:
         log("surrogate network kernels")
         out["cnn"] = cnn_kernels(torch)
