@@ -49,8 +49,8 @@ COUNTERS = {"c3": os.path.join(ROOT, "profiles", "c3_step_counters.json"),
 # FP32-compensated (u_hi, u_lo, v) 24, FP64 32; 3D 36 / 48
 STATE_BYTES = {(2, "fp32k"): 24, (2, "fp64"): 32, (3, "fp32k"): 36, (3, "fp64"): 48}
 KERNEL_NAMES = {
-    ("c3", "fp64"): "k_step_c3w<0, 2816> (3D compact layout, neighbours staged in LDS windows, fp64)",
-    ("c3", "fp32k"): "k_step_c3w<1, 2816> (3D compact layout, neighbours staged in LDS windows, fp32 forces, compensated fp32 displacements)",
+    ("c3", "fp64"): "k_step_c3w<0, 2816, 0> (3D compact layout, neighbours staged in LDS windows, fp64)",
+    ("c3", "fp32k"): "k_step_c3w<1, 2816, 0> (3D compact layout, neighbours staged in LDS windows, fp32 forces, compensated fp32 displacements)",
     ("c2", "fp32k"): "k_sweep2d_x2<1,1> (2D row sweep, two interior steps per launch, fp32 compensated)",
     ("c2", "fp64"): "k_sweep2d<0,1,1,0> (2D row sweep, fp64)",
 }

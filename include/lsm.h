@@ -125,9 +125,11 @@ typedef struct {
  *   LSM_SPRING_CUBIC: U = k d^2 / 2 + k c d^4 / (4 r0^2), d = r - r0, force
  *     magnitude k d (1 + c d^2 / r0^2) (c > 0 stiffening, c < 0 softening).
  * The break rule is the same for all.  Lattices with a law other than
- * LSM_SPRING_LINEAR run the gather kernel (LSM_KERNEL_AUTO resolves to it;
- * asking for another kernel is LSM_EINVAL); batches take the linear law
- * only.                                                                   */
+ * LSM_SPRING_LINEAR run the gather kernel, except for the interior steps
+ * of single-phase 3D lattices with LDS windows, which run the LSM_KERNEL_COMPACT
+ * form (LSM_KERNEL_AUTO resolves to that where it applies; asking for a
+ * kernel other than LSM_KERNEL_AUTO, LSM_KERNEL_GATHER or
+ * LSM_KERNEL_COMPACT is LSM_EINVAL); batches take the linear law only.    */
 #define LSM_SPRING_LINEAR 0
 #define LSM_SPRING_RECOVER 1
 #define LSM_SPRING_CUBIC 2

@@ -297,10 +297,12 @@ bool use_small(const lsm_handle *h) {
 }
 // 3D interior steps in the compact layout: the default for 3D lattices
 // (not under constant-rate loading, whose grip kernel moves site-grid state)
+// (spring laws other than the linear one: the LDS-window form only)
 bool use_compact(const lsm_handle *h) {
-    return h->dim == 3 && !h->crow.empty() && h->rate == 0.0 && linear_law(h) &&
-           (h->variant == LSM_KERNEL_AUTO || h->variant == LSM_KERNEL_COMPACT ||
-            h->variant == LSM_KERNEL_COMPACT_DIRECT);
+    if (h->dim != 3 || h->crow.empty() || h->rate != 0.0) return false;
+    if (h->variant != LSM_KERNEL_AUTO && h->variant != LSM_KERNEL_COMPACT && h->variant != LSM_KERNEL_COMPACT_DIRECT)
+        return false;
+    return linear_law(h) || (!h->cwin.empty() && h->variant != LSM_KERNEL_COMPACT_DIRECT);
 }
 // ... with the neighbours staged in LDS windows (where the lattice has them)
 bool use_window(const lsm_handle *h) {
@@ -1467,8 +1469,9 @@ int lsm_set_launch(lsm_handle *h, int variant, int rows_per_wave) {
     const bool compact = variant == LSM_KERNEL_COMPACT || variant == LSM_KERNEL_COMPACT_DIRECT;
     if (compact && h->dim != 3)
         return fail(h, LSM_EINVAL, "the compact layout is 3D only");
-    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && !linear_law(h))
-        return fail(h, LSM_EINVAL, "spring laws other than the linear one run the gather kernel only");
+    if (variant != LSM_KERNEL_AUTO && variant != LSM_KERNEL_GATHER && variant != LSM_KERNEL_COMPACT && !linear_law(h))
+        return fail(h, LSM_EINVAL,
+                    "spring laws other than the linear one run the gather kernel or the LDS-window compact one only");
     if (compact && h->built && h->crow.empty())
         return fail(h, LSM_EINVAL, "lattice too large for the compact layout");
     if (variant == LSM_KERNEL_SMALL && h->dim != 2) return fail(h, LSM_EINVAL, "the one-workgroup kernel is 2D only");

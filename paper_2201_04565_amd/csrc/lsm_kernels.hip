@@ -669,12 +669,17 @@ __device__ __attribute__((always_inline)) inline void spring_force_add(const typ
     }
 }
 
-// The 3D FP64 linear force of spring_force_add with -(k r0) precomputed
-// (nkr0 = -(T.x * T.y), the same product): the same result.
+// The 3D FP64 force of spring_force_add with -(k r0) precomputed (nkr0 =
+// -(T.x * T.y), the same product): the same result.
 __device__ __attribute__((always_inline)) inline void spring_force_add_f64(const D4 &T, double nkr0,
-                                                                          const SpringEval<3, 0> &o, double *F) {
+                                                                          const SpringEval<3, 0> &o, double *F,
+                                                                          double cubic) {
     const double rinv = rsqrt_pos(o.r2);
-    const double coef = fma(nkr0, rinv, T.x);
+    double coef = fma(nkr0, rinv, T.x);
+    if (cubic != 0.0) {
+        const double dr = (double(o.r2) * rinv - T.y) / T.y;
+        coef *= fma(cubic * dr, dr, 1.0);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) F[c] += coef * o.dv[c];
 }
@@ -1050,12 +1055,14 @@ __global__ __launch_bounds__(kBlock) void k_step_c3(StepParams P, int step_local
 // that site is solid -- gives the neighbours in the row (x - 1: entry - 1,
 // x: entry, x + 1: entry + solid bit); the own row's neighbours are p - 1
 // and p + 1.  A workgroup whose windows exceed the pool reads every
-// neighbour from global memory.  Arithmetic and summation order
-// are those of the gather kernel, so state, break bits and events are
-// bitwise the same.
-template <int PREC, int POOL>
+// neighbour from global memory.  LAW is the spring law (LSM_SPRING_*: a
+// broken spring acts again in compression under the recoverable law, the
+// cubic law scales the force).  Arithmetic and summation order are those
+// of the gather kernel, so state, break bits and events are bitwise the
+// same.
+template <int PREC, int POOL, int LAW>
 __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_step_c3w(StepParams P,
-                                                                                         int step_local) {
+                                                                                             int step_local) {
     constexpr int GRP = PREC ? 3 : 6;  // FP32-compensated: fewer registers, four waves per SIMD
     using CS = CState<PREC>;
     using R = typename CS::R;
@@ -1089,6 +1096,9 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
     const uint32_t mask = reinterpret_cast<const uint32_t *>(P.mask)[pp];
     const uint8_t fp = P.flags[pp];
     const uint4 er = reinterpret_cast<const uint4 *>(P.crel)[pp];
+    // absent springs (void or off-grid neighbour): the recoverable law tells
+    // them from broken ones
+    const uint32_t absent = LAW == LSM_SPRING_RECOVER ? P.cabs[pp] : 0u;
     // window copy: the loads of every round the windows need (index clamped
     // to the last record), then the stores.  (Batches of three or four
     // rounds measured 1-3 % slower; loads straight into LDS, 249 against
@@ -1128,6 +1138,7 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
     const TTy T0 = TT<PREC>::make(P.types[0]), T1 = TT<PREC>::make(P.types[LSM_MAX_PHASES * LSM_MAX_PHASES]);
     const double nk0 = -(double(T0.x) * double(T0.y)), nk1 = -(double(T1.x) * double(T1.y));  // FP64 only
     const double alat = P.a;
+    const double cubic = LAW == LSM_SPRING_CUBIC ? P.law_c : 0.0;
     const double mass = P.mass[0];
     const R imass = R(1.0 / mass);
     auto lds = [&](uint32_t x, R *qh, R *ql) {
@@ -1182,18 +1193,26 @@ __global__ __launch_bounds__(kC3WinBlock) __attribute__((amdgpu_waves_per_eu(4))
 #pragma unroll
             for (int t = 0; t < GRP; ++t) {
                 const int d = gi * GRP + t;
-                if (mask & (1u << d)) continue;
+                // a broken spring acts only under the recoverable law, in compression
+                if (((LAW == LSM_SPRING_RECOVER ? absent : mask) >> d) & 1u) continue;
                 const int ti = G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES);
                 const TTy T = G::geom(d) ? T1 : T0;
                 SpringEval<3, PREC> o;
                 spring_eval<3, PREC>(P, alat, T, ti, d, uph, upl, uqh[t], uql[t], o);
+                if constexpr (LAW == LSM_SPRING_RECOVER) {
+                    if ((mask >> d) & 1u) {
+                        const double r0 = P.types[ti].r0_64;
+                        if (!(double(o.r2) < r0 * r0)) continue;
+                        o.brk = false;
+                    }
+                }
                 if (o.brk) {
                     newmask |= 1u << d;
                     if (d < G::NF) fbrk |= 1u << d;
                     continue;
                 }
-                if constexpr (PREC == 0) spring_force_add_f64(T, G::geom(d) ? nk1 : nk0, o, F);
-                else spring_force_add<3, PREC>(T, o, F);
+                if constexpr (PREC == 0) spring_force_add_f64(T, G::geom(d) ? nk1 : nk0, o, F, cubic);
+                else spring_force_add<3, PREC>(T, o, F, cubic);
             }
         }
         // events of forward springs that break (before the update, which
@@ -2490,12 +2509,22 @@ hipError_t launch_step(const StepParams &p, int dim, int prec, int mode, hipStre
     return prec ? launch_step_t<3, 1>(p, mode, s, step_local) : launch_step_t<3, 0>(p, mode, s, step_local);
 }
 
+template <int PREC, int POOL>
+void launch_c3w(const StepParams &p, hipStream_t s, int step_local) {
+    const dim3 grid(p.c_wblocks), block(kC3WinBlock);
+    if (p.law == LSM_SPRING_RECOVER)
+        hipLaunchKernelGGL((k_step_c3w<PREC, POOL, LSM_SPRING_RECOVER>), grid, block, 0, s, p, step_local);
+    else if (p.law == LSM_SPRING_CUBIC)
+        hipLaunchKernelGGL((k_step_c3w<PREC, POOL, LSM_SPRING_CUBIC>), grid, block, 0, s, p, step_local);
+    else
+        hipLaunchKernelGGL((k_step_c3w<PREC, POOL, LSM_SPRING_LINEAR>), grid, block, 0, s, p, step_local);
+}
+
 hipError_t launch_step_c3(const StepParams &p, int prec, hipStream_t s, int step_local, int kind) {
     const dim3 grid(p.c_blocks), block(kBlock);
     if (kind == 2) {
-        const dim3 wgrid(p.c_wblocks), wblock(kC3WinBlock);
-        if (prec) hipLaunchKernelGGL((k_step_c3w<1, kC3PoolF32>), wgrid, wblock, 0, s, p, step_local);
-        else hipLaunchKernelGGL((k_step_c3w<0, kC3PoolF64>), wgrid, wblock, 0, s, p, step_local);
+        if (prec) launch_c3w<1, kC3PoolF32>(p, s, step_local);
+        else launch_c3w<0, kC3PoolF64>(p, s, step_local);
     } else if (kind == 1) {
         if (prec) hipLaunchKernelGGL((k_step_c3<1, true>), grid, block, 0, s, p, step_local);
         else hipLaunchKernelGGL((k_step_c3<0, true>), grid, block, 0, s, p, step_local);

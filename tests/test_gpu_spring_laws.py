@@ -49,7 +49,9 @@ def run(lsm, img, wl, precision, law, c, steps):
                                 gamma=wl["gamma"], void_value=wl.get("void_value", -1)))
     o.set_spring_law(LAW_ID[law], c)
     g = lsm.Lattice.from_workload(wl, img, precision=precision, spring_law=law, law_c=c)
-    assert g.launch()["variant"] == "gather" or law == "linear"
+    # 2D lattices run the gather kernel under a non-linear law, single-phase
+    # 3D ones the LDS-window compact kernel
+    assert law == "linear" or g.launch()["variant"] == ("compact" if img.ndim == 3 else "gather")
     ro, rg = [], []
     for d_eps in PROTOCOLS[law]:
         for x in (o, g):
@@ -89,3 +91,31 @@ def test_spring_law_matches_oracle(lsm, name, make, wlname, steps, law, c, preci
         last = ro[-1]["sigma"][0, 0], ro_lin[-1]["sigma"][0, 0]
         say(f"  final sigma_xx: recoverable {last[0]:.6g}, linear {last[1]:.6g}")
         assert last[0] < last[1] and abs(last[0] - last[1]) > 1e-3 * abs(last[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+@pytest.mark.parametrize("law,c", [("cubic", 5.0), ("recover", 0.0)])
+def test_spring_law_compact_is_bitwise_the_gather_kernel(lsm, law, c, precision):
+    # the interior steps of the LDS-window compact kernel under each law
+    # against the gather kernel: a random field and a solid block whose
+    # windows exceed the LDS pool (neighbours read from global memory), the
+    # law's protocol with fracture (and, for the recoverable law, closing
+    # cracks); state, break bits and events equal
+    wl = inputs.WORKLOADS["c3"]
+    cases = [("grf 18^3", inputs.gaussian_random_field_3d(18, corr_len=3.0, seed=4), 250),
+             ("solid 330x4x4", np.zeros((4, 4, 330), np.uint8), 150)]
+    for name, img, steps in cases:
+        say(f"{law} law compact vs gather {name} {precision}")
+        out = []
+        for variant in ("gather", "compact"):
+            g = lsm.Lattice.from_workload(wl, img, precision=precision, spring_law=law, law_c=c)
+            g.set_launch(variant)
+            assert g.launch()["variant"] == variant
+            for d_eps in PROTOCOLS[law]:
+                g.apply_increment(d_eps)
+                g.relax(steps)
+            out.append((g.save_state(), g.read_broken()))
+        assert len(out[0][1]) > 0, "the case should break springs"
+        say(f"  {len(out[0][1])} events")
+        assert np.array_equal(out[1][1], out[0][1])
+        assert out[1][0] == out[0][0]
