@@ -1267,6 +1267,11 @@ __global__ __launch_bounds__(256) void k_virial(StepParams P, const int32_t *sit
     using R = typename S::R;
     using G = Geo<DIM>;
     using Mask = typename G::Mask;
+    // (k, r0) of every spring type, staged in LDS: a type read per spring
+    // from global memory waits on its own load
+    __shared__ double2 tkr[kMaxTypes];
+    for (int t = threadIdx.x; t < kMaxTypes; t += 256) tkr[t] = make_double2(P.types[t].k64, P.types[t].r0_64);
+    __syncthreads();
     const int p = int(blockIdx.x) * 256 + int(threadIdx.x);
     if (p >= P.n_part) return;
     const int g = site_of[p];
@@ -1282,16 +1287,34 @@ __global__ __launch_bounds__(256) void k_virial(StepParams P, const int32_t *sit
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int b = 0; b < DIM; ++b) sv[a][b] = 0.0;
-    for (int d = 0; d < G::ND; ++d) {
+    // neighbours in groups of six: the flag and displacement loads of a
+    // group are issued unconditionally (from the site itself off the
+    // lattice) before any of them is used
+    constexpr int kGrp = 6;
+#pragma unroll
+    for (int d0 = 0; d0 < G::ND; d0 += kGrp) {
+    bool inb[kGrp];
+    uint8_t fqs[kGrp];
+    R uqhs[kGrp][DIM], uqls[kGrp][DIM];
+#pragma unroll
+    for (int t = 0; t < kGrp; ++t) {
+        const int d = d0 + t;
         const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
         const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-        if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
-        const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
-        const uint8_t fq = P.flags[q];
+        inb[t] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+        const int q = inb[t] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+        fqs[t] = P.flags[q];
+        S::load_u(P.u_in, q, P.nsites, uqhs[t], uqls[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < kGrp; ++t) {
+        const int d = d0 + t;
+        if (!inb[t]) continue;
+        const uint8_t fq = fqs[t];
         const bool was_broken = mask & (Mask(1) << d);
         if (fq == kVoid || (was_broken && P.law != LSM_SPRING_RECOVER)) continue;
-        R uqh[DIM], uql[DIM];
-        S::load_u(P.u_in, q, P.nsites, uqh, uql);
+        const R *uqh = uqhs[t];
+        const R *uql = uqls[t];
         double dd[DIM], r2 = 0.0;
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -1301,13 +1324,13 @@ __global__ __launch_bounds__(256) void k_virial(StepParams P, const int32_t *sit
             dd[c] = e + ((double(uqh[c]) - double(uph[c])) + (double(uql[c]) - double(upl[c])));
             r2 += dd[c] * dd[c];
         }
-        const TypeRec &T = P.types[G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES +
-                                   flag_phase(fq)];
+        const double2 T = tkr[G::geom(d) * (LSM_MAX_PHASES * LSM_MAX_PHASES) + pa * LSM_MAX_PHASES + flag_phase(fq)];
+        const double k64 = T.x, r0 = T.y;
         const double r = sqrt(r2);
-        if (was_broken && !(r < T.r0_64)) continue;  // recoverable law: compression only
-        double coef = T.k64 * (r - T.r0_64) / r;
+        if (was_broken && !(r < r0)) continue;  // recoverable law: compression only
+        double coef = k64 * (r - r0) / r;
         if (P.law == LSM_SPRING_CUBIC) {
-            const double dr = (r - T.r0_64) / T.r0_64;
+            const double dr = (r - r0) / r0;
             coef *= 1.0 + P.law_c * dr * dr;
         }
         const double half_coef = 0.5 * coef;
@@ -1315,6 +1338,7 @@ __global__ __launch_bounds__(256) void k_virial(StepParams P, const int32_t *sit
         for (int a = 0; a < DIM; ++a)
 #pragma unroll
             for (int b = 0; b < DIM; ++b) sv[a][b] += dd[a] * (half_coef * dd[b]);
+    }
     }
     const double m = P.mass[pa];
 #pragma unroll
@@ -1338,15 +1362,35 @@ __global__ __launch_bounds__(256) void k_virial_domain(StepParams P, const int32
     if (radius > 0) {
         const int g = site_of[p];
         const int i = g % P.nx, j = (g / P.nx) % P.ny, k = g / (P.nx * P.ny);
+        // every neighbour's particle index first (-1: void or off the
+        // lattice), then their contributions in groups of three, loaded
+        // unconditionally (p's own for a missing neighbour) before use
+        int qs[G::ND];
+#pragma unroll
         for (int d = 0; d < G::ND; ++d) {
             const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
             const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-            if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
-            const int q = part_of[g + ddi + P.nx * (ddj + P.ny * ddk)];
-            if (q < 0) continue;
+            const bool inb = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+            const int q = part_of[inb ? g + ddi + P.nx * (ddj + P.ny * ddk) : g];
+            qs[d] = inb ? q : -1;
+        }
+        constexpr int kGrp = 3;
 #pragma unroll
-            for (int e = 0; e < DIM * DIM; ++e) acc[e] += s[int64_t(q) * DIM * DIM + e];
-            ++count;
+        for (int d0 = 0; d0 < G::ND; d0 += kGrp) {
+            double sq[kGrp][DIM * DIM];
+#pragma unroll
+            for (int t = 0; t < kGrp; ++t) {
+                const int64_t q = qs[d0 + t] >= 0 ? qs[d0 + t] : p;
+#pragma unroll
+                for (int e = 0; e < DIM * DIM; ++e) sq[t][e] = s[q * DIM * DIM + e];
+            }
+#pragma unroll
+            for (int t = 0; t < kGrp; ++t) {
+                if (qs[d0 + t] < 0) continue;
+#pragma unroll
+                for (int e = 0; e < DIM * DIM; ++e) acc[e] += sq[t][e];
+                ++count;
+            }
         }
     }
     const double inv = 1.0 / (double(count) * vsite);
@@ -1374,15 +1418,27 @@ __global__ __launch_bounds__(256) void k_strain(StepParams P, const int32_t *sit
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
         for (int b = 0; b < DIM; ++b) A[a][b] = B[a][b] = 0.0;
+    // the first nearest neighbours' flags and displacements, loaded
+    // unconditionally (the site's own off the lattice) before use
+    bool inb[G::ND];
+    uint8_t fqs[G::ND];
+    R uqhs[G::ND][DIM], uqls[G::ND][DIM];
+#pragma unroll
     for (int d = 0; d < G::ND; ++d) {
-        if (G::geom(d) != 0) continue;  // first nearest neighbours only
+        if (G::geom(d) != 0) continue;
         const int ddi = G::di(d, j & 1), ddj = G::dj(d), ddk = G::dk(d);
         const int qi = i + ddi, qj = j + ddj, qk = k + ddk;
-        if (qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz) continue;
-        const int q = g + ddi + P.nx * (ddj + P.ny * ddk);
-        if (P.flags[q] == kVoid) continue;
-        R uqh[DIM], uql[DIM];
-        S::load_u(P.u_in, q, P.nsites, uqh, uql);
+        inb[d] = !(qi < 0 || qi >= P.nx || qj < 0 || qj >= P.ny || qk < 0 || qk >= P.nz);
+        const int q = inb[d] ? g + ddi + P.nx * (ddj + P.ny * ddk) : g;
+        fqs[d] = P.flags[q];
+        S::load_u(P.u_in, q, P.nsites, uqhs[d], uqls[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < G::ND; ++d) {
+        if (G::geom(d) != 0) continue;  // first nearest neighbours only
+        if (!inb[d] || fqs[d] == kVoid) continue;
+        const R *uqh = uqhs[d];
+        const R *uql = uqls[d];
         double d0[DIM], dd[DIM];
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
@@ -1429,6 +1485,7 @@ __global__ __launch_bounds__(256) void k_strain(StepParams P, const int32_t *sit
         return;
     }
     double J[DIM][DIM];
+    const double inv_det = 1.0 / det;  // one division instead of nine
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
 #pragma unroll
@@ -1436,7 +1493,7 @@ __global__ __launch_bounds__(256) void k_strain(StepParams P, const int32_t *sit
             double t = 0.0;
 #pragma unroll
             for (int c = 0; c < DIM; ++c) t += B[a][c] * Ai[c][b];
-            J[a][b] = t / det;
+            J[a][b] = t * inv_det;
         }
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
