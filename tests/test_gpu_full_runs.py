@@ -5,6 +5,8 @@
   oracle's run of the same increment stored in tests/golden (records every
   500 steps and 4096 sampled particle positions; written by
   tests/golden/make_c3_golden.py, which calls only the oracle).
+* The same lattice, three fracturing increments in the bench's launch
+  (LDS-window compact kernel) against the gather kernel, bitwise.
 * The 2048^2 brick-and-mortar lattice, the whole 200-increment protocol in
   FP32-compensated against the GPU's FP64 run (the oracle takes about an
   hour per increment at this size): broken-spring sequence identical before
@@ -74,6 +76,31 @@ def test_c3_one_increment_against_oracle(lsm, precision, rtol, xtol):
     dx = np.max(np.abs(x - gold["sample_x"]))
     say(f"  {len(gold['sample_ids'])} sampled positions: largest difference {dx:.2e}")
     assert dx <= xtol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32k"])
+def test_c3_window_kernel_is_bitwise_the_gather_kernel_at_full_size(lsm, precision):
+    # the bench's launch (LDS-window compact kernel, 512-particle
+    # workgroups) against the gather kernel on the whole 256^3 lattice:
+    # three increments of 0.4 % (fracture from the second on), state, break
+    # bits and events equal
+    wl = inputs.WORKLOADS["c3"]
+    img = inputs.c3_image()
+    out = []
+    for variant in ("gather", "compact"):
+        g = lsm.Lattice.from_workload(wl, img, precision=precision)
+        g.set_launch(variant)
+        assert g.launch()["variant"] == variant
+        say(f"c3 256^3 {precision} {variant}: 3 x 0.4 % x 2000 steps")
+        for _ in range(3):
+            g.apply_increment(0.004)
+            g.relax(2000)
+        out.append((g.save_state(), g.read_broken(), g.read_state()["n_broken"]))
+        del g
+    say(f"  {out[0][2]} springs broken")
+    assert out[0][2] > 0, "the run should break springs"
+    assert np.array_equal(out[1][1], out[0][1])
+    assert out[1][0] == out[0][0]
 
 
 def test_c2_full_run_fp32k_against_fp64(lsm):
