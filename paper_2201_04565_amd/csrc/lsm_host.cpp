@@ -419,7 +419,10 @@ hipError_t launch_mid_steps(const lsm_handle *h, int chunk, int local, int c) {
         p.mask = mc;
         p.v_out = va;
         p.mask_out = ma;
-        if (h->rate != 0.0) {
+        // constant-rate loading: the one-step sweep places the grips itself,
+        // the other kernels after the grip kernel
+        p.grip_rate = h->rate != 0.0 && use_sweep(h) ? 1 : 0;
+        if (h->rate != 0.0 && !p.grip_rate) {
             le = lsm::launch_grips(p, h->dim, h->prec, h->stream, local + s);
             if (le != hipSuccess) break;
         }

@@ -130,6 +130,9 @@ struct StepParams {
     // kernel (and the local fields) take a law other than the linear one
     int32_t law;
     double law_c;
+    // constant-rate loading in the one-step 2D sweep's interior steps: the
+    // sweep places the grips of the rows it loads itself (no grip kernel)
+    int32_t grip_rate;
 };
 
 // Launchers (lsm_kernels.hip).  All are asynchronous on `stream`.

@@ -1765,7 +1765,7 @@ struct SweepRow {
 
 template <int PREC>
 __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok, int jj,
-                                      SweepRow<typename State<2, PREC>::R> &r) {
+                                      SweepRow<typename State<2, PREC>::R> &r, double geps = 0.0) {
     // Loads are unconditional from always-valid addresses, so no branch
     // joins on a pending load and no select waits for one.  Off the
     // specimen a lane reads its flag and break bits from the sentinel site
@@ -1788,6 +1788,15 @@ __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, 
     }
     r.f = (P.flags + it.base)[gf];
     r.m = (reinterpret_cast<const uint8_t *>(P.mask) + it.base)[gf];
+    if (P.grip_rate && r.f != kVoid && flag_grip(r.f) != 0) {
+        // constant-rate loading: the grip's displacement at strain geps, the
+        // value the grip kernel would have stored (the step carries it over)
+        const double ux = geps * (double(i) * P.a) + 0.0;
+        r.uh[0] = R(ux);
+        r.ul[0] = R(ux - double(r.uh[0]));
+        r.uh[1] = R(0);
+        r.ul[1] = R(0);
+    }
     // the velocity too, also on the halo row below the chunk that is never
     // advanced: one more load there costs less than the branch around it
     const char *vb = static_cast<const char *>(P.v) + size_t(it.base) * (2 * sizeof(R)) + g * uint32_t(2 * sizeof(R));
@@ -2049,6 +2058,12 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const int jstart = j0 > 0 ? j0 - 1 : 0;
         const int js = jstart & ~1;  // even: the parity of each unrolled row is a constant
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
+        // strain of this step under constant-rate loading (the grip kernel's formula)
+        double geps = 0.0;
+        if (P.grip_rate) {
+            const int steps = P.ctl->step_base + step_local - P.ctl->rate_s0;
+            geps = __dadd_rn(P.ctl->rate_eps0, __dmul_rn(double(steps), P.ctl->rate_de));
+        }
 
         R pUL[2] = {R(0), R(0)}, pUR[2] = {R(0), R(0)};
         int pbrk = 0;
@@ -2058,7 +2073,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         auto row_step = [&](auto parc, int j, SweepRow<R> &rc, SweepRow<R> &ru,
                             SweepRow<R> &rn) __attribute__((always_inline)) {
             constexpr int PAR = decltype(parc)::value;
-            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn);
+            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn, geps);
             RowSprings<R> o;
             row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a, not_last, not_first);
             const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
@@ -2142,7 +2157,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
         for (int t = 0; t <= PF; ++t) {
             const int jj = js + t;
-            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, B[t]);
+            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, B[t], geps);
         }
         for (int j = js; j < j1; j += K) {
             unroll_rows<0, K>([&](auto tc) __attribute__((always_inline)) {

@@ -66,3 +66,38 @@ def test_notched_composite_constant_rate(lsm, mode1, precision, kernel):
     assert n >= 3
     if precision == "fp64":
         assert k >= 4
+
+
+def test_rate_sweep_agrees_with_the_gather_kernel(lsm):
+    # the one-step sweep places the grips itself under constant-rate
+    # loading, the gather kernel runs after the grip kernel; FP64 (the two
+    # kernels sum a site's springs in different orders, so they agree to
+    # rounding, not bit for bit): the notched composite and a ragged brick
+    # crop (several row chunks) through the protocol and then half the rate:
+    # the same broken springs at the same steps, the callback strains
+    # exactly, stress and energies within 1e-9, margins within 1e-9
+    wl = inputs.WORKLOADS["mode1"]
+    cases = [("notched", inputs.notched_composite(), wl["rate"], wl["steps"], wl["every"]),
+             ("bricks 203x141", inputs.brick_and_mortar(203, 141), 8 * wl["rate"], 4000, 1000)]
+    for name, img, rate, steps, every in cases:
+        say(f"rate sweep vs gather {name} fp64: {steps} steps at {rate}, then {steps // 2} at half")
+        out = []
+        for variant in ("gather", "sweep"):
+            g = lsm.Lattice.from_workload(wl, img, precision="fp64")
+            g.set_launch(variant)
+            recs = g.relax_trace(rate, steps, every)
+            recs += g.relax_trace(0.5 * rate, steps // 2, every)
+            out.append((g.read_broken(), recs))
+        (ea, ra), (eb, rb) = out
+        assert len(ea) > 0, "the case should break springs"
+        say(f"  {len(ea)} events, {len(ra)} callbacks")
+        for key in ("inc", "step", "id"):
+            assert np.array_equal(ea[key], eb[key]), key
+        assert np.max(np.abs(ea["margin"] - eb["margin"])) <= 1e-9 * np.max(np.abs(ea["margin"]))
+        assert len(ra) == len(rb)
+        for x, y in zip(ra, rb):
+            assert x["eps"] == y["eps"] and x["step"] == y["step"] and x["n_broken"] == y["n_broken"]
+            scale = max(np.max(np.abs(x["sigma"])), 1e-300)
+            assert np.max(np.abs(x["sigma"] - y["sigma"])) <= 1e-9 * scale
+            for q in ("pe", "ke"):
+                assert abs(x[q] - y[q]) <= 1e-9 * max(abs(x[q]), 1e-300)
