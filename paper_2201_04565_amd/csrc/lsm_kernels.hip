@@ -1763,7 +1763,7 @@ struct SweepRow {
     int f, m;
 };
 
-template <int PREC>
+template <int PREC, bool GRIP = false>
 __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, int i, bool col_ok, int jj,
                                       SweepRow<typename State<2, PREC>::R> &r, double geps = 0.0) {
     // Loads are unconditional from always-valid addresses, so no branch
@@ -1788,14 +1788,16 @@ __device__ inline void load_sweep_row(const StepParams &P, const SweepItem &it, 
     }
     r.f = (P.flags + it.base)[gf];
     r.m = (reinterpret_cast<const uint8_t *>(P.mask) + it.base)[gf];
-    if (P.grip_rate && r.f != kVoid && flag_grip(r.f) != 0) {
-        // constant-rate loading: the grip's displacement at strain geps, the
-        // value the grip kernel would have stored (the step carries it over)
-        const double ux = geps * (double(i) * P.a) + 0.0;
-        r.uh[0] = R(ux);
-        r.ul[0] = R(ux - double(r.uh[0]));
-        r.uh[1] = R(0);
-        r.ul[1] = R(0);
+    if constexpr (GRIP) {
+        if (r.f != kVoid && flag_grip(r.f) != 0) {
+            // constant-rate loading: the grip's displacement at strain geps,
+            // the value the grip kernel would have stored (the step carries it over)
+            const double ux = geps * (double(i) * P.a) + 0.0;
+            r.uh[0] = R(ux);
+            r.ul[0] = R(ux - double(r.uh[0]));
+            r.uh[1] = R(0);
+            r.ul[1] = R(0);
+        }
     }
     // the velocity too, also on the halo row below the chunk that is never
     // advanced: one more load there costs less than the branch around it
@@ -2022,8 +2024,10 @@ __device__ inline void row_force(const RowSprings<R> &o, const R *pUL, const R *
     newmask = m | o.nb | (bW << 3) | (bDR << 4) | (bDL << 5);
 }
 
-template <int PREC, int MODE, int PF, int BATCH>
-__global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
+// GRIP: constant-rate loading, where each row load places the grips at this
+// step's strain (interior steps only; compiled out of every other sweep)
+template <int PREC, int MODE, int PF, int BATCH, bool GRIP>
+__device__ __attribute__((always_inline)) inline void sweep2d_body(const StepParams &P, int step_local) {
     using S = State<2, PREC>;
     using R = typename S::R;
     using TTy = typename TT<PREC>::type;
@@ -2060,7 +2064,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         const double a64 = P.a, hy64 = kHalfSqrt3 * P.a;
         // strain of this step under constant-rate loading (the grip kernel's formula)
         double geps = 0.0;
-        if (P.grip_rate) {
+        if constexpr (GRIP) {
             const int steps = P.ctl->step_base + step_local - P.ctl->rate_s0;
             geps = __dadd_rn(P.ctl->rate_eps0, __dmul_rn(double(steps), P.ctl->rate_de));
         }
@@ -2073,7 +2077,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         auto row_step = [&](auto parc, int j, SweepRow<R> &rc, SweepRow<R> &ru,
                             SweepRow<R> &rn) __attribute__((always_inline)) {
             constexpr int PAR = decltype(parc)::value;
-            load_sweep_row<PREC>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn, geps);
+            load_sweep_row<PREC, GRIP>(P, it, i, col_ok, j + PF + 1 <= j1 ? j + PF + 1 : -1, rn, geps);
             RowSprings<R> o;
             row_springs<PREC, PAR>(tt, P.types, rc, ru, o, P.a, not_last, not_first);
             const R *eh = o.eh, *el = o.el, *ulh = o.ulh, *ull = o.ull, *urh = o.urh, *url = o.url;
@@ -2157,7 +2161,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
 #pragma unroll
         for (int t = 0; t <= PF; ++t) {
             const int jj = js + t;
-            load_sweep_row<PREC>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, B[t], geps);
+            load_sweep_row<PREC, GRIP>(P, it, i, col_ok, jj >= jstart && jj <= j1 ? jj : -1, B[t], geps);
         }
         for (int j = js; j < j1; j += K) {
             unroll_rows<0, K>([&](auto tc) __attribute__((always_inline)) {
@@ -2169,6 +2173,17 @@ __global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local
         }
     }
     (void)red_lds;
+}
+
+template <int PREC, int MODE, int PF, int BATCH>
+__global__ __launch_bounds__(kBlock) void k_sweep2d(StepParams P, int step_local) {
+    sweep2d_body<PREC, MODE, PF, BATCH, false>(P, step_local);
+}
+
+// interior step under constant-rate loading (single lattices)
+template <int PREC, int PF>
+__global__ __launch_bounds__(kBlock) void k_sweep2d_rate(StepParams P, int step_local) {
+    sweep2d_body<PREC, kMid, PF, 0, true>(P, step_local);
 }
 
 // Two interior time steps per launch: temporal blocking of the row sweep.
@@ -2397,7 +2412,15 @@ hipError_t launch_sweep_pf(const StepParams &p, int mode, hipStream_t s, int ste
     const dim3 grid(nblocks), block(kBlock);
     switch (mode) {
         case kStart: hipLaunchKernelGGL((k_sweep2d<PREC, kStart, PF, BATCH>), grid, block, 0, s, p, step_local); break;
-        case kMid: hipLaunchKernelGGL((k_sweep2d<PREC, kMid, PF, BATCH>), grid, block, 0, s, p, step_local); break;
+        case kMid:
+            if constexpr (BATCH == 0) {
+                if (p.grip_rate) {
+                    hipLaunchKernelGGL((k_sweep2d_rate<PREC, PF>), grid, block, 0, s, p, step_local);
+                    break;
+                }
+            }
+            hipLaunchKernelGGL((k_sweep2d<PREC, kMid, PF, BATCH>), grid, block, 0, s, p, step_local);
+            break;
         default: hipLaunchKernelGGL((k_sweep2d<PREC, kEnd, PF, BATCH>), grid, block, 0, s, p, step_local); break;
     }
     return hipGetLastError();
