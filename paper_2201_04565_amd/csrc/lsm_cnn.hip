@@ -16,8 +16,8 @@
 // weights, Adam moments and dense layers are FP32.
 //
 // Pooling never makes a pass of its own: the first layer (one input
-// channel) is computed and pooled by one kernel and recomputed from the
-// image in its backward pass; the other pooled layers pool in the conv
+// channel) is computed and pooled by one kernel, which also keeps the ReLU
+// signs for its backward pass; the other pooled layers pool in the conv
 // epilogue and keep a 4-bit ReLU mask per pooled pixel, which the next
 // layer's input-gradient epilogue uses to write the full-resolution gradient
 // directly.  Only the last conv output is stored at full resolution.
@@ -56,8 +56,8 @@ union Frag {
 // C channels.  Each of the four conv outputs is rounded to BF16 after the
 // ReLU and the four are averaged in the order (0,0), (0,1), (1,0), (1,1):
 // the same values as storing the conv output and pooling it, without the
-// full-resolution map ever reaching memory (the backward pass recomputes its
-// sign from the image).
+// full-resolution map ever reaching memory (its ReLU signs are kept, four
+// bits per pooled pixel and channel).
 __device__ inline void conv1_patch(const uint8_t *x, int H, int W, int64_t n, int yo, int xo, float v[4][4]) {
     // sixteen unconditional loads from clamped addresses, zeroed off the
     // image by a factor (a select would let the compiler put each load
@@ -98,8 +98,11 @@ __device__ inline float conv1_at(const float *w, const float *b, int c, const fl
     return s;
 }
 
+// The ReLU signs of the four conv outputs under each pooled pixel go to
+// mask, 32 bits per group of eight channels (bit 4 e + d: channel 8 g + e,
+// sub-pixel d = (d / 2, d mod 2)), for the backward pass.
 __global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const float *w, const float *b,
-                                                        u16 *pool, int B, int H, int W, int C) {
+                                                        u16 *pool, uint32_t *mask, int B, int H, int W, int C) {
     // weights and biases once per workgroup in LDS (C <= 256): every lane
     // reads the same word, a broadcast
     __shared__ float ws[256 * 9], bs[256];
@@ -114,16 +117,27 @@ __global__ __launch_bounds__(kBlk) void k_conv1_pool_fwd(const uint8_t *x, const
     split_pooled(q, Wo, Ho, xo, yo, n);
     float v[4][4];
     conv1_patch(x, H, W, n, yo, xo, v);
-    for (int c0 = 0; c0 < C; c0 += 8) {
-        u16 h[8];
+    // C is a multiple of 32: four groups of eight channels, one 16-byte mask store
+    for (int c1 = 0; c1 < C; c1 += 32) {
+        uint32_t mb[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            float s4 = 0.0f;
+        for (int gq = 0; gq < 4; ++gq) {
+            const int c0 = c1 + 8 * gq;
+            u16 h[8];
 #pragma unroll
-            for (int d = 0; d < 4; ++d) s4 += bf2f(f2bf(fmaxf(conv1_at(ws, bs, c0 + e, v, d >> 1, d & 1), 0.0f)));
-            h[e] = f2bf(0.25f * s4);
+            for (int e = 0; e < 8; ++e) {
+                float s4 = 0.0f;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    const float act = bf2f(f2bf(fmaxf(conv1_at(ws, bs, c0 + e, v, d >> 1, d & 1), 0.0f)));
+                    mb[gq] |= act > 0.0f ? 1u << (4 * e + d) : 0u;
+                    s4 += act;
+                }
+                h[e] = f2bf(0.25f * s4);
+            }
+            *reinterpret_cast<uint4 *>(pool + q * C + c0) = *reinterpret_cast<const uint4 *>(h);
         }
-        *reinterpret_cast<uint4 *>(pool + q * C + c0) = *reinterpret_cast<const uint4 *>(h);
+        *reinterpret_cast<uint4 *>(mask + q * (C / 8) + c1 / 8) = make_uint4(mb[0], mb[1], mb[2], mb[3]);
     }
 }
 
@@ -669,42 +683,48 @@ __device__ inline float wave_sum_f(float x) {
 }
 
 // Backward of the fused first layer: from the pooled gradient dpool, the
-// conv-output gradient of sub-pixel d is bf16(dpool / 4) where the
-// recomputed BF16 ReLU output is positive, else 0; it is multiplied into the
-// 9 image taps and the bias.  Pooled pixels of a split are strided over the
-// lanes; a fixed wavefront reduction combines the lanes.
-__global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const float *w, const float *b,
-                                                   const u16 *dpool, float *partial, int B, int H, int W, int C,
+// conv-output gradient of sub-pixel d is bf16(dpool / 4) where the forward
+// pass's BF16 ReLU output was positive (its mask bits), else 0; it is
+// multiplied into the 9 image taps and the bias.  Each wavefront takes
+// kC1Cpw channels (40 accumulators per lane, 90 registers: five wavefronts per SIMD, where
+// eight channels needed 130 registers and got three); pooled pixels of a
+// split are strided over the lanes; a fixed wavefront reduction combines
+// the lanes.
+constexpr int kC1Cpw = 4;
+
+__global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const uint32_t *mask, const u16 *dpool,
+                                                   float *partial, int B, int H, int W, int C,
                                                    int64_t q_per_split) {
     const int lane = threadIdx.x & 63;
     const int grp = (blockIdx.y * (kBlk / 64)) + (threadIdx.x >> 6);
-    if (grp * 8 >= C) return;  // whole wavefronts leave together
+    if (grp * kC1Cpw >= C) return;  // whole wavefronts leave together
     const int Ho = H / 2, Wo = W / 2;
     const int64_t nq = int64_t(B) * Ho * Wo;
     const int64_t b0 = int64_t(blockIdx.x) * q_per_split;
     const int64_t b1 = b0 + q_per_split < nq ? b0 + q_per_split : nq;
-    float acc[8][10];
+    // the mask word of eight channels holds this group's 16 bits at msh
+    const int mw = grp * kC1Cpw / 8, msh = (grp * kC1Cpw) % 8 * 4;
+    float acc[kC1Cpw][10];
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
+    for (int e = 0; e < kC1Cpw; ++e)
 #pragma unroll
         for (int k = 0; k < 10; ++k) acc[e][k] = 0.0f;
     for (int64_t q = b0 + lane; q < b1; q += 64) {
-        const uint4 gv = *reinterpret_cast<const uint4 *>(dpool + q * C + grp * 8);
+        const uint2 gv = *reinterpret_cast<const uint2 *>(dpool + q * C + grp * kC1Cpw);
         const u16 *gh = reinterpret_cast<const u16 *>(&gv);
+        const uint32_t mb = mask[q * (C / 8) + mw] >> msh;
         int xo, yo;
         int64_t n;
         split_pooled(q, Wo, Ho, xo, yo, n);
         float v[4][4];
         conv1_patch(x, H, W, n, yo, xo, v);
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int c = grp * 8 + e;
-            const float g = 0.25f * bf2f(gh[e]);
+        for (int e = 0; e < kC1Cpw; ++e) {
+            const float g = bf2f(f2bf(0.25f * bf2f(gh[e])));
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
                 const int dy = d >> 1, dx = d & 1;
-                const float act = bf2f(f2bf(fmaxf(conv1_at(w, b, c, v, dy, dx), 0.0f)));
-                const float da = bf2f(f2bf(act > 0.0f ? g : 0.0f));
+                const float da = (mb >> (4 * e + d)) & 1u ? g : 0.0f;
 #pragma unroll
                 for (int t = 0; t < 9; ++t) acc[e][t] = fmaf(da, v[dy + t / 3][dx + t % 3], acc[e][t]);
                 acc[e][9] += da;
@@ -712,11 +732,11 @@ __global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const floa
         }
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
+    for (int e = 0; e < kC1Cpw; ++e)
 #pragma unroll
         for (int k = 0; k < 10; ++k) {
             const float t = wave_sum_f(acc[e][k]);
-            if (lane == 0) partial[(int64_t(blockIdx.x) * C + grp * 8 + e) * 10 + k] = t;
+            if (lane == 0) partial[(int64_t(blockIdx.x) * C + grp * kC1Cpw + e) * 10 + k] = t;
         }
 }
 
@@ -1044,8 +1064,7 @@ size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
     for (int l = 1; l < kLayers; ++l) s.push_back(size_t(c->w_n[l]) * 2);  // wf
     for (int l = 1; l < kLayers; ++l) s.push_back(size_t(c->w_n[l]) * 2);  // wd
     // full-resolution conv outputs are stored only for the last layer; the
-    // others are pooled in the conv epilogue (the first layer's is
-    // recomputed in the backward pass, the others keep a ReLU mask)
+    // others are pooled in the conv epilogue and keep a ReLU mask
     const int L = kLayers - 1;
     s.push_back(size_t(B * c->Hs[L] * c->Hs[L] * c->C[L + 1]) * 2);  // act
     s.push_back(size_t(B * c->Hs[0] * c->Hs[0] / 4 * c->C[1]) * 2);  // dpool0
@@ -1053,7 +1072,8 @@ size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
         const int64_t hw = int64_t(c->Hs[l]) * c->Hs[l];
         s.push_back(l > 0 ? size_t(B * hw * c->C[l + 1]) * 2 : 0);       // dact
         s.push_back(l < L ? size_t(B * hw / 4 * c->C[l + 1]) * 2 : 0);   // pool
-        s.push_back(l > 0 && l < L ? size_t(B * hw / 4 * c->C[l + 1]) : 0);  // mask
+        // mask: 4 bits per pooled pixel and channel in the first layer, a byte in the others
+        s.push_back(l > 0 && l < L ? size_t(B * hw / 4 * c->C[l + 1]) : (l == 0 ? size_t(B * hw / 4 * c->C[1] / 2) : 0));
     }
     const int hid = c->cfg.hidden, out = c->cfg.outputs;
     s.push_back(size_t(B) * c->C[kLayers] * 4);  // gap
@@ -1238,7 +1258,8 @@ int lsm_cnn_forward(lsm_cnn *c, const uint8_t *x, int64_t batch, float *y) {
     const int B = int(batch);
     const int H0 = c->Hs[0];
     hipLaunchKernelGGL(k_conv1_pool_fwd, dim3(nblk(int64_t(B) * (H0 / 2) * (H0 / 2))), dim3(kBlk), 0, c->stream,
-                       x, c->p + c->w_off[0], c->p + c->b_off[0], c->pool[0], B, H0, H0, c->C[1]);
+                       x, c->p + c->w_off[0], c->p + c->b_off[0], c->pool[0],
+                       reinterpret_cast<uint32_t *>(c->mask[0]), B, H0, H0, c->C[1]);
     CHIP(c, hipGetLastError());
     for (int l = 1; l < kLayers; ++l) {
         const int H = c->Hs[l];
@@ -1379,10 +1400,10 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                                    int(cin));
             CHIP(c, hipGetLastError());
         } else {
-            const unsigned groups = unsigned((cout / 8 + kBlk / 64 - 1) / (kBlk / 64));
+            const unsigned groups = unsigned((cout / kC1Cpw + kBlk / 64 - 1) / (kBlk / 64));
             hipLaunchKernelGGL(k_conv1_bwd, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
-                               c->p + c->w_off[0], c->p + c->b_off[0], c->dpool0, c->part, B, H, H, int(cout),
-                               int64_t(kSplitPix / 4));
+                               reinterpret_cast<const uint32_t *>(c->mask[0]), c->dpool0, c->part, B, H, H,
+                               int(cout), int64_t(kSplitPix / 4));
             // part layout [split][co][10]: taps then bias
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout * 10)), dim3(kBlk), 0, c->stream, c->part,
                                c->part + sp * cout * 10, cout * 10, int(sp));

@@ -264,8 +264,8 @@ def test_input_gradient_raw(run):
 
 
 def test_first_layer_backward(run):
-    # the first layer's backward kernel recomputes the ReLU signs of its
-    # conv outputs from the image (FP32) and sums the tap and bias gradients
+    # the first layer's backward kernel takes the ReLU signs of its conv
+    # outputs (FP32 from the image) kept by the forward pass and sums the tap and bias gradients
     # of the pooled gradient; signs within the FP32 error of zero may go
     # either way and widen the bound by their terms
     b = run["buf"]
