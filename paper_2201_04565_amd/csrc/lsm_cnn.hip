@@ -957,8 +957,8 @@ __global__ __launch_bounds__(kBlk) void k_conv_weights_bf16(const float *w, u16 
 }
 
 // first-layer gradients: [co][10] sums (9 taps, then bias) -> weights, bias
-__global__ void k_scatter_conv1(const float *sum, float *gw, float *gb, int C) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlk) void k_scatter_conv1(const float *sum, float *gw, float *gb, int C) {
+    const int t = int(blockIdx.x) * kBlk + int(threadIdx.x);
     if (t >= C * 10) return;
     const int co = t / 10, k = t % 10;
     if (k < 9)
