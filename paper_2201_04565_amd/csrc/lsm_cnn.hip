@@ -654,6 +654,145 @@ __global__ __launch_bounds__(kBlk) void k_conv_wgrad_wide(const u16 *in, const u
     }
 }
 
+// Weight gradient over 8 x 8 pixel tiles (layers whose sides are multiples
+// of 8): per tile the 64 pixels' dout rows and the input of the tile with
+// its one-pixel halo (10 x 10 pixels, 32 input channels) are staged once;
+// the operand of tap (ty, tx) for the tile's pixel row y is then the staged
+// halo row y + ty from column tx on -- eight consecutive staged pixels, so
+// the transposing LDS read takes it as it takes a dout row.  Each input
+// value is loaded once per tile instead of once per tap.  Workgroup tile:
+// 64 output channels x (9 taps x 32 input channels); wavefront w computes
+// 32 channels x nine of the eighteen 16-column tiles (tile ct: tap ct / 2,
+// channels 16 (ct mod 2) ..).  Splits are runs of tiles; partial[split][co]
+// [n] as for the wide kernel, bias partials from the workgroups of the
+// first channel block (fixed-order reductions).
+constexpr int kWhS = 48;     // u16 per staged halo pixel: 32 channels + pad (conflict-free transposed reads)
+constexpr int kWhPix = 100;  // 10 x 10 staged pixels
+
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(3))) void k_conv_wgrad_halo(const u16 *in, const u16 *dout, float *partial,
+                                                         float *bias_partial, int B, int H, int W, int Cin,
+                                                         int Cout, int tiles_per_split) {
+    __shared__ __align__(16) u16 sd[64 * kWwDS];     // [tile pixel][co]
+    __shared__ __align__(16) u16 sx[kWhPix * kWhS];  // [halo pixel][ci]
+    __shared__ float bred[kBlk / 64][64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int N = 9 * Cin;
+    const int co_t = blockIdx.x * 64, ci_t = blockIdx.y * 32;
+    const int split = blockIdx.z;
+    const int tx_n = W >> 3, ty_n = H >> 3;
+    const int ntiles = B * ty_n * tx_n;
+    const int tbeg = split * tiles_per_split;
+    const int tend = min(tbeg + tiles_per_split, ntiles);
+    const int r16 = lane & 15, kq = lane >> 4;
+    const int wco = (wv >> 1) * 32, wct = (wv & 1) * 9;
+    const bool do_bias = blockIdx.y == 0;
+    f32x4 acc[2][9];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bsum[e] = 0.0f;
+    // staging: dout chunk q = tid + 256 i is tile pixel q / 8, channels
+    // co_t + 8 (q mod 8); halo chunk h = tid + 256 i (h < 400) is halo pixel
+    // h / 4, channels ci_t + 8 (h mod 4)
+    uint4 rd[2], rx[2];
+    auto gload = [&](int t) {
+        const int txi = t % tx_n, rr = t / tx_n, tyi = rr % ty_n, n = rr / ty_n;
+        const int y0 = 8 * tyi, x0 = 8 * txi;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = tid + kBlk * i, pix = q >> 3;
+            const int64_t p = (int64_t(n) * H + y0 + (pix >> 3)) * W + x0 + (pix & 7);
+            rd[i] = *reinterpret_cast<const uint4 *>(dout + p * Cout + co_t + 8 * (q & 7));
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            // unconditional loads from valid addresses, zeroed off the image
+            const int h = tid + kBlk * i, hp = min(h >> 2, kWhPix - 1);
+            const int y = y0 + hp / 10 - 1, x = x0 + hp % 10 - 1;
+            const bool ok = h < 4 * kWhPix && y >= 0 && y < H && x >= 0 && x < W;
+            const int64_t pi = ok ? (int64_t(n) * H + y) * W + x : 0;
+            const uint4 v = *reinterpret_cast<const uint4 *>(in + pi * Cin + ci_t + 8 * (h & 3));
+            rx[i] = ok ? v : make_uint4(0, 0, 0, 0);
+        }
+    };
+    if (tbeg < tend) gload(tbeg);
+    for (int t = tbeg; t < tend; ++t) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int q = tid + kBlk * i;
+            *reinterpret_cast<uint4 *>(sd + (q >> 3) * kWwDS + 8 * (q & 7)) = rd[i];
+            if (do_bias) {
+                const u16 *e8 = reinterpret_cast<const u16 *>(&rd[i]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) bsum[e] += bf2f(e8[e]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int h = tid + kBlk * i;
+            if (h < 4 * kWhPix) *reinterpret_cast<uint4 *>(sx + (h >> 2) * kWhS + 8 * (h & 3)) = rx[i];
+        }
+        __syncthreads();
+        if (t + 1 < tend) gload(t + 1);  // next tile in flight during the MFMAs
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int k0 = ks * 32 + 8 * kq;  // tile pixels k0 .. k0 + 7: row k0 / 8
+            bf16x8 a[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) a[r] = tr_frag_s<kWwDS>(sd, k0, wco + r * 16, r16);
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const int ct = wct + c, tap = ct >> 1;
+                const int hrow = ((k0 >> 3) + tap / 3) * 10 + tap % 3;
+                const bf16x8 bb = tr_frag_s<kWhS>(sx, hrow, 16 * (ct & 1), r16);
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r], bb, acc[r][c], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // D: rows = co (4 kq + i), column = r16 of tile ct
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const int ct = wct + c;
+            const int n = (ct >> 1) * Cin + ci_t + 16 * (ct & 1) + r16;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = co_t + wco + r * 16 + 4 * kq + i;
+                partial[(int64_t(split) * Cout + co) * N + n] = acc[r][c][i];
+            }
+        }
+    if (do_bias) {  // uniform per workgroup
+        // thread tid summed channels co_t + 8 (tid mod 8) ..: lanes of equal
+        // tid mod 8 within the wavefront, then the four wavefronts in order
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            float v = bsum[e];
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            bsum[e] = v;
+        }
+        if (lane < 8) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bred[wv][8 * lane + e] = bsum[e];
+        }
+        __syncthreads();
+        if (tid < 64) {
+            float v = 0.0f;
+#pragma unroll
+            for (int w = 0; w < kBlk / 64; ++w) v += bred[w][tid];
+            bias_partial[int64_t(split) * Cout + co_t + tid] = v;
+        }
+    }
+}
+
 // Fixed-order sum of split partials: four interleaved running sums (splits
 // k = 0, 1, 2, 3 mod 4) so the loads overlap, combined as (s0 + s1) + (s2 + s3).
 __global__ __launch_bounds__(kBlk) void k_sum_splits(const float *partial, float *out, int64_t n, int splits) {
@@ -1053,6 +1192,16 @@ int64_t wgrad_pix_per_split(int64_t npix, int64_t cout, int64_t cin) {
     return std::max<int64_t>(64, ((npix + sp - 1) / sp + 63) / 64 * 64);
 }
 
+// The halo weight-gradient kernel: sides multiples of 8, whole 32-channel
+// input blocks and 64-channel output blocks.  Splits are runs of 8 x 8
+// tiles, about 512 workgroups in all.
+bool wgrad_halo_ok(int64_t H, int64_t cin, int64_t cout) { return H % 8 == 0 && cin % 32 == 0 && cout % 64 == 0; }
+int64_t wgrad_halo_tiles_per_split(int64_t ntiles, int64_t cout, int64_t cin) {
+    const int64_t blocks = (cout / 64) * (cin / 32);
+    const int64_t sp = std::max<int64_t>(1, (512 + blocks - 1) / blocks);
+    return std::max<int64_t>(1, (ntiles + sp - 1) / sp);
+}
+
 size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
     const int64_t B = c->cfg.batch;
     const int64_t P = c->nparam;
@@ -1147,6 +1296,10 @@ int lsm_cnn_create(const lsm_cnn_config *cfg, lsm_cnn **out) {
             const int64_t pps = wgrad_pix_per_split(npix, c->C[l + 1], c->C[l]);
             const int64_t sw = (npix + pps - 1) / pps;
             pn = std::max(pn, size_t(sw * (c->w_n[l] + c->C[l + 1])));
+            if (wgrad_halo_ok(c->Hs[l], c->C[l], c->C[l + 1])) {
+                const int64_t nt = npix / 64, tps = wgrad_halo_tiles_per_split(nt, c->C[l + 1], c->C[l]);
+                pn = std::max(pn, size_t((nt + tps - 1) / tps * (c->w_n[l] + c->C[l + 1])));
+            }
         }
     }
     // slack for the first layer's summed [co][10] block after its partials
@@ -1359,12 +1512,23 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
         const int64_t nw = c->w_n[l], cout = c->C[l + 1], cin = c->C[l];
         if (l > 0) {
             // weight gradient: MFMA over pixel splits, then a fixed-order sum
-            const int64_t pps = wgrad_pix_per_split(npix, cout, cin);
-            const int64_t sw = (npix + pps - 1) / pps;
-            const dim3 grid(unsigned((cout + 63) / 64), unsigned(9 * cin / kWwN), unsigned(sw));
-            float *bias_part = c->part + sw * nw;  // [split][co] after the weight partials
-            hipLaunchKernelGGL(k_conv_wgrad_wide, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l], c->part,
-                               bias_part, B, H, H, int(cin), int(cout), int(pps));
+            int64_t sw;
+            float *bias_part;
+            if (wgrad_halo_ok(H, cin, cout)) {
+                const int64_t nt = npix / 64, tps = wgrad_halo_tiles_per_split(nt, cout, cin);
+                sw = (nt + tps - 1) / tps;
+                bias_part = c->part + sw * nw;  // [split][co] after the weight partials
+                const dim3 grid(unsigned(cout / 64), unsigned(cin / 32), unsigned(sw));
+                hipLaunchKernelGGL(k_conv_wgrad_halo, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l],
+                                   c->part, bias_part, B, H, H, int(cin), int(cout), int(tps));
+            } else {
+                const int64_t pps = wgrad_pix_per_split(npix, cout, cin);
+                sw = (npix + pps - 1) / pps;
+                bias_part = c->part + sw * nw;
+                const dim3 grid(unsigned((cout + 63) / 64), unsigned(9 * cin / kWwN), unsigned(sw));
+                hipLaunchKernelGGL(k_conv_wgrad_wide, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l],
+                                   c->part, bias_part, B, H, H, int(cin), int(cout), int(pps));
+            }
             CHIP(c, hipGetLastError());
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
                                int(sw));
