@@ -466,6 +466,13 @@ __global__ __launch_bounds__(kBlk) void k_conv_lds128(const u16 *in, const u16 *
     conv_lds_body<128, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
 }
 
+// 256 input channels (the input gradient of the last layer): a 53 KB patch
+template <int TW, int BN, int EPI>
+__global__ __launch_bounds__(kBlk) void k_conv_lds256(const u16 *in, const u16 *wt, const float *bias, u16 *out,
+                                                     uint8_t *mask_out, int B, int H, int W, int Cout) {
+    conv_lds_body<256, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+}
+
 // The staged-patch kernel takes layers with 32, 64 or 128 input channels
 // whose 8 x TW tiles and 64-channel blocks divide the layer exactly; layers
 // with a multiple of 128 output channels take 128-channel blocks (one
@@ -1548,6 +1555,10 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             else if (l > 1 && cout == 128 && cin == 128 && H % 16 == 0)
                 hipLaunchKernelGGL((k_conv_lds128<16, 128, kEpiExpand>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
                                    c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
+            else if (l > 1 && cout == 256 && cin % 128 == 0 && H % 8 == 0)
+                hipLaunchKernelGGL((k_conv_lds256<8, 128, kEpiExpand>), dim3(unsigned(B * (H / 8) * (H / 8)),
+                                   unsigned(cin / 128)), dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
+                                   c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
             else if (l > 1)
                 hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
