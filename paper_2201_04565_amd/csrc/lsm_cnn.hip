@@ -394,10 +394,50 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < NT; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bcur[c].v, acc[r][c], 0, 0, 0);
+            for (int c = 0; c < NT; ++c) {
+                // the expanding epilogue takes the transposed product: four
+                // consecutive channels of one pixel per lane
+                if constexpr (EPI == kEpiExpand)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bcur[c].v, a[r].v, acc[r][c], 0, 0, 0);
+                else
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[r].v, bcur[c].v, acc[r][c], 0, 0, 0);
+            }
 #pragma unroll
         for (int c = 0; c < NT; ++c) bcur[c] = bnext[c];
+    }
+    if constexpr (EPI == kEpiExpand) {
+        // input gradient of a pooled layer: this layer's output grid is the
+        // pooled grid of the one below; each value, times a quarter, goes to
+        // the 2 x 2 pixels whose ReLU was active (mask_out holds the masks of
+        // the layer below, read here).  This lane holds channels
+        // cw + 16 c + 4 kq .. + 3 of pixel row 16 r + r16 of the tile (quad
+        // 4 r + r16 / 4, position r16 mod 4): one 4-byte mask load and four
+        // 8-byte stores per tile.
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ql = 4 * r + (r16 >> 2), pos = r16 & 3;
+            const int qy = y0 / 2 + 2 * wm + ql / QW, qx = x0 / 2 + ql % QW;
+            const int y = 2 * qy + (pos >> 1), x = 2 * qx + (pos & 1);
+            const int64_t pp = (int64_t(n) * H + y) * W + x;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const int co0 = cw + 16 * c + 4 * kq;
+                const uint32_t m4 = *reinterpret_cast<const uint32_t *>(mask_out + pp * Cout + co0);
+                u16 h[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) h[i] = f2bf(0.25f * bf2f(f2bf(acc[r][c][i])));
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    u16 v[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = (m4 >> (8 * i + d)) & 1u ? h[i] : u16(0);
+                    const int64_t o = ((int64_t(n) * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * Cout + co0;
+                    *reinterpret_cast<uint2 *>(out + o) = make_uint2(uint32_t(v[0]) | (uint32_t(v[1]) << 16),
+                                                                     uint32_t(v[2]) | (uint32_t(v[3]) << 16));
+                }
+            }
+        }
+        return;
     }
     // epilogue: this lane holds quad 4 r + kq of M tile r, channel column
     // r16 of N tile c
@@ -408,26 +448,9 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int co = cw + 16 * c + r16;
-            // input gradients (raw, expand) carry no bias
-            const float bv = (EPI == kEpiRaw || EPI == kEpiExpand) ? 0.0f : bias[co];
-            if constexpr (EPI == kEpiExpand) {
-                // input gradient of a pooled layer: this layer's output grid
-                // is the pooled grid of the one below; each value, times a
-                // quarter, goes to the 2 x 2 pixels whose ReLU was active
-                // (mask_out holds the masks of the layer below, read here)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int y = 2 * qy + (i >> 1), x = 2 * qx + (i & 1);
-                    const int64_t pp = (int64_t(n) * H + y) * W + x;
-                    const u16 h = f2bf(0.25f * bf2f(f2bf(acc[r][c][i])));
-                    const unsigned m = mask_out[pp * Cout + co];
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) {
-                        const int64_t o = ((int64_t(n) * 2 * H + 2 * y + (d >> 1)) * (2 * W) + 2 * x + (d & 1)) * Cout + co;
-                        out[o] = (m >> d) & 1u ? h : u16(0);
-                    }
-                }
-            } else if constexpr (EPI == kEpiPool) {
+            // raw input gradients carry no bias
+            const float bv = EPI == kEpiRaw ? 0.0f : bias[co];
+            if constexpr (EPI == kEpiPool) {
                 const int64_t q = (int64_t(n) * (H / 2) + qy) * (W / 2) + qx;
                 float s4 = 0.0f;
                 unsigned m = 0;
