@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 // epilogue above).  The reduction runs in the same K steps and order as
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
-template <int CIN, int TW, int BN, int EPI>
+template <int CIN, int TW, int BN, int EPI, int MT>
 __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *in, const u16 *wt, const float *bias,
                                                                     u16 *out, uint8_t *mask_out, int B, int H, int W,
                                                                     int Cout) {
@@ -338,7 +338,9 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     constexpr int RS = PW * PS + 16;
     constexpr int KPT = CIN / 32;
     constexpr int NK = 9 * KPT;
-    constexpr int NT = TW == 16 ? BN / 32 : BN / 64;  // 16-column MFMA tiles per wavefront
+    // MT 16-row MFMA tiles (MT * 16 pixels) x NT 16-column tiles per wavefront
+    static_assert(MT == 4 || (MT == 8 && TW == 16), "128-pixel wavefronts need 8 x 16 tiles");
+    constexpr int NT = MT == 8 ? BN / 64 : (TW == 16 ? BN / 32 : BN / 64);
     constexpr int QW = TW / 2;            // quads per tile row pair
     __shared__ __attribute__((aligned(16))) u16 patch[PH * RS];
     const int tiles_x = W / TW, tiles_y = H / 8;
@@ -357,23 +359,25 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int wm = TW == 16 ? (wv & 1) : 0;
-    const int cw = blockIdx.y * BN + (TW == 16 ? (BN / 2) * (wv >> 1) : (BN / 4) * wv);  // wavefront's first channel
+    // wavefront's first channel, and first quad row (pairs of pixel rows) of the tile
+    const int cw = blockIdx.y * BN + (MT == 8 || TW == 8 ? (BN / 4) * wv : (BN / 2) * (wv >> 1));
+    const int qr0 = MT == 8 ? 0 : 2 * wm;
     const int r16 = lane & 15, kq = lane >> 4;
     // patch pixel (before the tap shift) of this lane's row in each M tile:
     // row 16 r + r16 is quad 4 r + r16 / 4, position r16 mod 4
-    int abase[4];
+    int abase[MT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < MT; ++r) {
         const int ql = 4 * r + (r16 >> 2), sub = r16 & 3;
-        const int y = 4 * wm + 2 * (ql / QW) + (sub >> 1), x = 2 * (ql % QW) + (sub & 1);
+        const int y = 2 * (qr0 + ql / QW) + (sub >> 1), x = 2 * (ql % QW) + (sub & 1);
         abase[r] = (y + 1) * RS + (x + 1) * PS + 8 * kq;
     }
     const u16 *wrow[NT];
 #pragma unroll
     for (int c = 0; c < NT; ++c) wrow[c] = wt + int64_t(cw + 16 * c + r16) * (9 * CIN) + 8 * kq;
-    f32x4 acc[4][NT];
+    f32x4 acc[MT][NT];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int r = 0; r < MT; ++r)
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     Frag bcur[NT], bnext[NT];
@@ -388,11 +392,11 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
         }
         const int tap = kk / KPT, ci0 = (kk - tap * KPT) * 32;
         const int shift = (tap / 3 - 1) * RS + (tap % 3 - 1) * PS + ci0;
-        Frag a[4];
+        Frag a[MT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r].u = *reinterpret_cast<const uint4 *>(patch + abase[r] + shift);
+        for (int r = 0; r < MT; ++r) a[r].u = *reinterpret_cast<const uint4 *>(patch + abase[r] + shift);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int r = 0; r < MT; ++r)
 #pragma unroll
             for (int c = 0; c < NT; ++c) {
                 // the expanding epilogue takes the transposed product: four
@@ -414,9 +418,9 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
         // 4 r + r16 / 4, position r16 mod 4): one 4-byte mask load and four
         // 8-byte stores per tile.
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < MT; ++r) {
             const int ql = 4 * r + (r16 >> 2), pos = r16 & 3;
-            const int qy = y0 / 2 + 2 * wm + ql / QW, qx = x0 / 2 + ql % QW;
+            const int qy = y0 / 2 + qr0 + ql / QW, qx = x0 / 2 + ql % QW;
             const int y = 2 * qy + (pos >> 1), x = 2 * qx + (pos & 1);
             const int64_t pp = (int64_t(n) * H + y) * W + x;
 #pragma unroll
@@ -442,9 +446,9 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     // epilogue: this lane holds quad 4 r + kq of M tile r, channel column
     // r16 of N tile c
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < MT; ++r) {
         const int ql = 4 * r + kq;
-        const int qy = y0 / 2 + 2 * wm + ql / QW, qx = x0 / 2 + ql % QW;  // pooled coordinates
+        const int qy = y0 / 2 + qr0 + ql / QW, qx = x0 / 2 + ql % QW;  // pooled coordinates
 #pragma unroll
         for (int c = 0; c < NT; ++c) {
             const int co = cw + 16 * c + r16;
@@ -477,23 +481,23 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 // Register target of four waves per SIMD; with 128 input channels the
 // 49 KB patch leaves room for three workgroups per CU anyway, and that
 // variant keeps its registers (measured faster than squeezed).
-template <int CIN, int TW, int BN, int EPI>
+template <int CIN, int TW, int BN, int EPI, int MT = 4>
 __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_lds(
     const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask_out, int B, int H, int W, int Cout) {
-    conv_lds_body<CIN, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+    conv_lds_body<CIN, TW, BN, EPI, MT>(in, wt, bias, out, mask_out, B, H, W, Cout);
 }
 
-template <int TW, int BN, int EPI>
+template <int TW, int BN, int EPI, int MT = 4>
 __global__ __launch_bounds__(kBlk) void k_conv_lds128(const u16 *in, const u16 *wt, const float *bias, u16 *out,
                                                      uint8_t *mask_out, int B, int H, int W, int Cout) {
-    conv_lds_body<128, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+    conv_lds_body<128, TW, BN, EPI, MT>(in, wt, bias, out, mask_out, B, H, W, Cout);
 }
 
 // 256 input channels (the input gradient of the last layer): a 53 KB patch
 template <int TW, int BN, int EPI>
 __global__ __launch_bounds__(kBlk) void k_conv_lds256(const u16 *in, const u16 *wt, const float *bias, u16 *out,
                                                      uint8_t *mask_out, int B, int H, int W, int Cout) {
-    conv_lds_body<256, TW, BN, EPI>(in, wt, bias, out, mask_out, B, H, W, Cout);
+    conv_lds_body<256, TW, BN, EPI, 4>(in, wt, bias, out, mask_out, B, H, W, Cout);
 }
 
 // The staged-patch kernel takes layers with 32, 64 or 128 input channels
@@ -508,13 +512,16 @@ inline int conv_lds_tw(int H, int W, int Cin, int Cout) {
 template <int EPI, int TW, int BN>
 void launch_conv_lds_bn(hipStream_t st, const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask,
                         int B, int H, int Cin, int Cout) {
+    // 8 x 16 tiles: each wavefront takes all 128 pixels and BN / 4 channels
+    // (half the weight loads per MFMA of 64-pixel wavefronts over BN / 2)
+    constexpr int MT = TW == 16 ? 8 : 4;
     const dim3 g(unsigned(B * (H / 8) * (H / TW)), unsigned(Cout / BN));
     if (Cin == 32)
-        hipLaunchKernelGGL((k_conv_lds<32, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+        hipLaunchKernelGGL((k_conv_lds<32, TW, BN, EPI, MT>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
     else if (Cin == 64)
-        hipLaunchKernelGGL((k_conv_lds<64, TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+        hipLaunchKernelGGL((k_conv_lds<64, TW, BN, EPI, MT>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
     else
-        hipLaunchKernelGGL((k_conv_lds128<TW, BN, EPI>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
+        hipLaunchKernelGGL((k_conv_lds128<TW, BN, EPI, MT>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
 }
 
 template <int EPI>
@@ -1573,10 +1580,10 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             if (l > 1 && cout == 128 && cin == 64 && H % 16 == 0)
                 // staged-patch kernel (same K order, same bits); the mask
                 // slot carries the masks of the layer below, read
-                hipLaunchKernelGGL((k_conv_lds128<16, 64, kEpiExpand>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
+                hipLaunchKernelGGL((k_conv_lds128<16, 64, kEpiExpand, 8>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
                                    c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
             else if (l > 1 && cout == 128 && cin == 128 && H % 16 == 0)
-                hipLaunchKernelGGL((k_conv_lds128<16, 128, kEpiExpand>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
+                hipLaunchKernelGGL((k_conv_lds128<16, 128, kEpiExpand, 8>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
                                    c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], B, H, H, int(cin));
             else if (l > 1 && cout == 256 && cin % 128 == 0 && H % 8 == 0)
                 hipLaunchKernelGGL((k_conv_lds256<8, 128, kEpiExpand>), dim3(unsigned(B * (H / 8) * (H / 8)),
@@ -1589,7 +1596,7 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             else if (cout == 64 && cin % 32 == 0 && H % 16 == 0)
                 // the staged-patch kernel (same K order, same bits): 64-channel
                 // gradient input, 32-channel blocks of the output
-                hipLaunchKernelGGL((k_conv_lds<64, 16, 32, kEpiRaw>), dim3(unsigned(B * (H / 8) * (H / 16)),
+                hipLaunchKernelGGL((k_conv_lds<64, 16, 32, kEpiRaw, 4>), dim3(unsigned(B * (H / 8) * (H / 16)),
                                    unsigned(cin / 32)), dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
                                    c->dpool0, nullptr, B, H, H, int(cin));
             else
