@@ -316,14 +316,18 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 
 // Forward convolution (ReLU, then 2x2 average pooling or a plain store)
 // with the input patch staged in LDS.  A workgroup computes an 8 x TW pixel
-// tile of one image (TW = 16 or 8) and BN output channels (64 or 128): the
-// (8 + 2) x (TW + 2) x CIN input patch (zeros off the image) is loaded into
-// LDS once and serves all nine taps, so each input value is fetched once
-// per tile instead of once per tap.  With TW = 16 the four wavefronts split
-// the tile into 2 x 2 blocks of 64 pixels (4 tile rows) x BN / 2 channels;
-// with TW = 8 each takes all 64 pixels and BN / 4 channels.  A wavefront's pixels form four
-// 16-row MFMA tiles of four 2x2 quads each (the row order of the pooling
-// epilogue above).  The reduction runs in the same K steps and order as
+// tile of one image (TW = 8, 16 or 32) and BN output channels (32 to 128):
+// the (8 + 2) x (TW + 2) x CIN input patch (zeros off the image) is loaded
+// into LDS once and serves all nine taps, so each input value is fetched
+// once per tile instead of once per tap.  A wavefront takes MT * 16 pixels
+// (MT 16-row MFMA tiles of four 2x2 quads each, the row order of the
+// pooling epilogue above) and the channels of its group: with 8 x 16 tiles
+// and MT = 8 each of the four takes all 128 pixels and BN / 4 channels, with
+// 8 x 32 tiles two take each half of the pixels for BN / 2 channels, with
+// 8 x 8 tiles each takes all 64 pixels (MT = 4).  More pixels per wavefront
+// means fewer weight loads per MFMA: on 8 x 16 tiles, 128-pixel wavefronts
+// ran the layers 20-35 % faster than 64-pixel ones over BN / 2 channels,
+// and 32-pixel ones over all BN channels 30-45 % slower.  The reduction runs in the same K steps and order as
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
 template <int CIN, int TW, int BN, int EPI, int MT>
@@ -339,8 +343,12 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     constexpr int KPT = CIN / 32;
     constexpr int NK = 9 * KPT;
     // MT 16-row MFMA tiles (MT * 16 pixels) x NT 16-column tiles per wavefront
-    static_assert(MT == 4 || (MT == 8 && TW == 16), "128-pixel wavefronts need 8 x 16 tiles");
-    constexpr int NT = MT == 8 ? BN / 64 : (TW == 16 ? BN / 32 : BN / 64);
+    // the tile's 8 TW pixels form PG groups of MT * 16 (one per wavefront),
+    // the BN channels CG groups: wavefront w takes pixel group w mod PG and
+    // channel group w / PG
+    constexpr int PG = 8 * TW / (16 * MT), CG = 4 / PG;
+    static_assert(PG * 16 * MT == 8 * TW && PG * CG == 4 && BN % (16 * CG) == 0, "wavefront layout");
+    constexpr int NT = BN / (16 * CG);
     constexpr int QW = TW / 2;            // quads per tile row pair
     __shared__ __attribute__((aligned(16))) u16 patch[PH * RS];
     const int tiles_x = W / TW, tiles_y = H / 8;
@@ -358,10 +366,9 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int wm = TW == 16 ? (wv & 1) : 0;
     // wavefront's first channel, and first quad row (pairs of pixel rows) of the tile
-    const int cw = blockIdx.y * BN + (MT == 8 || TW == 8 ? (BN / 4) * wv : (BN / 2) * (wv >> 1));
-    const int qr0 = MT == 8 ? 0 : 2 * wm;
+    const int cw = blockIdx.y * BN + (wv / PG) * (BN / CG);
+    const int qr0 = (wv % PG) * (8 * MT / TW);
     const int r16 = lane & 15, kq = lane >> 4;
     // patch pixel (before the tap shift) of this lane's row in each M tile:
     // row 16 r + r16 is quad 4 r + r16 / 4, position r16 mod 4
@@ -478,11 +485,12 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     }
 }
 
-// Register target of four waves per SIMD; with 128 input channels the
-// 49 KB patch leaves room for three workgroups per CU anyway, and that
-// variant keeps its registers (measured faster than squeezed).
+// Register target of four waves per SIMD (three for 8 x 32 tiles, whose
+// 49 KB patch leaves room for three workgroups per CU); with 128 input
+// channels the patch is 49 KB too, and that variant keeps its registers
+// (measured faster than squeezed).
 template <int CIN, int TW, int BN, int EPI, int MT = 4>
-__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_conv_lds(
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(TW == 32 ? 3 : 4))) void k_conv_lds(
     const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask_out, int B, int H, int W, int Cout) {
     conv_lds_body<CIN, TW, BN, EPI, MT>(in, wt, bias, out, mask_out, B, H, W, Cout);
 }
@@ -514,7 +522,7 @@ void launch_conv_lds_bn(hipStream_t st, const u16 *in, const u16 *wt, const floa
                         int B, int H, int Cin, int Cout) {
     // 8 x 16 tiles: each wavefront takes all 128 pixels and BN / 4 channels
     // (half the weight loads per MFMA of 64-pixel wavefronts over BN / 2)
-    constexpr int MT = TW == 16 ? 8 : 4;
+    constexpr int MT = TW >= 16 ? 8 : 4;
     const dim3 g(unsigned(B * (H / 8) * (H / TW)), unsigned(Cout / BN));
     if (Cin == 32)
         hipLaunchKernelGGL((k_conv_lds<32, TW, BN, EPI, MT>), g, dim3(kBlk), 0, st, in, wt, bias, out, mask, B, H, H, Cout);
@@ -528,6 +536,7 @@ template <int EPI>
 void launch_conv_lds(hipStream_t st, int tw, const u16 *in, const u16 *wt, const float *bias, u16 *out,
                      uint8_t *mask, int B, int H, int Cin, int Cout) {
     const bool wide = Cout % 128 == 0;
+    // (8 x 32 tiles for the 32-channel layer: 119 against 108 us)
     if (tw == 16 && wide) launch_conv_lds_bn<EPI, 16, 128>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
     else if (tw == 16) launch_conv_lds_bn<EPI, 16, 64>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
     else if (wide) launch_conv_lds_bn<EPI, 8, 128>(st, in, wt, bias, out, mask, B, H, Cin, Cout);
@@ -1593,9 +1602,14 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                 hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
                                    int(cout), int(cin));
-            else if (cout == 64 && cin % 32 == 0 && H % 16 == 0)
+            else if (cout == 64 && cin % 32 == 0 && H % 32 == 0)
                 // the staged-patch kernel (same K order, same bits): 64-channel
-                // gradient input, 32-channel blocks of the output
+                // gradient input, 32-channel blocks of the output, 8 x 32 tiles
+                // (two wavefronts of 128 pixels per 16 channels)
+                hipLaunchKernelGGL((k_conv_lds<64, 32, 32, kEpiRaw, 8>), dim3(unsigned(B * (H / 8) * (H / 32)),
+                                   unsigned(cin / 32)), dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
+                                   c->dpool0, nullptr, B, H, H, int(cin));
+            else if (cout == 64 && cin % 32 == 0 && H % 16 == 0)
                 hipLaunchKernelGGL((k_conv_lds<64, 16, 32, kEpiRaw, 4>), dim3(unsigned(B * (H / 8) * (H / 16)),
                                    unsigned(cin / 32)), dim3(kBlk), 0, c->stream, c->dact[l], c->wd[l], nullptr,
                                    c->dpool0, nullptr, B, H, H, int(cin));
