@@ -1141,6 +1141,19 @@ __global__ __launch_bounds__(kBlk) void k_conv_weights_bf16(const float *w, u16 
     if (wd) wd[(int64_t(ci) * 9 + (8 - tap)) * Cout + co] = h;
 }
 
+// Fixed-order sum of split partials for few outputs over many splits: one
+// wavefront per output, lane l summing splits l, l + 64, ... in order, then
+// a fixed butterfly over the lanes.
+__global__ __launch_bounds__(kBlk) void k_sum_splits_wave(const float *partial, float *out, int64_t n, int splits) {
+    const int64_t i = int64_t(blockIdx.x) * (kBlk / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;  // whole wavefronts
+    const int lane = threadIdx.x & 63;
+    float s = 0.0f;
+    for (int k = lane; k < splits; k += 64) s += partial[int64_t(k) * n + i];
+    s = wave_sum_f(s);
+    if (lane == 0) out[i] = s;
+}
+
 // first-layer gradients: [co][10] sums (9 taps, then bias) -> weights, bias
 __global__ __launch_bounds__(kBlk) void k_scatter_conv1(const float *sum, float *gw, float *gb, int C) {
     const int t = int(blockIdx.x) * kBlk + int(threadIdx.x);
@@ -1578,8 +1591,8 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             CHIP(c, hipGetLastError());
             hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
                                int(sw));
-            hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout)), dim3(kBlk), 0, c->stream, bias_part,
-                               c->g + c->b_off[l], cout, int(sw));
+            hipLaunchKernelGGL(k_sum_splits_wave, dim3(unsigned((cout + kBlk / 64 - 1) / (kBlk / 64))), dim3(kBlk), 0,
+                               c->stream, bias_part, c->g + c->b_off[l], cout, int(sw));
             CHIP(c, hipGetLastError());
             // input gradient: implicit GEMM with the flipped weights; its
             // epilogue applies the pooling and ReLU of the layer below (the
@@ -1624,8 +1637,8 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                                reinterpret_cast<const uint32_t *>(c->mask[0]), c->dpool0, c->part, B, H, H,
                                int(cout), int64_t(kSplitPix / 4));
             // part layout [split][co][10]: taps then bias
-            hipLaunchKernelGGL(k_sum_splits, dim3(nblk(cout * 10)), dim3(kBlk), 0, c->stream, c->part,
-                               c->part + sp * cout * 10, cout * 10, int(sp));
+            hipLaunchKernelGGL(k_sum_splits_wave, dim3(unsigned((cout * 10 + kBlk / 64 - 1) / (kBlk / 64))),
+                               dim3(kBlk), 0, c->stream, c->part, c->part + sp * cout * 10, cout * 10, int(sp));
             CHIP(c, hipGetLastError());
             hipLaunchKernelGGL(k_scatter_conv1, dim3(nblk(cout * 10)), dim3(kBlk), 0, c->stream,
                                c->part + sp * cout * 10, c->g + c->w_off[0], c->g + c->b_off[0], int(cout));
