@@ -356,13 +356,30 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y;
     const int n = tile / (tiles_x * tiles_y);
     const int y0 = ty * 8, x0 = tx * TW;
-    for (int idx = threadIdx.x; idx < PH * PW * (CIN / 8); idx += kBlk) {
-        const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
-        const int gy = y0 + pix / PW - 1, gx = x0 + pix % PW - 1;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-            v = *reinterpret_cast<const uint4 *>(in + ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8);
-        *reinterpret_cast<uint4 *>(patch + (pix / PW) * RS + (pix % PW) * PS + 8 * c8) = v;
+    // patch copy: every round's loads (unconditional, from the image's first
+    // pixel off the image, zeroed afterwards), then the stores, so no round
+    // waits for the previous one's load
+    {
+        constexpr int NCH = PH * PW * (CIN / 8), NR = (NCH + kBlk - 1) / kBlk;
+        uint4 v[NR];
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            const int idx = min(int(threadIdx.x) + it * kBlk, NCH - 1);
+            const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
+            const int gy = y0 + pix / PW - 1, gx = x0 + pix % PW - 1;
+            const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const uint4 t = *reinterpret_cast<const uint4 *>(
+                in + (ok ? ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8 : int64_t(0)));
+            v[it] = ok ? t : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int it = 0; it < NR; ++it) {
+            const int idx = int(threadIdx.x) + it * kBlk;
+            if (idx < NCH) {
+                const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
+                *reinterpret_cast<uint4 *>(patch + (pix / PW) * RS + (pix % PW) * PS + 8 * c8) = v[it];
+            }
+        }
     }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
