@@ -687,8 +687,9 @@ __device__ __attribute__((always_inline)) inline void spring_force_add_f64(const
 // ------------------------------------------------------------ step kernel
 // One time step of one site: all incident springs in direction order
 // (break test, Eq. 1-2 force), then the integrator.  Everything is read and
-// written through P, so a caller may point the state arrays at LDS.
-template <int DIM, int PREC, int MODE>
+// written through P, so a caller may point the state arrays at LDS.  LAW:
+// the spring law (LSM_SPRING_*), or -1 to take it from P at run time.
+template <int DIM, int PREC, int MODE, int LAW = -1>
 __device__ __attribute__((always_inline)) inline void step_site(
     const StepParams &P, const typename TT<PREC>::type *tt, const double *mass_s,
     const typename State<DIM, PREC>::R *imass_s, int g, int i, int j, int k, uint8_t fp, double *red,
@@ -698,6 +699,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
     using G = Geo<DIM>;
     using Mask = typename G::Mask;
     using TTy = typename TT<PREC>::type;
+    const int law = LAW < 0 ? int(P.law) : LAW;
     R uph[DIM], upl[DIM];
     S::load_u(P.u_in, g, P.nsites, uph, upl);
     const Mask mask = reinterpret_cast<const Mask *>(P.mask)[g];
@@ -739,7 +741,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
         if (fwd) ++rank;
         // a broken spring acts only under the recoverable law, in compression
         const bool was_broken = mask & (Mask(1) << d);
-        if (was_broken && P.law != LSM_SPRING_RECOVER) continue;
+        if (was_broken && law != LSM_SPRING_RECOVER) continue;
         const R *uqh = uqhs[t];
         const R *uql = uqls[t];
         const int pb = flag_phase(fq);
@@ -775,7 +777,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
             }
             continue;
         }
-        spring_force_add<DIM, PREC>(T, o, F, P.law == LSM_SPRING_CUBIC ? P.law_c : 0.0);
+        spring_force_add<DIM, PREC>(T, o, F, law == LSM_SPRING_CUBIC ? P.law_c : 0.0);
         if constexpr (MODE == kEnd) {
             if (fwd) {
                 // virial (Eq. 7) and potential energy (Eq. 1) in FP64
@@ -793,7 +795,7 @@ __device__ __attribute__((always_inline)) inline void step_site(
                 double coef64 = T64.k64 * (r64 - T64.r0_64) / r64;
                 const double dl = r64 - T64.r0_64;
                 double pe = 0.5 * T64.k64 * dl * dl;
-                if (P.law == LSM_SPRING_CUBIC) {
+                if (law == LSM_SPRING_CUBIC) {
                     const double dr = dl / T64.r0_64;
                     coef64 *= 1.0 + P.law_c * dr * dr;
                     pe += 0.25 * T64.k64 * P.law_c * dl * dl * dr * dr;
@@ -1587,7 +1589,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_small_mid(StepParams P, int nst
             const uint8_t fp = fl[g];
             if (fp == kVoid) continue;
             double red[1] = {0.0};
-            step_site<2, PREC, kMid>(L, tt, mass_s, imass_s, g, g % P.nx, g / P.nx, 0, fp, red, step_local + s);
+            step_site<2, PREC, kMid, LSM_SPRING_LINEAR>(L, tt, mass_s, imass_s, g, g % P.nx, g / P.nx, 0, fp, red,
+                                                        step_local + s);
         }
         __syncthreads();
     }
