@@ -942,6 +942,83 @@ __global__ __launch_bounds__(kBlk) void k_conv1_bwd(const uint8_t *x, const uint
         }
 }
 
+// The same backward walking down pooled rows (images whose pooled width is
+// a multiple of 64 and pooled height a multiple of kC1Rows): lane l of a
+// split owns pooled column 64 chunk + l of kC1Rows consecutive pooled rows
+// of one image; the 4 x 4 image patch of the next row shares two rows with
+// the current one, so each step loads two new patch rows (eight bytes) and
+// no pixel index is divided.  Same arithmetic per pooled pixel; splits are
+// (row block, column chunk), kSplitPix / 4 pooled pixels each.
+constexpr int kC1Rows = 32;
+
+__global__ __launch_bounds__(kBlk) void k_conv1_bwd_rows(const uint8_t *x, const uint32_t *mask, const u16 *dpool,
+                                                        float *partial, int B, int H, int W, int C) {
+    const int lane = threadIdx.x & 63;
+    const int grp = (blockIdx.y * (kBlk / 64)) + (threadIdx.x >> 6);
+    if (grp * kC1Cpw >= C) return;  // whole wavefronts leave together
+    const int Ho = H / 2, Wo = W / 2, nch = Wo / 64;
+    const int chunk = int(blockIdx.x) % nch, rb = int(blockIdx.x) / nch;
+    const int n = rb * kC1Rows / Ho, yo0 = rb * kC1Rows % Ho;
+    const int xo = 64 * chunk + lane;
+    const int mw = grp * kC1Cpw / 8, msh = (grp * kC1Cpw) % 8 * 4;
+    const uint8_t *img = x + int64_t(n) * H * W;
+    // patch column c: image column 2 xo - 1 + c (clamped; off the image its values are zeroed)
+    int cx[4];
+    float con[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int sx = 2 * xo - 1 + c;
+        cx[c] = min(max(sx, 0), W - 1);
+        con[c] = sx >= 0 && sx < W ? 1.0f : 0.0f;
+    }
+    auto load_row = [&](int sy, float *row) {
+        const int cy = min(max(sy, 0), H - 1);
+        const float on = sy >= 0 && sy < H ? 1.0f : 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) row[c] = float(img[int64_t(cy) * W + cx[c]]) * (on * con[c]);
+    };
+    float acc[kC1Cpw][10];
+#pragma unroll
+    for (int e = 0; e < kC1Cpw; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) acc[e][k] = 0.0f;
+    float v[4][4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) load_row(2 * yo0 - 1 + r, v[r]);
+    for (int yo = yo0; yo < yo0 + kC1Rows; ++yo) {
+        load_row(2 * yo + 1, v[2]);
+        load_row(2 * yo + 2, v[3]);
+        const int64_t q = (int64_t(n) * Ho + yo) * Wo + xo;
+        const uint2 gv = *reinterpret_cast<const uint2 *>(dpool + q * C + grp * kC1Cpw);
+        const u16 *gh = reinterpret_cast<const u16 *>(&gv);
+        const uint32_t mb = mask[q * (C / 8) + mw] >> msh;
+#pragma unroll
+        for (int e = 0; e < kC1Cpw; ++e) {
+            const float g = bf2f(f2bf(0.25f * bf2f(gh[e])));
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int dy = d >> 1, dx = d & 1;
+                const float da = (mb >> (4 * e + d)) & 1u ? g : 0.0f;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) acc[e][t] = fmaf(da, v[dy + t / 3][dx + t % 3], acc[e][t]);
+                acc[e][9] += da;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v[0][c] = v[2][c];
+            v[1][c] = v[3][c];
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < kC1Cpw; ++e)
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const float t = wave_sum_f(acc[e][k]);
+            if (lane == 0) partial[(int64_t(blockIdx.x) * C + grp * kC1Cpw + e) * 10 + k] = t;
+        }
+}
+
 // ------------------------------------------------------ pooling and GAP
 __global__ __launch_bounds__(kBlk) void k_gap_fwd(const u16 *in, float *out, int B, int HW, int C) {
     const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
@@ -1650,9 +1727,15 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             CHIP(c, hipGetLastError());
         } else {
             const unsigned groups = unsigned((cout / kC1Cpw + kBlk / 64 - 1) / (kBlk / 64));
-            hipLaunchKernelGGL(k_conv1_bwd, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
-                               reinterpret_cast<const uint32_t *>(c->mask[0]), c->dpool0, c->part, B, H, H,
-                               int(cout), int64_t(kSplitPix / 4));
+            if ((H / 2) % 64 == 0 && (H / 2) % kC1Rows == 0 && kC1Rows * 64 == kSplitPix / 4)
+                // (row blocks x column chunks = the sp splits of kSplitPix / 4 pooled pixels)
+                hipLaunchKernelGGL(k_conv1_bwd_rows, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
+                                   reinterpret_cast<const uint32_t *>(c->mask[0]), c->dpool0, c->part, B, H, H,
+                                   int(cout));
+            else
+                hipLaunchKernelGGL(k_conv1_bwd, dim3(unsigned(sp), groups), dim3(kBlk), 0, c->stream, c->x_last,
+                                   reinterpret_cast<const uint32_t *>(c->mask[0]), c->dpool0, c->part, B, H, H,
+                                   int(cout), int64_t(kSplitPix / 4));
             // part layout [split][co][10]: taps then bias
             hipLaunchKernelGGL(k_sum_splits_wave, dim3(unsigned((cout * 10 + kBlk / 64 - 1) / (kBlk / 64))),
                                dim3(kBlk), 0, c->stream, c->part, c->part + sp * cout * 10, cout * 10, int(sp));
