@@ -856,23 +856,22 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(3))) void 
     }
 }
 
-// Fixed-order sum of split partials: four interleaved running sums (splits
-// k = 0, 1, 2, 3 mod 4) so the loads overlap, combined as (s0 + s1) + (s2 + s3).
+// Fixed-order sum of split partials: wavefront w of a workgroup sums the
+// splits k = w (mod 4) of 64 consecutive outputs in split order, and the
+// four are combined as (s0 + s1) + (s2 + s3) -- a quarter of the dependent
+// loads per lane of one running sum per output.
 __global__ __launch_bounds__(kBlk) void k_sum_splits(const float *partial, float *out, int64_t n, int splits) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (i >= n) return;
-    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-    int k = 0;
-    // unrolled: sixteen loads in flight, each chain still summed in split order
-#pragma unroll 4
-    for (; k + 4 <= splits; k += 4) {
-        s0 += partial[int64_t(k) * n + i];
-        s1 += partial[int64_t(k + 1) * n + i];
-        s2 += partial[int64_t(k + 2) * n + i];
-        s3 += partial[int64_t(k + 3) * n + i];
-    }
-    for (; k < splits; ++k) s0 += partial[int64_t(k) * n + i];
-    out[i] = (s0 + s1) + (s2 + s3);
+    __shared__ float red[kBlk / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+    const bool ok = i < n;
+    const int64_t ii = ok ? i : 0;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int k = w; k < splits; k += 4) s += partial[int64_t(k) * n + ii];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && ok) out[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // Weight gradient of the one-channel first layer: partials [split][co][10]
@@ -1158,27 +1157,35 @@ __global__ __launch_bounds__(kBlk) void k_fc_bwd_data(const float *dy, const flo
     dx[t] = s;
 }
 
-// dw[o, i] = sum_n dy[n, o] x[n, i]; db[o] = sum_n dy[n, o] (column In)
+// dw[o, i] = sum_n dy[n, o] x[n, i]; db[o] = sum_n dy[n, o] (column In).
+// Wavefront w of a workgroup sums the samples n = w (mod 4) of 64
+// consecutive outputs in sample order (the bias column multiplies by one);
+// the four are combined as (s0 + s1) + (s2 + s3).
 __global__ __launch_bounds__(kBlk) void k_fc_bwd_weight(const float *dy, const float *x, float *dw, float *db, int B,
                                                        int In, int Out) {
-    const int64_t t = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (t >= int64_t(Out) * (In + 1)) return;
-    const int i = int(t % (In + 1));
-    const int o = int(t / (In + 1));
+    __shared__ float red[kBlk / 64][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t t = int64_t(blockIdx.x) * 64 + lane;
+    const bool ok = t < int64_t(Out) * (In + 1);
+    const int64_t tt = ok ? t : 0;
+    const int i = int(tt % (In + 1));
+    const int o = int(tt / (In + 1));
     float s = 0.0f;
-    // unrolled so the loads of sixteen samples are in flight together (the
-    // sum keeps its order); the bias column multiplies by one
     if (i < In) {
-#pragma unroll 16
-        for (int n = 0; n < B; ++n) s = fmaf(dy[int64_t(n) * Out + o], x[int64_t(n) * In + i], s);
+#pragma unroll 8
+        for (int n = w; n < B; n += 4) s = fmaf(dy[int64_t(n) * Out + o], x[int64_t(n) * In + i], s);
     } else {
-#pragma unroll 16
-        for (int n = 0; n < B; ++n) s = fmaf(dy[int64_t(n) * Out + o], 1.0f, s);
+#pragma unroll 8
+        for (int n = w; n < B; n += 4) s = fmaf(dy[int64_t(n) * Out + o], 1.0f, s);
     }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w != 0 || !ok) return;
+    const float v = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
     if (i < In)
-        dw[int64_t(o) * In + i] = s;
+        dw[int64_t(o) * In + i] = v;
     else
-        db[o] = s;
+        db[o] = v;
 }
 
 // mean squared error: loss partials and dy = 2 (y - t) / (B * Out)
@@ -1224,15 +1231,31 @@ __global__ __launch_bounds__(kBlk) void k_adam(float *p, const float *g, float *
 
 // BF16 copies of a conv weight [Cout, 9, Cin]: forward layout and the
 // flipped, transposed layout of the input-gradient product [Cin, 9, Cout].
-__global__ __launch_bounds__(kBlk) void k_conv_weights_bf16(const float *w, u16 *wf, u16 *wd, int Cin, int Cout) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    if (i >= int64_t(Cout) * 9 * Cin) return;
+// BF16 copies of the conv weights of layers 1..kLayers - 1 in one launch:
+// wf in the [Cout][9][Cin] layout, wd flipped and transposed for the input
+// gradient ([Cin][9][Cout], tap 8 - t).  Element i belongs to the layer
+// whose range [start[l], start[l + 1]) holds it.
+struct ConvWeights {
+    const float *w[kLayers];
+    u16 *wf[kLayers], *wd[kLayers];
+    int cin[kLayers], cout[kLayers];
+    int64_t start[kLayers + 1];
+};
+
+__global__ __launch_bounds__(kBlk) void k_conv_weights_bf16(ConvWeights cw) {
+    const int64_t g = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    if (g >= cw.start[kLayers - 1]) return;
+    int l = 0;
+#pragma unroll
+    for (int m = 1; m < kLayers - 1; ++m) l = g >= cw.start[m] ? m : l;
+    const int64_t i = g - cw.start[l];
+    const int Cin = cw.cin[l], Cout = cw.cout[l];
     const int ci = int(i % Cin);
     const int tap = int((i / Cin) % 9);
     const int co = int(i / (int64_t(9) * Cin));
-    const u16 h = f2bf(w[i]);
-    wf[i] = h;
-    if (wd) wd[(int64_t(ci) * 9 + (8 - tap)) * Cout + co] = h;
+    const u16 h = f2bf(cw.w[l][i]);
+    cw.wf[l][i] = h;
+    cw.wd[l][(int64_t(ci) * 9 + (8 - tap)) * Cout + co] = h;
 }
 
 // Fixed-order sum of split partials for few outputs over many splits: one
@@ -1526,11 +1549,19 @@ int lsm_cnn_bind(lsm_cnn *c, void *dptr, size_t bytes, void *hip_stream) {
 }
 
 static int refresh_bf16(lsm_cnn *c) {
-    for (int l = 1; l < kLayers; ++l) {
-        hipLaunchKernelGGL(k_conv_weights_bf16, dim3(nblk(c->w_n[l])), dim3(kBlk), 0, c->stream,
-                           c->p + c->w_off[l], c->wf[l], c->wd[l], c->C[l], c->C[l + 1]);
-        CHIP(c, hipGetLastError());
+    ConvWeights cw{};
+    cw.start[0] = 0;
+    for (int l = 1; l < kLayers; ++l) {  // entry l - 1: conv layer l
+        cw.w[l - 1] = c->p + c->w_off[l];
+        cw.wf[l - 1] = c->wf[l];
+        cw.wd[l - 1] = c->wd[l];
+        cw.cin[l - 1] = c->C[l];
+        cw.cout[l - 1] = c->C[l + 1];
+        cw.start[l] = cw.start[l - 1] + c->w_n[l];
     }
+    cw.start[kLayers] = cw.start[kLayers - 1];
+    hipLaunchKernelGGL(k_conv_weights_bf16, dim3(nblk(cw.start[kLayers - 1])), dim3(kBlk), 0, c->stream, cw);
+    CHIP(c, hipGetLastError());
     return LSM_OK;
 }
 
@@ -1645,11 +1676,11 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
     const int hid = c->cfg.hidden, out = c->cfg.outputs, CL = c->C[kLayers];
     if (dy && dy != c->dy) CHIP(c, hipMemcpyAsync(c->dy, dy, size_t(B) * out * 4, hipMemcpyDeviceToDevice, c->stream));
     // dense layers
-    hipLaunchKernelGGL(k_fc_bwd_weight, dim3(nblk(int64_t(out) * (hid + 1))), dim3(kBlk), 0, c->stream, c->dy, c->h1,
+    hipLaunchKernelGGL(k_fc_bwd_weight, dim3(unsigned((int64_t(out) * (hid + 1) + 63) / 64)), dim3(kBlk), 0, c->stream, c->dy, c->h1,
                        c->g + c->w_off[kLayers + 1], c->g + c->b_off[kLayers + 1], B, hid, out);
     hipLaunchKernelGGL(k_fc_bwd_data, dim3(nblk(int64_t(B) * hid)), dim3(kBlk), 0, c->stream, c->dy,
                        c->p + c->w_off[kLayers + 1], c->h1, c->dh1, B, hid, out);
-    hipLaunchKernelGGL(k_fc_bwd_weight, dim3(nblk(int64_t(hid) * (CL + 1))), dim3(kBlk), 0, c->stream, c->dh1, c->gap,
+    hipLaunchKernelGGL(k_fc_bwd_weight, dim3(unsigned((int64_t(hid) * (CL + 1) + 63) / 64)), dim3(kBlk), 0, c->stream, c->dh1, c->gap,
                        c->g + c->w_off[kLayers], c->g + c->b_off[kLayers], B, CL, hid);
     hipLaunchKernelGGL(k_fc_bwd_data, dim3(nblk(int64_t(B) * CL)), dim3(kBlk), 0, c->stream, c->dh1,
                        c->p + c->w_off[kLayers], nullptr, c->dgap, B, CL, hid);
@@ -1683,7 +1714,7 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                                    c->part, bias_part, B, H, H, int(cin), int(cout), int(pps));
             }
             CHIP(c, hipGetLastError());
-            hipLaunchKernelGGL(k_sum_splits, dim3(nblk(nw)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
+            hipLaunchKernelGGL(k_sum_splits, dim3(unsigned((nw + 63) / 64)), dim3(kBlk), 0, c->stream, c->part, c->g + c->w_off[l], nw,
                                int(sw));
             hipLaunchKernelGGL(k_sum_splits_wave, dim3(unsigned((cout + kBlk / 64 - 1) / (kBlk / 64))), dim3(kBlk), 0,
                                c->stream, bias_part, c->g + c->b_off[l], cout, int(sw));
