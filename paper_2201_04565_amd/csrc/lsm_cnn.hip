@@ -46,6 +46,20 @@ __device__ inline u16 f2bf(float x) {
 }
 __device__ inline float bf2f(u16 h) { return __uint_as_float(unsigned(h) << 16); }
 
+// Full-resolution gradient below a pooled layer from its pooled gradient
+// g (BF16, eight channels) and the ReLU mask bytes of those channels: at
+// sub-pixel d of a 2 x 2 quad, bf16(g / 4) where bit d is set, else 0 --
+// the values the expanding epilogue stores.
+__device__ inline uint4 expand8(uint4 g8, uint2 m8, int d) {
+    const u16 *g = reinterpret_cast<const u16 *>(&g8);
+    const uint8_t *m = reinterpret_cast<const uint8_t *>(&m8);
+    u16 o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) o[e] = (m[e] >> d) & 1u ? f2bf(0.25f * bf2f(g[e])) : u16(0);
+    return *reinterpret_cast<const uint4 *>(o);
+}
+
+
 union Frag {
     uint4 u;
     bf16x8 v;
@@ -330,10 +344,13 @@ __global__ __launch_bounds__(kBlk) void k_conv_mfma(const u16 *in, const u16 *wt
 // and 32-pixel ones over all BN channels 30-45 % slower.  The reduction runs in the same K steps and order as
 // k_conv_mfma, so both kernels produce the same bits; weights come from
 // global memory (L1/L2 resident), one step ahead.
-template <int CIN, int TW, int BN, int EPI, int MT>
+// XIN: the input is the pooled gradient of the layer ([B][H/2][W/2][CIN])
+// with the ReLU masks xmask of the layer below, expanded to H x W while the
+// patch is staged (the full-resolution gradient is never stored).
+template <int CIN, int TW, int BN, int EPI, int MT, bool XIN = false>
 __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *in, const u16 *wt, const float *bias,
                                                                     u16 *out, uint8_t *mask_out, int B, int H, int W,
-                                                                    int Cout) {
+                                                                    int Cout, const uint8_t *xmask = nullptr) {
     constexpr int PH = 10, PW = TW + 2;
     // u16 per staged pixel and per staged row: pixel strides of 4 (mod 32)
     // LDS banks and row strides of 16 put the eight pixels that one
@@ -362,22 +379,35 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
     {
         constexpr int NCH = PH * PW * (CIN / 8), NR = (NCH + kBlk - 1) / kBlk;
         uint4 v[NR];
+        uint2 vm[XIN ? NR : 1];
 #pragma unroll
         for (int it = 0; it < NR; ++it) {
             const int idx = min(int(threadIdx.x) + it * kBlk, NCH - 1);
             const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
             const int gy = y0 + pix / PW - 1, gx = x0 + pix % PW - 1;
             const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
-            const uint4 t = *reinterpret_cast<const uint4 *>(
-                in + (ok ? ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8 : int64_t(0)));
-            v[it] = ok ? t : make_uint4(0, 0, 0, 0);
+            if constexpr (XIN) {
+                const int64_t e = ok ? ((int64_t(n) * (H / 2) + (gy >> 1)) * (W / 2) + (gx >> 1)) * CIN + 8 * c8 : 0;
+                v[it] = *reinterpret_cast<const uint4 *>(in + e);
+                vm[it] = *reinterpret_cast<const uint2 *>(xmask + e);
+            } else {
+                const uint4 t = *reinterpret_cast<const uint4 *>(
+                    in + (ok ? ((int64_t(n) * H + gy) * W + gx) * CIN + 8 * c8 : int64_t(0)));
+                v[it] = ok ? t : make_uint4(0, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int it = 0; it < NR; ++it) {
             const int idx = int(threadIdx.x) + it * kBlk;
             if (idx < NCH) {
                 const int pix = idx / (CIN / 8), c8 = idx - pix * (CIN / 8);
-                *reinterpret_cast<uint4 *>(patch + (pix / PW) * RS + (pix % PW) * PS + 8 * c8) = v[it];
+                uint4 t = v[it];
+                if constexpr (XIN) {
+                    const int gy = y0 + pix / PW - 1, gx = x0 + pix % PW - 1;
+                    const bool ok = gy >= 0 && gy < H && gx >= 0 && gx < W;
+                    t = ok ? expand8(t, vm[it], ((gy & 1) << 1) | (gx & 1)) : make_uint4(0, 0, 0, 0);
+                }
+                *reinterpret_cast<uint4 *>(patch + (pix / PW) * RS + (pix % PW) * PS + 8 * c8) = t;
             }
         }
     }
@@ -506,10 +536,11 @@ __device__ __attribute__((always_inline)) inline void conv_lds_body(const u16 *i
 // 49 KB patch leaves room for three workgroups per CU); with 128 input
 // channels the patch is 49 KB too, and that variant keeps its registers
 // (measured faster than squeezed).
-template <int CIN, int TW, int BN, int EPI, int MT = 4>
+template <int CIN, int TW, int BN, int EPI, int MT = 4, bool XIN = false>
 __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(TW == 32 ? 3 : 4))) void k_conv_lds(
-    const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask_out, int B, int H, int W, int Cout) {
-    conv_lds_body<CIN, TW, BN, EPI, MT>(in, wt, bias, out, mask_out, B, H, W, Cout);
+    const u16 *in, const u16 *wt, const float *bias, u16 *out, uint8_t *mask_out, int B, int H, int W, int Cout,
+    const uint8_t *xmask = nullptr) {
+    conv_lds_body<CIN, TW, BN, EPI, MT, XIN>(in, wt, bias, out, mask_out, B, H, W, Cout, xmask);
 }
 
 template <int TW, int BN, int EPI, int MT = 4>
@@ -732,9 +763,12 @@ __global__ __launch_bounds__(kBlk) void k_conv_wgrad_wide(const u16 *in, const u
 constexpr int kWhS = 48;     // u16 per staged halo pixel: 32 channels + pad (conflict-free transposed reads)
 constexpr int kWhPix = 100;  // 10 x 10 staged pixels
 
-__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(3))) void k_conv_wgrad_halo(const u16 *in, const u16 *dout, float *partial,
-                                                         float *bias_partial, int B, int H, int W, int Cin,
-                                                         int Cout, int tiles_per_split) {
+// XD: dout is the pooled gradient [B][H/2][W/2][Cout] with the ReLU masks
+// dmask of the layer (expanded while staging) instead of the full-resolution one.
+template <bool XD>
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(XD ? 2 : 3))) void k_conv_wgrad_halo(
+    const u16 *in, const u16 *dout, const uint8_t *dmask, float *partial, float *bias_partial, int B, int H, int W,
+    int Cin, int Cout, int tiles_per_split) {
     __shared__ __align__(16) u16 sd[64 * kWwDS];     // [tile pixel][co]
     __shared__ __align__(16) u16 sx[kWhPix * kWhS];  // [halo pixel][ci]
     __shared__ float bred[kBlk / 64][64];
@@ -762,14 +796,21 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(3))) void 
     // co_t + 8 (q mod 8); halo chunk h = tid + 256 i (h < 400) is halo pixel
     // h / 4, channels ci_t + 8 (h mod 4)
     uint4 rd[2], rx[2];
+    uint2 rm[2];  // XD: the mask bytes of rd's channels
     auto gload = [&](int t) {
         const int txi = t % tx_n, rr = t / tx_n, tyi = rr % ty_n, n = rr / ty_n;
         const int y0 = 8 * tyi, x0 = 8 * txi;
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int q = tid + kBlk * i, pix = q >> 3;
-            const int64_t p = (int64_t(n) * H + y0 + (pix >> 3)) * W + x0 + (pix & 7);
-            rd[i] = *reinterpret_cast<const uint4 *>(dout + p * Cout + co_t + 8 * (q & 7));
+            if constexpr (XD) {
+                const int64_t pp = (int64_t(n) * (H / 2) + ((y0 + (pix >> 3)) >> 1)) * (W / 2) + ((x0 + (pix & 7)) >> 1);
+                rd[i] = *reinterpret_cast<const uint4 *>(dout + pp * Cout + co_t + 8 * (q & 7));
+                rm[i] = *reinterpret_cast<const uint2 *>(dmask + pp * Cout + co_t + 8 * (q & 7));
+            } else {
+                const int64_t p = (int64_t(n) * H + y0 + (pix >> 3)) * W + x0 + (pix & 7);
+                rd[i] = *reinterpret_cast<const uint4 *>(dout + p * Cout + co_t + 8 * (q & 7));
+            }
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -787,6 +828,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(3))) void 
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int q = tid + kBlk * i;
+            // (tile origins are even: the sub-pixel is the tile pixel's parity)
+            if constexpr (XD) rd[i] = expand8(rd[i], rm[i], (((q >> 6) & 1) << 1) | ((q >> 3) & 1));
             *reinterpret_cast<uint4 *>(sd + (q >> 3) * kWwDS + 8 * (q & 7)) = rd[i];
             if (do_bias) {
                 const u16 *e8 = reinterpret_cast<const u16 *>(&rd[i]);
@@ -1258,6 +1301,23 @@ __global__ __launch_bounds__(kBlk) void k_conv_weights_bf16(ConvWeights cw) {
     cw.wd[l][(int64_t(ci) * 9 + (8 - tap)) * Cout + co] = h;
 }
 
+// The full-resolution gradient from a pooled gradient and the masks (the
+// test hook's view of a gradient that is not stored): one thread per
+// full-resolution pixel and eight channels.
+__global__ __launch_bounds__(kBlk) void k_expand_grad(const u16 *gp, const uint8_t *mask, u16 *out, int B, int H,
+                                                     int W, int C) {
+    const int64_t t = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    if (t >= int64_t(B) * H * W * (C / 8)) return;
+    const int c8 = int(t % (C / 8));
+    const int64_t p = t / (C / 8);
+    const int x = int(p % W), y = int((p / W) % H);
+    const int64_t n = p / (int64_t(H) * W);
+    const int64_t e = ((n * (H / 2) + (y >> 1)) * (W / 2) + (x >> 1)) * C + 8 * c8;
+    *reinterpret_cast<uint4 *>(out + p * C + 8 * c8) =
+        expand8(*reinterpret_cast<const uint4 *>(gp + e), *reinterpret_cast<const uint2 *>(mask + e),
+                ((y & 1) << 1) | (x & 1));
+}
+
 // Fixed-order sum of split partials for few outputs over many splits: one
 // wavefront per output, lane l summing splits l, l + 64, ... in order, then
 // a fixed butterfly over the lanes.
@@ -1305,6 +1365,11 @@ struct lsm_cnn {
     // layers; mask: their ReLU masks (4 bits per pooled pixel and channel);
     // dact: conv output gradients; dpool: gradient of the first pooled map
     u16 *act = nullptr, *pool[kLayers]{}, *dact[kLayers]{}, *dpool0 = nullptr;
+    // pooled gradient of layer 2's input (the full-resolution dact[1] is
+    // then not stored: its consumers expand it with mask[1]); gp_used: the
+    // last backward pass took that path
+    u16 *gp = nullptr;
+    bool gp_used = false;
     uint8_t *mask[kLayers]{};
     float *gap = nullptr, *h1 = nullptr, *y = nullptr;
     float *dgap = nullptr, *dh1 = nullptr, *dy = nullptr;
@@ -1393,6 +1458,7 @@ size_t cnn_layout(const lsm_cnn *c, std::vector<size_t> *sizes) {
     const int L = kLayers - 1;
     s.push_back(size_t(B * c->Hs[L] * c->Hs[L] * c->C[L + 1]) * 2);  // act
     s.push_back(size_t(B * c->Hs[0] * c->Hs[0] / 4 * c->C[1]) * 2);  // dpool0
+    s.push_back(size_t(B * c->Hs[2] * c->Hs[2] * c->C[2]) * 2);      // gp
     for (int l = 0; l < kLayers; ++l) {
         const int64_t hw = int64_t(c->Hs[l]) * c->Hs[l];
         s.push_back(l > 0 ? size_t(B * hw * c->C[l + 1]) * 2 : 0);       // dact
@@ -1527,6 +1593,7 @@ int lsm_cnn_bind(lsm_cnn *c, void *dptr, size_t bytes, void *hip_stream) {
     for (int l = 1; l < kLayers; ++l) c->wd[l] = reinterpret_cast<u16 *>(take());
     c->act = reinterpret_cast<u16 *>(take());
     c->dpool0 = reinterpret_cast<u16 *>(take());
+    c->gp = reinterpret_cast<u16 *>(take());
     for (int l = 0; l < kLayers; ++l) {
         c->dact[l] = reinterpret_cast<u16 *>(take());
         c->pool[l] = reinterpret_cast<u16 *>(take());
@@ -1689,6 +1756,13 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
     hipLaunchKernelGGL(k_gap_bwd_relu, dim3(nblk(int64_t(B) * HL * HL * CL)), dim3(kBlk), 0, c->stream, c->dgap,
                        c->act, c->dact[kLayers - 1], B, HL * HL, CL);
     CHIP(c, hipGetLastError());
+    // The input gradient of layer 2 stays at its pooled resolution (gp) when
+    // the kernels that consume the full-resolution one -- layer 1's halo
+    // weight gradient and its 8 x 32-tile input gradient -- can expand it
+    // with mask[1] themselves (the conditions of their launches below).
+    const bool xin = c->C[3] == 128 && c->C[2] == 64 && c->Hs[2] % 16 == 0 &&
+                     wgrad_halo_ok(c->Hs[1], c->C[1], c->C[2]) && c->C[1] % 32 == 0 && c->Hs[1] % 32 == 0;
+    c->gp_used = xin;
     for (int l = kLayers - 1; l >= 0; --l) {
         const int H = c->Hs[l];
         const int64_t npix = int64_t(B) * H * H;
@@ -1703,8 +1777,13 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                 sw = (nt + tps - 1) / tps;
                 bias_part = c->part + sw * nw;  // [split][co] after the weight partials
                 const dim3 grid(unsigned(cout / 64), unsigned(cin / 32), unsigned(sw));
-                hipLaunchKernelGGL(k_conv_wgrad_halo, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->dact[l],
-                                   c->part, bias_part, B, H, H, int(cin), int(cout), int(tps));
+                if (l == 1 && xin)
+                    hipLaunchKernelGGL(k_conv_wgrad_halo<true>, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1], c->gp,
+                                       c->mask[1], c->part, bias_part, B, H, H, int(cin), int(cout), int(tps));
+                else
+                    hipLaunchKernelGGL(k_conv_wgrad_halo<false>, grid, dim3(kBlk), 0, c->stream, c->pool[l - 1],
+                                       c->dact[l], nullptr, c->part, bias_part, B, H, H, int(cin), int(cout),
+                                       int(tps));
             } else {
                 const int64_t pps = wgrad_pix_per_split(npix, cout, cin);
                 sw = (npix + pps - 1) / pps;
@@ -1724,7 +1803,11 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
             // first layer's backward takes the pooled gradient itself)
             const dim3 g2 = conv_grid(npix, int(cin));
             const dim3 g16(unsigned(B * (H / 8) * (H / 16)), 1);
-            if (l > 1 && cout == 128 && cin == 64 && H % 16 == 0)
+            if (l == 2 && xin)
+                // the pooled gradient of layer 2's input, kept at its own resolution
+                hipLaunchKernelGGL((k_conv_lds128<16, 64, kEpiRaw, 8>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
+                                   c->wd[l], nullptr, c->gp, nullptr, B, H, H, int(cin));
+            else if (l > 1 && cout == 128 && cin == 64 && H % 16 == 0)
                 // staged-patch kernel (same K order, same bits); the mask
                 // slot carries the masks of the layer below, read
                 hipLaunchKernelGGL((k_conv_lds128<16, 64, kEpiExpand, 8>), g16, dim3(kBlk), 0, c->stream, c->dact[l],
@@ -1740,6 +1823,11 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                 hipLaunchKernelGGL((k_conv_mfma<kEpiExpand, kConvWM, kConvWN>), g2, dim3(kBlk), 0, c->stream,
                                    c->dact[l], c->wd[l], nullptr, c->dact[l - 1], c->mask[l - 1], nullptr, B, H, H,
                                    int(cout), int(cin));
+            else if (xin)
+                // (l == 1) the same kernel expanding the pooled gradient while staging
+                hipLaunchKernelGGL((k_conv_lds<64, 32, 32, kEpiRaw, 8, true>), dim3(unsigned(B * (H / 8) * (H / 32)),
+                                   unsigned(cin / 32)), dim3(kBlk), 0, c->stream, c->gp, c->wd[l], nullptr,
+                                   c->dpool0, nullptr, B, H, H, int(cin), c->mask[1]);
             else if (cout == 64 && cin % 32 == 0 && H % 32 == 0)
                 // the staged-patch kernel (same K order, same bits): 64-channel
                 // gradient input, 32-channel blocks of the output, 8 x 32 tiles
@@ -1821,6 +1909,12 @@ int lsm_cnn_read_buffer(lsm_cnn *c, int buffer, int layer, void *host, size_t *b
         break;
     case LSM_CNN_BUF_DACT:
         if (lok && layer > 0) src = c->dact[layer], n = size_t(B * hw * ch) * 2;
+        if (lok && layer == 1 && c->gp_used && host) {
+            // not stored by the backward pass: expand the pooled gradient
+            hipLaunchKernelGGL(k_expand_grad, dim3(nblk(int64_t(B) * hw * (ch / 8))), dim3(kBlk), 0, c->stream,
+                               c->gp, c->mask[1], c->dact[1], int(B), c->Hs[1], c->Hs[1], int(ch));
+            CHIP(c, hipGetLastError());
+        }
         break;
     case LSM_CNN_BUF_DPOOL0:
         src = c->dpool0, n = size_t(B * c->Hs[0] * c->Hs[0] / 4 * c->C[1]) * 2;
