@@ -176,11 +176,13 @@ def curve_strength(pred: np.ndarray) -> np.ndarray:
 
 
 def calibrate_gate(sur: Surrogate, images: np.ndarray, lab: Labels, target_p95: float = 0.05,
-                   max_gate: float = 0.05) -> dict:
+                   max_gate: float = 0.05, min_accept: int = 20) -> dict:
     """Spread gate from a held-out split: the largest threshold (at most
-    max_gate) whose accepted specimens -- spread at or below it -- have a
-    95th-percentile modulus error within target_p95 on that split.  A gate of
-    0 sends every specimen to the model."""
+    max_gate) whose accepted specimens -- spread at or below it, at least
+    min_accept of them -- have a 95th-percentile modulus error within
+    target_p95 on that split.  (The 95th percentile of fewer than 20 errors
+    is their largest or second largest: a gate set on so few would not hold
+    on another split.)  A gate of 0 sends every specimen to the model."""
     pred, spread, _ = sur.predict(images)
     err = np.abs(pred[:, -1] - lab.modulus) / np.abs(lab.modulus)
     order = np.argsort(spread, kind="stable")
@@ -189,7 +191,7 @@ def calibrate_gate(sur: Surrogate, images: np.ndarray, lab: Labels, target_p95: 
         g = float(spread[order[m - 1]])
         if g > max_gate:
             break
-        if np.quantile(err[order[:m]], 0.95) <= target_p95:
+        if m >= min_accept and np.quantile(err[order[:m]], 0.95) <= target_p95:
             best = g
     acc = spread <= best
     return dict(gate=best, val_n=len(images), val_accept_rate=float(acc.mean()),
