@@ -549,7 +549,7 @@ def main():
                     help="training specimens (the full C5 configuration: 50000)")
     ap.add_argument("--sur-val", type=int, default=1024, help="validation specimens (C5: 5000)")
     ap.add_argument("--sur-test", type=int, default=1024, help="test specimens (C5: 5000)")
-    ap.add_argument("--sur-epochs", type=int, default=10, help="epochs (C5: 20)")
+    ap.add_argument("--sur-epochs", type=int, default=20, help="epochs (as C5)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (counter scale reference)")
     args = ap.parse_args()
