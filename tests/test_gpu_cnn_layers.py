@@ -32,7 +32,12 @@ from oracle import cnn_oracle as co
 pytestmark = pytest.mark.gpu
 
 U = 2.0 ** -24
-B, SIZE = 4, 128
+B = 4
+# 128 x 128 images (the benchmark's) and 64 x 64 (the small surrogate
+# test's): the sizes select different kernels (8 x 16 / 8 x 32 tiles, the
+# row-walking or the strided first-layer backward, direct kernels for the
+# 4 x 4 last layer)
+SIZES = (128, 64)
 
 
 def say(msg):
@@ -92,12 +97,13 @@ def conv_bounds(x, w, b):
     return v, (K + 2) * U * s
 
 
-@pytest.fixture(scope="module")
-def run():
+@pytest.fixture(scope="module", params=SIZES, ids=lambda s: f"{s}px")
+def run(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2201_04565_amd import cnn
+    SIZE = request.param
     say(f"surrogate network {SIZE}x{SIZE}, batch {B}: one forward + loss + backward")
     net = cnn.Network(size=SIZE, batch=B)
     spec, n = co.layout(net.channels, net.hidden, net.outputs)
