@@ -1075,23 +1075,34 @@ __global__ __launch_bounds__(kBlk) void k_gap_fwd(const u16 *in, float *out, int
     out[i] = s / float(HW);
 }
 
+// Gradient of the last conv output: dg / HW where its ReLU output is
+// positive.  One thread per pixel and eight channels (C is a multiple of
+// 8): 16-byte loads and stores, one index division per eight values.
 __global__ __launch_bounds__(kBlk) void k_gap_bwd_relu(const float *dg, const u16 *act, u16 *dact, int B, int HW,
                                                       int C) {
-    const int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x;
-    const int64_t total = int64_t(B) * HW * C;
-    if (i >= total) return;
-    int c;
+    const int64_t t = int64_t(blockIdx.x) * kBlk + threadIdx.x;
+    const int64_t total8 = int64_t(B) * HW * (C / 8);
+    if (t >= total8) return;
+    const int64_t i = 8 * t;  // first of the eight elements
+    int c0;
     int64_t n;
-    if (total <= 0x7FFFFFFF) {  // 32-bit division where the index fits
+    if (i <= 0x7FFFFFFF) {  // 32-bit division where the index fits
         const uint32_t u = uint32_t(i);
-        c = int(u % uint32_t(C));
+        c0 = int(u % uint32_t(C));
         n = int64_t(u / uint32_t(HW * C));
     } else {
-        c = int(i % C);
+        c0 = int(i % C);
         n = i / (int64_t(HW) * C);
     }
-    const float g = dg[n * C + c] / float(HW);
-    dact[i] = f2bf(bf2f(act[i]) > 0.0f ? g : 0.0f);
+    const uint4 a = *reinterpret_cast<const uint4 *>(act + i);
+    const u16 *ah = reinterpret_cast<const u16 *>(&a);
+    u16 o[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float g = dg[n * C + c0 + e] / float(HW);
+        o[e] = f2bf(bf2f(ah[e]) > 0.0f ? g : 0.0f);
+    }
+    *reinterpret_cast<uint4 *>(dact + i) = *reinterpret_cast<const uint4 *>(o);
 }
 
 // ---------------------------------------------------------- dense layers
@@ -1753,7 +1764,7 @@ int lsm_cnn_backward(lsm_cnn *c, const float *dy) {
                        c->p + c->w_off[kLayers], nullptr, c->dgap, B, CL, hid);
     CHIP(c, hipGetLastError());
     const int HL = c->Hs[kLayers - 1];
-    hipLaunchKernelGGL(k_gap_bwd_relu, dim3(nblk(int64_t(B) * HL * HL * CL)), dim3(kBlk), 0, c->stream, c->dgap,
+    hipLaunchKernelGGL(k_gap_bwd_relu, dim3(nblk(int64_t(B) * HL * HL * (CL / 8))), dim3(kBlk), 0, c->stream, c->dgap,
                        c->act, c->dact[kLayers - 1], B, HL * HL, CL);
     CHIP(c, hipGetLastError());
     // The input gradient of layer 2 stays at its pooled resolution (gp) when
